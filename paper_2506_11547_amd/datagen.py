@@ -1,0 +1,199 @@
+"""Seeded synthetic correspondences for the rotation-voting workloads.
+
+This module only *draws* inputs: a ground-truth rotation, unit directions, noise
+and outliers.  It contains none of the voting method's arithmetic (no circle
+basis, no sampling, no chart, no binning, no scoring), so both the HIP library
+and the CPU oracle can be fed from it without sharing any of the method.
+
+Conventions
+-----------
+* Quaternions are (w, x, y, z), Hamilton product, unit norm, ``w >= 0``.
+* Correspondences are float32 SoA arrays of shape ``[3, N]`` (all x components,
+  then y, then z), the layout the C-ABI expects.
+* Everything is drawn in float64 from ``numpy.random.default_rng(seed)`` (PCG64)
+  in a fixed order and cast to float32 at the end.
+
+Workload shapes follow the synthetic experiments of the paper (Sec. 5.3.1:
+N = 1e5..1e6 correspondences, outlier ratios up to 99 %, random mismatches as
+outliers; Table 1's same-axis structured outliers) and the named configurations
+below.  No external dataset is used.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+__all__ = [
+    "Instance",
+    "Workload",
+    "WORKLOADS",
+    "make_instance",
+    "make_workload",
+    "quat_to_matrix",
+    "rotation_error_deg",
+]
+
+
+@dataclass
+class Instance:
+    x: np.ndarray          # float32 [3, N]
+    y: np.ndarray          # float32 [3, N]
+    q_gt: np.ndarray       # float64 [4], w >= 0
+    inlier: np.ndarray     # bool [N], ground-truth inlier flags
+    seed: int
+    params: dict = field(default_factory=dict)
+
+    @property
+    def n(self) -> int:
+        return int(self.x.shape[1])
+
+
+@dataclass(frozen=True)
+class Workload:
+    """One named synthetic solve: input recipe plus the solver settings."""
+    name: str
+    n: int
+    outlier_ratio: float
+    sigma_deg: float
+    grid: int
+    samples: int           # J, samples per circle
+    eps_deg: float         # inlier threshold of the rescoring step (degrees)
+    topk: int
+    seed: int
+    radii: tuple | None = None     # (lo, hi): scale x by U[lo, hi] radii
+    noise: str = "angular"         # "angular" (tangent Gaussian) or "additive"
+
+    def instance(self) -> Instance:
+        return make_instance(self.n, self.outlier_ratio, self.sigma_deg, self.seed,
+                             radii=self.radii, noise=self.noise)
+
+
+# Named single-solve workloads.  "large" is the headline measurement
+# (N = 1e6 at 99 % outliers); "small" is the oracle-sized case.
+WORKLOADS = {
+    "small": Workload("small", n=1000, outlier_ratio=0.90, sigma_deg=0.5, grid=64,
+                      samples=512, eps_deg=1.0, topk=16, seed=0),
+    "medium": Workload("medium", n=100_000, outlier_ratio=0.95, sigma_deg=0.5, grid=128,
+                       samples=1024, eps_deg=1.0, topk=16, seed=1, radii=(0.5, 2.0)),
+    "large": Workload("large", n=1_000_000, outlier_ratio=0.99, sigma_deg=1.0, grid=256,
+                      samples=2048, eps_deg=1.5, topk=64, seed=2),
+    # The paper's default resolution (accumulator step 1/180, i.e. a 360^3 grid,
+    # and 180 samples per circle; Sec. 5.1) with its additive noise model.
+    "paper_default": Workload("paper_default", n=1_000_000, outlier_ratio=0.99,
+                              sigma_deg=0.0, grid=360, samples=180, eps_deg=1.5,
+                              topk=16, seed=5, noise="additive"),
+}
+
+
+def make_workload(name: str) -> tuple[Workload, Instance]:
+    w = WORKLOADS[name]
+    return w, w.instance()
+
+
+def quat_to_matrix(q) -> np.ndarray:
+    """Rotation matrix of a unit quaternion (w, x, y, z) (float64)."""
+    w, x, y, z = (float(c) for c in q)
+    return np.array([
+        [w * w + x * x - y * y - z * z, 2 * (x * y - w * z), 2 * (x * z + w * y)],
+        [2 * (x * y + w * z), w * w - x * x + y * y - z * z, 2 * (y * z - w * x)],
+        [2 * (x * z - w * y), 2 * (y * z + w * x), w * w - x * x - y * y + z * z],
+    ])
+
+
+def rotation_error_deg(q_a, q_b) -> float:
+    """Geodesic angle between two rotations, in degrees (Sec. 5.2's e_R)."""
+    ra, rb = quat_to_matrix(q_a), quat_to_matrix(q_b)
+    c = (np.trace(ra.T @ rb) - 1.0) * 0.5
+    return math.degrees(math.acos(min(1.0, max(-1.0, c))))
+
+
+def _unit_rows(v: np.ndarray) -> np.ndarray:
+    return v / np.linalg.norm(v, axis=1, keepdims=True)
+
+
+def _random_unit_quat(rng) -> np.ndarray:
+    q = rng.normal(size=4)
+    q /= np.linalg.norm(q)
+    if q[0] < 0:
+        q = -q
+    return q
+
+
+def _rotate_about(v: np.ndarray, axis: np.ndarray, angle: np.ndarray) -> np.ndarray:
+    """Rodrigues rotation of rows of v about unit rows of axis by angle (rad)."""
+    c = np.cos(angle)[:, None]
+    s = np.sin(angle)[:, None]
+    kv = np.sum(axis * v, axis=1, keepdims=True)
+    return v * c + np.cross(axis, v) * s + axis * kv * (1.0 - c)
+
+
+def _angular_noise(rng, z: np.ndarray, sigma_rad: float) -> np.ndarray:
+    """Perturb unit rows z by a tangent-plane Gaussian rotation (std sigma per axis)."""
+    if sigma_rad == 0.0 or len(z) == 0:
+        return z.copy()
+    helper = np.where(np.abs(z[:, :1]) < 0.9, np.array([[1.0, 0.0, 0.0]]),
+                      np.array([[0.0, 1.0, 0.0]]))
+    t1 = _unit_rows(np.cross(z, helper))
+    t2 = np.cross(z, t1)
+    g = rng.normal(size=(len(z), 2)) * sigma_rad
+    omega = g[:, :1] * t1 + g[:, 1:] * t2            # rotation vector, tangent to z
+    ang = np.linalg.norm(omega, axis=1)
+    safe = np.where(ang > 0, ang, 1.0)
+    axis = omega / safe[:, None]
+    out = _rotate_about(z, axis, ang)
+    return np.where(ang[:, None] > 0, out, z)
+
+
+def make_instance(n: int, outlier_ratio: float, sigma_deg: float, seed: int, *,
+                  radii: tuple | None = None, noise: str = "angular",
+                  same_axis_ratio: float = 0.0, q_gt=None) -> Instance:
+    """Draw one synthetic rotation-estimation instance.
+
+    Draw order (fixed): q_gt; unit x; radii (if any); a permutation whose first
+    ``n_in = round((1 - outlier_ratio) * n)`` entries are inliers; inlier noise;
+    outlier directions; same-axis structured outliers (Table 1's eta).
+
+    noise="angular": y = Rot(omega) R x with omega a tangent-plane Gaussian of
+    std ``sigma_deg`` per axis.  noise="additive": the paper's Sec. 5.2 model,
+    y = normalise(R x + delta * N(0, I)) with delta = sigma_deg read as the raw
+    perturbation std (0.01 in Table 1); delta defaults to 0.01 when sigma_deg is 0.
+    """
+    if n < 0:
+        raise ValueError("n must be >= 0")
+    rng = np.random.default_rng(seed)
+    q = _random_unit_quat(rng) if q_gt is None else np.asarray(q_gt, np.float64)
+    R = quat_to_matrix(q)
+    xh = _unit_rows(rng.normal(size=(n, 3))) if n else np.zeros((0, 3))
+    if radii is not None:
+        r = rng.uniform(radii[0], radii[1], size=n)
+    else:
+        r = np.ones(n)
+    perm = rng.permutation(n)
+    n_in = int(round((1.0 - outlier_ratio) * n))
+    inlier = np.zeros(n, dtype=bool)
+    inlier[perm[:n_in]] = True
+    z = xh @ R.T
+    y = np.empty((n, 3))
+    idx_in = perm[:n_in]
+    if noise == "angular":
+        y[idx_in] = _angular_noise(rng, z[idx_in], math.radians(sigma_deg))
+    elif noise == "additive":
+        delta = sigma_deg if sigma_deg > 0 else 0.01
+        y[idx_in] = _unit_rows(z[idx_in] + delta * rng.normal(size=(n_in, 3)))
+    else:
+        raise ValueError(f"unknown noise model {noise!r}")
+    idx_out = perm[n_in:]
+    y[idx_out] = _unit_rows(rng.normal(size=(len(idx_out), 3))) if len(idx_out) else y[idx_out]
+    if same_axis_ratio > 0.0 and len(idx_out):
+        n_sa = min(len(idx_out), int(round(same_axis_ratio * n)))
+        sel = idx_out[:n_sa]
+        axis = _unit_rows(rng.normal(size=(1, 3)))
+        ang = rng.uniform(-math.pi, math.pi, size=n_sa)
+        y[sel] = _rotate_about(xh[sel], np.repeat(axis, n_sa, axis=0), ang)
+    x_out = (xh * r[:, None]).T.astype(np.float32)
+    y_out = y.T.astype(np.float32)
+    return Instance(np.ascontiguousarray(x_out), np.ascontiguousarray(y_out), q, inlier,
+                    seed, dict(n=n, outlier_ratio=outlier_ratio, sigma_deg=sigma_deg,
+                               radii=radii, noise=noise, same_axis_ratio=same_axis_ratio))
