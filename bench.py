@@ -1,0 +1,147 @@
+"""Benchmark of one robust rotation solve on one MI355X.
+
+A step is one whole solve (clear grid, vote, top-K, rescore, mask, readback of
+q and the count) on the large workload: N = 1e6 correspondences at 99 %
+outliers, G = 256 (64 MiB int32 grid), J = 2048 samples per circle, eps = 1.5
+deg, K = 64.  Inputs are resident in HBM before the timed region starts.
+
+Prints one JSON line.  ``value`` is circle-sample votes per second of the whole
+solve (N * J / seconds per solve); solves/s, the per-stage device times (HIP
+events recorded on the solve stream inside the timed region), the roofline of
+the dominant kernel and the CPU oracle's rate on a bounded sample ride along.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+from pathlib import Path
+
+ROOT = Path(__file__).resolve().parent
+sys.path.insert(0, str(ROOT))
+
+METRIC = "circle-sample votes/s + solves/s at N=1e6, 99% outliers; p99 latency served"
+
+# Peak rates of one MI355X used for the roofline fractions.
+HBM_PEAK_GBS = 8000.0
+# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz: one 32-bit vector operation per lane
+# per clock (the 157.3 TFLOP/s fp32 figure counts an FMA as 2 and packed dual
+# issue as 2 more, and packed fp32 is not used here).
+ALU_PEAK_GOPS = 256 * 64 * 2.4
+
+# Algorithmic 32-bit operations per circle sample, counted from the binary32
+# rule (one IEEE operation each): sampling 4 mul + 4 fma; sign test 1;
+# chart 1 add + 1 reciprocal + 1 mul; cell 3 fma + 3 floor + 6 clamp
+# compares + 2 index multiply-adds; vote 1 integer add.
+OPS_PER_SAMPLE = 27
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="large")
+    ap.add_argument("--strategy", default="auto")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=150_000,
+                    help="correspondences of the workload the CPU oracle times")
+    return ap.parse_args()
+
+
+def cpu_baseline(w, inst, n_sample: int) -> dict:
+    """The oracle, as it is, on the first n_sample correspondences."""
+    import oracle
+    o = oracle.get()
+    threads = oracle.threads()
+    n_sample = min(n_sample, inst.n)
+    x = inst.x[:, :n_sample].copy()
+    y = inst.y[:, :n_sample].copy()
+    eps = float(__import__("ctypes").c_float(w.eps_deg * math.pi / 180.0).value)
+    t0 = time.perf_counter()
+    o.solve(x, y, w.grid, w.samples, eps, w.topk, nthreads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": n_sample * w.samples / dt, "unit": "votes/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"first {n_sample} of the {inst.n} correspondences, whole solve "
+                      f"(G={w.grid}, J={w.samples}, K={w.topk}); vote loop on {threads} "
+                      f"OpenMP threads, top-K and rescoring single-threaded; {dt:.2f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (this build has no multi-GPU path); "
+              f"got --gpus {args.gpus}", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2506_11547_amd import datagen, rotvote
+
+    w, inst = datagen.make_workload(args.workload)
+    dev = torch.device("cuda", 0)
+    x = torch.from_numpy(inst.x).to(dev)
+    y = torch.from_numpy(inst.y).to(dev)
+    mask = torch.empty(inst.n, dtype=torch.bool, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    solver = rotvote.Solver(device=0, max_n=inst.n, max_grid=w.grid, topk=w.topk,
+                            samples_per_circle=w.samples, strategy=args.strategy, timing=True,
+                            stream=stream)
+    for _ in range(args.warmup):
+        solver.solve(x, y, w.grid, w.eps_deg, mask=mask)
+    stage = {k: 0.0 for k in rotvote.STAGE_NAMES}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        q, cnt, _ = solver.solve(x, y, w.grid, w.eps_deg, mask=mask)
+        for k, v in solver.timings().items():
+            stage[k] += v
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    plan = solver.plan()
+    top = solver.topk()
+    solver.close()
+
+    steps = args.steps
+    samples = inst.n * w.samples
+    ms_step = dt / steps * 1e3
+    stage_ms = {k: v / steps for k, v in stage.items()}
+    vote_s = stage_ms["vote"] * 1e-3
+    achieved = OPS_PER_SAMPLE * samples / vote_s / 1e9
+    out = {
+        "metric": METRIC,
+        "value": samples / (dt / steps),
+        "unit": "votes/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "n": w.n, "outlier_ratio": w.outlier_ratio,
+                   "sigma_deg": w.sigma_deg, "grid": w.grid, "samples_per_circle": w.samples,
+                   "eps_deg": w.eps_deg, "topk": w.topk, "seed": w.seed,
+                   "vote_strategy": plan["strategy"]},
+        "solves_per_s": steps / dt,
+        "stage_ms": stage_ms,
+        "roofline": {"bound": "alu", "kernel": "vote", "achieved": achieved / 1e3,
+                     "peak": ALU_PEAK_GOPS / 1e3, "unit": "TOP/s", "frac": achieved / ALU_PEAK_GOPS,
+                     "traffic": None,
+                     "ops_per_sample": OPS_PER_SAMPLE, "samples_per_launch": samples},
+        "result": {"q": q, "inliers": cnt, "e_R_deg": datagen.rotation_error_deg(q, inst.q_gt),
+                   "winner": top["winner"], "true_inliers": int(inst.inlier.sum())},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, inst, args.cpu_sample)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,137 @@
+/*
+ * rotvote — robust rotation estimation by quaternion-circle voting on one
+ * MI355X (gfx950), as a C ABI.
+ *
+ * Method ("Linearly Solving Robust Rotation Estimation", arXiv 2506.11547):
+ * the rotations that take x_i to y_i form a great circle of the unit
+ * quaternion sphere (Sec. 4.1), the null space of the 4x4 constraint
+ * L_i q = 0 (Lemma 1, App. D).  Each circle is sampled, the samples are
+ * projected stereographically into the cube [-1,1]^3 cut into G^3 cells
+ * (Sec. 4.3.1) and every sample adds one vote to its cell (Alg. 1).  The K
+ * cells with the most votes (Alg. 1's peak; Sec. 4.4 keeps several peaks)
+ * are rescored exactly by counting |L_i q| <= 2 sin(eps/2), i.e. the angle
+ * between R(q) x_i and y_i is at most eps, and the best one is returned with
+ * its inlier count and inlier mask.
+ *
+ * Conventions used throughout:
+ *  - correspondences: float32 structure-of-arrays, x[3*n] = {x_0..x_{n-1}
+ *    components 0, then components 1, then components 2}; same for y.  Only
+ *    the direction is used; a vector whose squared norm is not a positive
+ *    finite float is "unusable": it casts no vote and is never an inlier.
+ *  - quaternions: (w, x, y, z), Hamilton convention, returned with w >= 0
+ *    (first nonzero component positive).
+ *  - vote grid: int32 [G][G][G], x fastest: idx = (iz*G + iy)*G + ix; cell
+ *    (ix,iy,iz) covers the chart points p = q_vec / (1 + w) with
+ *    (p_c + 1) G/2 in [i_c, i_c + 1).
+ *  - J samples per circle: 0 in the config means J = 8 G.
+ *  - every call runs on the handle's HIP stream; rot_vote_solve returns after
+ *    that stream has finished the solve.
+ *  - errors: a negative rv_status; the outputs are left untouched and
+ *    rot_vote_last_error(h) describes the reason.  A handle is not
+ *    thread-safe; several handles may coexist on one device.
+ */
+#ifndef ROTVOTE_H
+#define ROTVOTE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rv_handle rv_handle;
+
+typedef enum rv_status {
+    RV_OK = 0,
+    RV_EINVAL = -1,        /* an argument is out of range, NULL, or not device memory */
+    RV_ENOMEM = -2,        /* device or pinned host allocation failed */
+    RV_EDEVICE = -3,       /* the HIP runtime reported an error */
+    RV_EUNSUPPORTED = -4   /* valid but beyond the library's limits (n*J > 2^31-1) */
+} rv_status;
+
+/* How the vote histogram is accumulated; every strategy yields the same
+ * histogram bit for bit (integer additions commute). */
+typedef enum rv_vote_strategy {
+    RV_VOTE_AUTO = 0,      /* chosen per (G, n) from measurements */
+    RV_VOTE_GLOBAL = 1,    /* run-coalesced atomics straight into the grid */
+    RV_VOTE_BRICK = 2      /* runs binned by brick, bricks accumulated in LDS */
+} rv_vote_strategy;
+
+enum {
+    RV_FLAG_TIMING = 1u    /* record per-stage HIP events (rot_vote_get_timings) */
+};
+
+enum { RV_MAX_TOPK = 64, RV_MAX_GRID = 1024, RV_NUM_STAGES = 6 };
+
+typedef struct rv_config {
+    int32_t device;              /* HIP device ordinal */
+    void *stream;                /* hipStream_t to launch on; NULL = the null stream */
+    int64_t max_n;               /* largest n a solve may pass (>= 0) */
+    int32_t max_grid;            /* largest G a solve may pass, 1..RV_MAX_GRID */
+    int32_t samples_per_circle;  /* J; 0 = 8*G per solve */
+    int32_t topk;                /* K candidates rescored, 1..RV_MAX_TOPK */
+    int32_t vote_strategy;       /* rv_vote_strategy */
+    uint32_t flags;              /* RV_FLAG_* */
+    int32_t reserved[4];         /* must be 0 */
+} rv_config;
+
+/* Fills *cfg with: device 0, null stream, max_n 1<<20, max_grid 256, J = 8G,
+ * K = 16, automatic vote strategy, no flags. */
+void rot_vote_default_config(rv_config *cfg);
+
+/* Creates a handle on cfg->device and allocates all device scratch for the
+ * config's maxima: the G^3 int32 grid (64 MiB at G = 256), the sample table,
+ * top-K and result buffers.  The handle owns that memory until destroy.
+ * *out is set only on success.  RV_EINVAL for a bad config, RV_ENOMEM when the
+ * scratch does not fit, RV_EDEVICE for other runtime errors. */
+rv_status rot_vote_create(rv_handle **out, const rv_config *cfg);
+
+/* Releases the handle and its scratch (after its stream is idle).  NULL is a
+ * no-op. */
+rv_status rot_vote_destroy(rv_handle *h);
+
+/* Reason for the handle's last error ("" if none); valid until the next call
+ * on h.  A NULL handle yields the reason of the last failed create. */
+const char *rot_vote_last_error(const rv_handle *h);
+
+/* Rebinds the handle to another HIP stream (e.g. the caller's current one). */
+rv_status rot_vote_set_stream(rv_handle *h, void *stream);
+
+/* One robust solve (Alg. 1 voting, then exact rescoring of the top K cells).
+ *   x, y          device pointers, float32 SoA [3][n] (see conventions); read only.
+ *   n             number of correspondences, 0..max_n.
+ *   grid          G, cells per axis of the vote cube, 1..max_grid.
+ *   eps_rad       inlier angle threshold in radians, (0, pi].
+ *   q_out         host float[4]: the winning cell centre as a unit quaternion.
+ *   inlier_count  host: number of usable correspondences with angle <= eps.
+ *   inlier_mask   device uint8[n]: 1 for those correspondences, else 0.
+ * n == 0 returns q = (1,0,0,0), count 0.  No votes at all (every
+ * correspondence unusable) gives the same.  RV_EUNSUPPORTED if n*J exceeds
+ * 2^31-1 (int32 vote counts).  Synchronous on the handle's stream. */
+rv_status rot_vote_solve(rv_handle *h, const float *x, const float *y, int64_t n, int32_t grid,
+                         float eps_rad, float q_out[4], int64_t *inlier_count,
+                         uint8_t *inlier_mask);
+
+/* Test hook: copies the last solve's vote grid (G^3 int32, x fastest) to the
+ * device buffer dst.  RV_EINVAL before the first solve. */
+rv_status rot_vote_get_histogram(rv_handle *h, int32_t *dst_device);
+
+/* Test hook: the last solve's candidates.  Writes *n_cand (<= K) and, for
+ * k < *n_cand, the cell vote count, cell index and exact inlier count of
+ * candidate k (ordered by votes desc, index asc) to host arrays of length K;
+ * *winner is the position of the returned candidate (-1 if none). */
+rv_status rot_vote_get_topk(rv_handle *h, int32_t *n_cand, int32_t *votes, int32_t *cell_idx,
+                            int64_t *inliers, int32_t *winner);
+
+/* Test hook: J and the vote strategy the last solve used. */
+rv_status rot_vote_get_plan(rv_handle *h, int32_t *samples_per_circle, int32_t *vote_strategy);
+
+/* With RV_FLAG_TIMING: device milliseconds of the last solve's stages
+ * {clear grid, vote, top-K partial, top-K final, rescore, mask} measured with
+ * HIP events on the handle's stream; ms must hold RV_NUM_STAGES floats. */
+rv_status rot_vote_get_timings(rv_handle *h, float *ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,283 @@
+"""Thin Python binding of ``librotvote.so`` (argument marshalling only).
+
+PyTorch provides device memory and streams; every step of a solve runs in the
+library's HIP kernels.  There is no fallback: if the library is missing or no
+GPU is visible, construction raises.
+
+torch is imported before the library is loaded so that the library binds to
+the HIP runtime torch already loaded (one runtime per process).
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import math
+from pathlib import Path
+
+import torch
+
+PKG = Path(__file__).resolve().parent
+LIB_PATH = PKG / "librotvote.so"
+PROBE_PATH = PKG / "librotvote_probe.so"
+
+RV_OK, RV_EINVAL, RV_ENOMEM, RV_EDEVICE, RV_EUNSUPPORTED = 0, -1, -2, -3, -4
+STATUS_NAMES = {0: "RV_OK", -1: "RV_EINVAL", -2: "RV_ENOMEM", -3: "RV_EDEVICE",
+                -4: "RV_EUNSUPPORTED"}
+STRATEGIES = {"auto": 0, "global": 1, "brick": 2}
+STRATEGY_NAMES = {v: k for k, v in STRATEGIES.items()}
+FLAG_TIMING = 1
+MAX_TOPK = 64
+NUM_STAGES = 6
+STAGE_NAMES = ("clear", "vote", "topk_partial", "topk_final", "rescore", "mask")
+
+# Names the C header declares; the CPU test suite checks the library exports each.
+EXPORTS = ("rot_vote_default_config", "rot_vote_create", "rot_vote_destroy",
+           "rot_vote_last_error", "rot_vote_set_stream", "rot_vote_solve",
+           "rot_vote_get_histogram", "rot_vote_get_topk", "rot_vote_get_plan",
+           "rot_vote_get_timings")
+
+
+class RvConfig(ct.Structure):
+    _fields_ = [("device", ct.c_int32), ("stream", ct.c_void_p), ("max_n", ct.c_int64),
+                ("max_grid", ct.c_int32), ("samples_per_circle", ct.c_int32),
+                ("topk", ct.c_int32), ("vote_strategy", ct.c_int32), ("flags", ct.c_uint32),
+                ("reserved", ct.c_int32 * 4)]
+
+
+class RotVoteError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def load_library(path: Path | str = LIB_PATH) -> ct.CDLL:
+    """Load (once) and type the C-ABI."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = Path(path)
+    if not path.exists():
+        raise ImportError(f"{path.name} is not built; run __graft_entry__.build() first")
+    L = ct.CDLL(str(path))
+    vp, i32, i64, f32 = ct.c_void_p, ct.c_int32, ct.c_int64, ct.c_float
+    L.rot_vote_default_config.argtypes = [ct.POINTER(RvConfig)]
+    L.rot_vote_default_config.restype = None
+    L.rot_vote_create.argtypes = [ct.POINTER(vp), ct.POINTER(RvConfig)]
+    L.rot_vote_create.restype = i32
+    L.rot_vote_destroy.argtypes = [vp]
+    L.rot_vote_destroy.restype = i32
+    L.rot_vote_last_error.argtypes = [vp]
+    L.rot_vote_last_error.restype = ct.c_char_p
+    L.rot_vote_set_stream.argtypes = [vp, vp]
+    L.rot_vote_set_stream.restype = i32
+    L.rot_vote_solve.argtypes = [vp, vp, vp, i64, i32, f32, ct.POINTER(f32 * 4),
+                                 ct.POINTER(i64), vp]
+    L.rot_vote_solve.restype = i32
+    L.rot_vote_get_histogram.argtypes = [vp, vp]
+    L.rot_vote_get_histogram.restype = i32
+    L.rot_vote_get_topk.argtypes = [vp, ct.POINTER(i32), ct.POINTER(i32 * MAX_TOPK),
+                                    ct.POINTER(i32 * MAX_TOPK), ct.POINTER(i64 * MAX_TOPK),
+                                    ct.POINTER(i32)]
+    L.rot_vote_get_topk.restype = i32
+    L.rot_vote_get_plan.argtypes = [vp, ct.POINTER(i32), ct.POINTER(i32)]
+    L.rot_vote_get_plan.restype = i32
+    L.rot_vote_get_timings.argtypes = [vp, ct.POINTER(f32 * NUM_STAGES)]
+    L.rot_vote_get_timings.restype = i32
+    _lib = L
+    return L
+
+
+def eps_deg_to_rad(eps_deg: float) -> float:
+    """Degrees to the float32 radians the C-ABI takes (converted in float64)."""
+    return float(ct.c_float(eps_deg * math.pi / 180.0).value)
+
+
+class Solver:
+    """One library handle: owns the vote grid and scratch for its maxima."""
+
+    def __init__(self, device: int = 0, max_n: int = 1 << 20, max_grid: int = 256,
+                 topk: int = 16, samples_per_circle: int = 0, strategy: str = "auto",
+                 timing: bool = False, stream: torch.cuda.Stream | None = None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("rotvote needs a HIP GPU; none is visible")
+        self._lib = load_library()
+        self.device = torch.device("cuda", device)
+        cfg = RvConfig()
+        self._lib.rot_vote_default_config(ct.byref(cfg))
+        cfg.device = device
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        cfg.stream = ct.c_void_p(s.cuda_stream)
+        cfg.max_n = max_n
+        cfg.max_grid = max_grid
+        cfg.samples_per_circle = samples_per_circle
+        cfg.topk = topk
+        cfg.vote_strategy = STRATEGIES[strategy]
+        cfg.flags = FLAG_TIMING if timing else 0
+        h = ct.c_void_p()
+        st = self._lib.rot_vote_create(ct.byref(h), ct.byref(cfg))
+        if st != RV_OK:
+            raise RotVoteError(st, self._lib.rot_vote_last_error(None).decode())
+        self._h = h
+        self.topk_k = topk
+        self.max_n = max_n
+        self.max_grid = max_grid
+        self._stream = s
+        self._last_grid = None
+
+    # ---- lifetime
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.rot_vote_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def _check(self, st: int):
+        if st != RV_OK:
+            raise RotVoteError(st, self._lib.rot_vote_last_error(self._h).decode())
+
+    def set_stream(self, stream: torch.cuda.Stream):
+        self._check(self._lib.rot_vote_set_stream(self._h, ct.c_void_p(stream.cuda_stream)))
+        self._stream = stream
+
+    # ---- solve
+    def solve_raw(self, x_ptr: int, y_ptr: int, n: int, grid: int, eps_rad: float,
+                  mask_ptr: int):
+        """Direct C-ABI call on raw device addresses; returns (q, count)."""
+        q = (ct.c_float * 4)()
+        cnt = ct.c_int64()
+        self._check(self._lib.rot_vote_solve(self._h, ct.c_void_p(x_ptr), ct.c_void_p(y_ptr), n,
+                                             grid, ct.c_float(eps_rad), ct.byref(q),
+                                             ct.byref(cnt), ct.c_void_p(mask_ptr)))
+        self._last_grid = grid
+        return [q[0], q[1], q[2], q[3]], int(cnt.value)
+
+    def solve(self, x: torch.Tensor, y: torch.Tensor, grid: int, eps_deg: float,
+              mask: torch.Tensor | None = None):
+        """x, y: float32 [3, N] device tensors (SoA).  Returns (q, count, mask)."""
+        for t, nm in ((x, "x"), (y, "y")):
+            if t.dtype != torch.float32 or t.dim() != 2 or t.shape[0] != 3 or not t.is_cuda:
+                raise ValueError(f"{nm} must be a float32 [3, N] device tensor")
+        if x.shape != y.shape:
+            raise ValueError("x and y must have the same shape")
+        x = x.contiguous()
+        y = y.contiguous()
+        n = x.shape[1]
+        if mask is None:
+            mask = torch.empty(n, dtype=torch.bool, device=x.device)
+        q, cnt = self.solve_raw(x.data_ptr(), y.data_ptr(), n, grid, eps_deg_to_rad(eps_deg),
+                                mask.data_ptr() if n else 0)
+        return q, cnt, mask
+
+    # ---- test hooks
+    def histogram(self) -> torch.Tensor:
+        g = self._last_grid
+        if g is None:
+            raise RuntimeError("no solve yet")
+        out = torch.empty(g ** 3, dtype=torch.int32, device=self.device)
+        self._check(self._lib.rot_vote_get_histogram(self._h, ct.c_void_p(out.data_ptr())))
+        return out
+
+    def topk(self) -> dict:
+        nc = ct.c_int32()
+        votes = (ct.c_int32 * MAX_TOPK)()
+        idx = (ct.c_int32 * MAX_TOPK)()
+        inl = (ct.c_int64 * MAX_TOPK)()
+        win = ct.c_int32()
+        self._check(self._lib.rot_vote_get_topk(self._h, ct.byref(nc), ct.byref(votes),
+                                                ct.byref(idx), ct.byref(inl), ct.byref(win)))
+        m = nc.value
+        return dict(votes=list(votes[:m]), idx=list(idx[:m]), inliers=list(inl[:m]),
+                    winner=win.value)
+
+    def plan(self) -> dict:
+        J = ct.c_int32()
+        s = ct.c_int32()
+        self._check(self._lib.rot_vote_get_plan(self._h, ct.byref(J), ct.byref(s)))
+        return dict(samples_per_circle=J.value, strategy=STRATEGY_NAMES.get(s.value, s.value))
+
+    def timings(self) -> dict:
+        ms = (ct.c_float * NUM_STAGES)()
+        self._check(self._lib.rot_vote_get_timings(self._h, ct.byref(ms)))
+        return dict(zip(STAGE_NAMES, list(ms)))
+
+
+class Probe:
+    """Test hooks of ``librotvote_probe.so``: single device steps of the rule."""
+
+    def __init__(self, path: Path | str = PROBE_PATH):
+        path = Path(path)
+        if not path.exists():
+            raise ImportError(f"{path.name} is not built; run __graft_entry__.build() first")
+        L = self.lib = ct.CDLL(str(path))
+        vp, i64, i32 = ct.c_void_p, ct.c_int64, ct.c_int32
+        L.rvp_recip.argtypes = [vp, vp, i64, i32]
+        L.rvp_div_sqrt.argtypes = [vp, vp, vp, vp, i64]
+        L.rvp_basis.argtypes = [vp, vp, i64, vp, vp, vp]
+        L.rvp_cells.argtypes = [vp, i64, i32, vp, i32]
+        L.rvp_decode.argtypes = [vp, i64, i32, vp]
+        L.rvp_residual.argtypes = [vp, vp, i64, vp, vp]
+        for f in (L.rvp_recip, L.rvp_div_sqrt, L.rvp_basis, L.rvp_cells, L.rvp_decode,
+                  L.rvp_residual):
+            f.restype = i32
+
+    @staticmethod
+    def _p(t: torch.Tensor):
+        return ct.c_void_p(t.data_ptr())
+
+    def _run(self, rc: int):
+        if rc != 0:
+            raise RuntimeError(f"probe kernel failed with HIP error {rc}")
+
+    def recip(self, d: torch.Tensor, fast: bool) -> torch.Tensor:
+        torch.cuda.synchronize()
+        out = torch.empty_like(d)
+        self._run(self.lib.rvp_recip(self._p(d), self._p(out), d.numel(), int(fast)))
+        return out
+
+    def div_sqrt(self, a: torch.Tensor, b: torch.Tensor):
+        torch.cuda.synchronize()
+        q = torch.empty_like(a)
+        r = torch.empty_like(a)
+        self._run(self.lib.rvp_div_sqrt(self._p(a), self._p(b), self._p(q), self._p(r), a.numel()))
+        return q, r
+
+    def basis(self, x: torch.Tensor, y: torch.Tensor):
+        torch.cuda.synchronize()
+        n = x.shape[1]
+        u = torch.empty(n, 4, dtype=torch.float32, device=x.device)
+        v = torch.empty_like(u)
+        ok = torch.empty(n, dtype=torch.int32, device=x.device)
+        self._run(self.lib.rvp_basis(self._p(x), self._p(y), n, self._p(u), self._p(v), self._p(ok)))
+        return u, v, ok
+
+    def cells(self, q: torch.Tensor, G: int, fast: bool) -> torch.Tensor:
+        torch.cuda.synchronize()
+        out = torch.empty(q.shape[0], dtype=torch.int32, device=q.device)
+        self._run(self.lib.rvp_cells(self._p(q), q.shape[0], G, self._p(out), int(fast)))
+        return out
+
+    def decode(self, idx: torch.Tensor, G: int) -> torch.Tensor:
+        torch.cuda.synchronize()
+        q = torch.empty(idx.numel(), 4, dtype=torch.float32, device=idx.device)
+        self._run(self.lib.rvp_decode(self._p(idx), idx.numel(), G, self._p(q)))
+        return q
+
+    def residual(self, x: torch.Tensor, y: torch.Tensor, q: torch.Tensor) -> torch.Tensor:
+        torch.cuda.synchronize()
+        out = torch.empty(x.shape[1], dtype=torch.float32, device=x.device)
+        self._run(self.lib.rvp_residual(self._p(x), self._p(y), x.shape[1], self._p(q),
+                                        self._p(out)))
+        return out

@@ -1,0 +1,91 @@
+"""The C-ABI library loads and exports every entry point its header declares
+(no compute calls: this runs without a GPU), and stays independent of the
+oracle."""
+import ctypes as ct
+import re
+import subprocess
+from pathlib import Path
+
+import pytest
+
+ROOT = Path(__file__).resolve().parents[1]
+HEADER = ROOT / "include" / "rotvote.h"
+LIB = ROOT / "paper_2506_11547_amd" / "librotvote.so"
+PROBE = ROOT / "paper_2506_11547_amd" / "librotvote_probe.so"
+
+
+def declared():
+    text = HEADER.read_text()
+    return sorted(set(re.findall(r"\b(rot_vote_\w+)\s*\(", text)))
+
+
+def dynamic_symbols(lib: Path):
+    out = subprocess.run(["nm", "-D", "--defined-only", str(lib)], capture_output=True,
+                         text=True, check=True).stdout
+    return {ln.split()[-1] for ln in out.splitlines() if ln.strip()}
+
+
+@pytest.fixture(scope="module")
+def lib_path():
+    if not LIB.exists():
+        pytest.fail("librotvote.so is not built (run __graft_entry__.build())")
+    return LIB
+
+
+def test_header_declares_the_boundary():
+    names = declared()
+    for need in ("rot_vote_create", "rot_vote_solve", "rot_vote_destroy", "rot_vote_last_error"):
+        assert need in names
+
+
+def test_library_exports_every_declared_symbol(lib_path):
+    syms = dynamic_symbols(lib_path)
+    missing = [n for n in declared() if n not in syms]
+    assert not missing, missing
+    # nothing but the C-ABI is exported
+    extra = [s for s in syms if s.startswith("rot_vote") and s not in declared()]
+    assert not extra, extra
+    lib = ct.CDLL(str(lib_path))
+    for n in declared():
+        assert getattr(lib, n) is not None
+
+
+def test_binding_names_match_header():
+    from paper_2506_11547_amd import rotvote
+    assert sorted(rotvote.EXPORTS) == declared()
+
+
+def test_product_library_does_not_reference_the_oracle(lib_path):
+    out = subprocess.run(["nm", "-D", str(lib_path)], capture_output=True, text=True).stdout
+    assert "orc_" not in out
+    ldd = subprocess.run(["readelf", "-d", str(lib_path)], capture_output=True, text=True).stdout
+    assert "liborc" not in ldd
+    for src in (ROOT / "paper_2506_11547_amd").rglob("*"):
+        if src.suffix in (".py", ".hip", ".cpp", ".h"):
+            text = src.read_text()
+            assert "import oracle" not in text and "from oracle" not in text, src
+            assert "rotvote_oracle" not in text, src
+
+
+def test_probe_library_exports(lib_path):
+    syms = dynamic_symbols(PROBE)
+    for n in ("rvp_recip", "rvp_div_sqrt", "rvp_basis", "rvp_cells", "rvp_decode", "rvp_residual"):
+        assert n in syms
+
+
+def test_default_config_and_create_without_gpu(lib_path):
+    from paper_2506_11547_amd.rotvote import RvConfig
+    lib = ct.CDLL(str(lib_path))
+    cfg = RvConfig()
+    lib.rot_vote_default_config(ct.byref(cfg))
+    assert cfg.max_grid == 256 and cfg.topk == 16 and cfg.samples_per_circle == 0
+    lib.rot_vote_create.argtypes = [ct.POINTER(ct.c_void_p), ct.POINTER(RvConfig)]
+    lib.rot_vote_last_error.restype = ct.c_char_p
+    lib.rot_vote_last_error.argtypes = [ct.c_void_p]
+    bad = RvConfig()
+    lib.rot_vote_default_config(ct.byref(bad))
+    bad.topk = 65
+    h = ct.c_void_p()
+    assert lib.rot_vote_create(ct.byref(h), ct.byref(bad)) == -1
+    assert b"topk" in lib.rot_vote_last_error(None)
+    assert not h.value
