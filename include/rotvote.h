@@ -126,9 +126,16 @@ rv_status rot_vote_get_topk(rv_handle *h, int32_t *n_cand, int32_t *votes, int32
 /* Test hook: J and the vote strategy the last solve used. */
 rv_status rot_vote_get_plan(rv_handle *h, int32_t *samples_per_circle, int32_t *vote_strategy);
 
-/* With RV_FLAG_TIMING: device milliseconds of the last solve's stages
- * {clear grid, vote, top-K partial, top-K final, rescore, mask} measured with
- * HIP events on the handle's stream; ms must hold RV_NUM_STAGES floats. */
+/* With RV_FLAG_TIMING: device milliseconds of the last solve's stages,
+ * measured with HIP events on the handle's stream; ms must hold
+ * RV_NUM_STAGES floats:
+ *   0 prepare  (global: clear the grid; brick: size the brick queues)
+ *   1 vote     (sample every circle and accumulate or bin its votes)
+ *   2 reduce   (global: per-block top-64 scan; brick: accumulate bricks in LDS,
+ *               write the grid, per-brick top-64)
+ *   3 top-K    (merge the lists, decode the K candidates)
+ *   4 rescore  (exact inlier count of every candidate)
+ *   5 mask     (winner, inlier mask, result record) */
 rv_status rot_vote_get_timings(rv_handle *h, float *ms);
 
 #ifdef __cplusplus

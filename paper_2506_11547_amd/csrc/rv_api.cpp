@@ -18,6 +18,9 @@
 namespace {
 
 constexpr int kStages = RV_NUM_STAGES;
+// Below this grid the whole int32 grid (<= 1.4 MiB at 72^3) sits in every
+// XCD's L2 and run-coalesced atomics straight into it beat binning.
+constexpr int kBrickMinGrid = 72;
 
 std::string g_create_error;  // reason of the last failed create (NULL handle)
 
@@ -43,6 +46,11 @@ struct rv_handle {
     rv::Result* h_result = nullptr;     // pinned
     float2* h_table = nullptr;          // pinned staging for the table
     int32_t table_J = -1;               // J the device table holds
+
+    // brick strategy scratch (allocated when the config allows that strategy)
+    bool brick_ok = false;
+    rv::BinArgs bin{};
+    int32_t* d_ovf = nullptr;           // max_grid^3, zero between solves
 
     hipEvent_t ev[kStages + 1] = {};
     bool timing = false;
@@ -108,6 +116,13 @@ void release(rv_handle* h)
     (void)hipFree(h->d_cand_idx);
     (void)hipFree(h->d_cand_inl);
     (void)hipFree(h->d_result);
+    (void)hipFree(h->bin.pool);
+    (void)hipFree(h->bin.fill);
+    (void)hipFree(h->bin.qbase);
+    (void)hipFree(h->bin.cap);
+    (void)hipFree(h->bin.est);
+    (void)hipFree(h->bin.flags);
+    (void)hipFree(h->d_ovf);
     (void)hipHostFree(h->h_result);
     (void)hipHostFree(h->h_table);
     for (auto& e : h->ev)
@@ -221,6 +236,31 @@ RV_API rv_status rot_vote_create(rv_handle** out, const rv_config* cfg)
     for (auto& ev : h->ev)
         if ((e = hipEventCreate(&ev)) != hipSuccess)
             return bail(e, "events");
+    if (cfg->vote_strategy != RV_VOTE_GLOBAL && h->max_grid <= rv::kMaxBrickGrid) {
+        // Run pool: about 1.7 G runs per circle are expected at J = 8 G (at
+        // most J); room for 3 G per circle plus the per-queue slack.
+        const uint64_t per_circle = (uint64_t)std::min<int64_t>(h->max_J, 3 * (int64_t)h->max_grid);
+        uint64_t runs = (uint64_t)h->max_n * per_circle +
+                        (uint64_t)rv::kQueueSets * rv::kMaxBricks * 320u;
+        runs = std::min<uint64_t>(runs, 0xFFFFFFFFull - 64);
+        h->bin.pool_runs = runs;
+        const size_t nq = (size_t)rv::kQueueSets * rv::kMaxBricks;
+        if ((e = hipMalloc(&h->bin.pool, runs * sizeof(uint32_t))) != hipSuccess)
+            return bail(e, "brick run pool");
+        if ((e = hipMalloc(&h->bin.fill, nq * sizeof(uint32_t))) != hipSuccess ||
+            (e = hipMalloc(&h->bin.qbase, nq * sizeof(uint32_t))) != hipSuccess ||
+            (e = hipMalloc(&h->bin.cap, rv::kMaxBricks * sizeof(uint32_t))) != hipSuccess ||
+            (e = hipMalloc(&h->bin.est, rv::kMaxBricks * sizeof(uint32_t))) != hipSuccess ||
+            (e = hipMalloc(&h->bin.flags, rv::kMaxBricks * sizeof(uint32_t))) != hipSuccess ||
+            (e = hipMalloc(&h->d_ovf, ncell * sizeof(int32_t))) != hipSuccess)
+            return bail(e, "brick scratch");
+        if ((e = hipMemset(h->bin.est, 0, rv::kMaxBricks * sizeof(uint32_t))) != hipSuccess ||
+            (e = hipMemset(h->d_ovf, 0, ncell * sizeof(int32_t))) != hipSuccess ||
+            (e = hipDeviceSynchronize()) != hipSuccess)
+            return bail(e, "brick scratch init");
+        h->bin.ovf = h->d_ovf;
+        h->brick_ok = true;
+    }
     *out = h;
     return RV_OK;
 }
@@ -280,7 +320,13 @@ RV_API rv_status rot_vote_solve(rv_handle* h, const float* x, const float* y, in
     hipStream_t s = h->stream;
     const int64_t ncell = (int64_t)grid * grid * grid;
     const float T2 = residual_bound(eps_rad);
-    const int strategy = RV_VOTE_GLOBAL;
+    int strategy = h->cfg.vote_strategy;
+    if (strategy == RV_VOTE_AUTO)
+        strategy = (h->brick_ok && grid >= kBrickMinGrid && grid <= rv::kMaxBrickGrid)
+                       ? RV_VOTE_BRICK : RV_VOTE_GLOBAL;
+    if (strategy == RV_VOTE_BRICK && !(h->brick_ok && grid <= rv::kMaxBrickGrid))
+        return fail(h, RV_EUNSUPPORTED,
+                    "rot_vote_solve: the brick strategy needs grid <= 256 and a handle created for it");
 
     if (h->table_J != J) {
         RV_HIP(h, hipStreamSynchronize(s), "sync before table upload");
@@ -292,16 +338,36 @@ RV_API rv_status rot_vote_solve(rv_handle* h, const float* x, const float* y, in
     }
 
     const bool tm = h->timing;
-    if (tm)
-        RV_HIP(h, hipEventRecord(h->ev[0], s), "event");
-    RV_HIP(h, rv::launch_fill(h->d_hist, ncell, 0, s), "clear grid");
-    if (tm)
-        RV_HIP(h, hipEventRecord(h->ev[1], s), "event");
-
+    const bool brick = strategy == RV_VOTE_BRICK;
     h->solved = true;
     h->last_grid = grid;
     h->last_J = J;
     h->last_strategy = strategy;
+    if (tm)
+        RV_HIP(h, hipEventRecord(h->ev[0], s), "event");
+    if (brick)
+        RV_HIP(h, rv::launch_bin_prepare(x, y, n, grid, J, h->d_table, h->bin, s), "brick plan");
+    else
+        RV_HIP(h, rv::launch_fill(h->d_hist, ncell, 0, s), "clear grid");
+    if (tm)
+        RV_HIP(h, hipEventRecord(h->ev[1], s), "event");
+    if (brick)
+        RV_HIP(h, rv::launch_bin_vote(x, y, n, grid, J, h->d_table, h->bin, s), "binned vote");
+    else
+        RV_HIP(h, rv::launch_vote_global(x, y, n, grid, J, h->d_table, h->d_hist, 0, s), "vote");
+    if (tm)
+        RV_HIP(h, hipEventRecord(h->ev[2], s), "event");
+    int nlists;
+    if (brick) {
+        RV_HIP(h, rv::launch_brick_accum(grid, h->d_hist, h->d_partial, h->bin, s), "brick accumulate");
+        const int nba = rv::brick_axis(grid);
+        nlists = nba * nba * nba;
+    } else {
+        nlists = rv::topk_blocks(ncell);
+        RV_HIP(h, rv::launch_topk_partial(h->d_hist, ncell, nlists, h->d_partial, s), "top-K partial");
+    }
+    if (tm)
+        RV_HIP(h, hipEventRecord(h->ev[3], s), "event");
     if (n == 0) {
         RV_HIP(h, hipStreamSynchronize(s), "sync");
         q_out[0] = 1.0f;
@@ -313,16 +379,8 @@ RV_API rv_status rot_vote_solve(rv_handle* h, const float* x, const float* y, in
         h->events_recorded = false;
         return RV_OK;
     }
-
-    RV_HIP(h, rv::launch_vote_global(x, y, n, grid, J, h->d_table, h->d_hist, 0, s), "vote");
-    if (tm)
-        RV_HIP(h, hipEventRecord(h->ev[2], s), "event");
-    const int nb = rv::topk_blocks(ncell);
-    RV_HIP(h, rv::launch_topk_partial(h->d_hist, ncell, nb, h->d_partial, s), "top-K partial");
-    if (tm)
-        RV_HIP(h, hipEventRecord(h->ev[3], s), "event");
     const rv::Candidates c = candidates(h);
-    RV_HIP(h, rv::launch_topk_final(h->d_partial, nb, h->K, grid, c, s), "top-K final");
+    RV_HIP(h, rv::launch_topk_final(h->d_partial, nlists, h->K, grid, c, s), "top-K final");
     if (tm)
         RV_HIP(h, hipEventRecord(h->ev[4], s), "event");
     RV_HIP(h, rv::launch_rescore(x, y, n, T2, c, s), "rescore");
@@ -409,7 +467,7 @@ RV_API rv_status rot_vote_get_timings(rv_handle* h, float* ms)
         return fail(h, RV_EINVAL, "rot_vote_get_timings: NULL argument");
     if (!h->timing || !h->events_recorded)
         return fail(h, RV_EINVAL, "rot_vote_get_timings: no timed solve (create with RV_FLAG_TIMING)");
-    // stages: clear, vote, top-K partial, top-K final, rescore, mask
+    // stages: prepare, vote, reduce, top-K, rescore, mask
     for (int k = 0; k < kStages; ++k)
         RV_HIP(h, hipEventElapsedTime(&ms[k], h->ev[k], h->ev[k + 1]), "hipEventElapsedTime");
     return RV_OK;

@@ -1,0 +1,414 @@
+// Brick-binned vote for grids up to 256^3 (the grid is far larger than LDS and
+// L2, so scattered atomics into it are bound by line traffic).
+//
+// The G^3 grid is cut into 32^3-cell bricks (128 KiB of int32, one brick per
+// CU's LDS).  Each vote run (a cell and how many consecutive samples of one
+// circle fell in it) is routed to its brick's queue in HBM; a second kernel
+// accumulates each brick's queue in LDS and writes the finished brick out once,
+// keeping its 64 best cells for the top-K stage.
+//
+//   k_bin_estimate  every 32nd circle, runs counted per brick (queue sizing)
+//   k_bin_plan      queue capacities and offsets in the run pool
+//   k_vote_bin      all circles: sample, bin (LDS staging), append to queues
+//   k_brick_accum   per brick: LDS histogram, write-out, top-64 list
+//
+// Queues are kept per XCD (blockIdx % 8), so the reservation atomics and the
+// partial-line writes of a queue tail stay in one XCD's L2.  A queue that
+// fills up sends its excess runs straight to a zeroed overflow grid with
+// atomics, and the brick's accumulation adds (and re-zeroes) those cells: the
+// capacities only change speed, never the histogram.
+#include "rv_device.h"
+#include "rv_internal.h"
+#include "rv_topk.h"
+
+namespace rv {
+
+namespace {
+
+constexpr int kEdge = 32;
+constexpr int kBrickCells = kEdge * kEdge * kEdge;
+constexpr int kSets = kQueueSets;
+constexpr int kBinWaves = 8;
+constexpr int kBinThreads = kBinWaves * kWave;
+constexpr int kStageCap = 2048;  // runs staged per wave between flushes
+constexpr int kStep = 16;        // samples per lane between flush checks
+constexpr int kSplit = 240;      // runs are cut every 240 samples: counts fit 8 bits
+// flush before a step could overflow a wave's staging: one step adds at most
+// kWave * kStep runs and a run-block boundary at most kWave more.
+constexpr int kFlushAt = kStageCap - kWave * kStep - kWave;
+constexpr int kAccumThreads = 1024;
+constexpr int kAccumWaves = kAccumThreads / kWave;
+
+__device__ __forceinline__ uint32_t brick_of(uint32_t pc, int nba)
+{
+    const uint32_t ix = pc & 255u, iy = (pc >> 8) & 255u, iz = (pc >> 16) & 255u;
+    return ((iz >> 5) * (uint32_t)nba + (iy >> 5)) * (uint32_t)nba + (ix >> 5);
+}
+
+__device__ __forceinline__ uint32_t local_of(uint32_t pc)
+{
+    const uint32_t ix = pc & 255u, iy = (pc >> 8) & 255u, iz = (pc >> 16) & 255u;
+    return ((iz & 31u) << 10) | ((iy & 31u) << 5) | (ix & 31u);
+}
+
+__device__ __forceinline__ int64_t global_of(uint32_t b, uint32_t loc, int nba, int G)
+{
+    const uint32_t bx = b % nba, by = (b / nba) % nba, bz = b / (nba * nba);
+    const int64_t gx = bx * kEdge + (loc & 31u);
+    const int64_t gy = by * kEdge + ((loc >> 5) & 31u);
+    const int64_t gz = bz * kEdge + (loc >> 10);
+    return (gz * G + gy) * G + gx;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------- estimate
+
+__global__ __launch_bounds__(256) void k_bin_estimate(const float* __restrict__ x,
+                                                      const float* __restrict__ y, int64_t n,
+                                                      float H, float gm, int J,
+                                                      const float2* __restrict__ table, int nba,
+                                                      uint32_t* __restrict__ est)
+{
+    __shared__ uint32_t s_est[kMaxBricks];
+    const int nb = nba * nba * nba;
+    for (int b = threadIdx.x; b < nb; b += 256)
+        s_est[b] = 0;
+    __syncthreads();
+    const int64_t i = ((int64_t)blockIdx.x * 256 + threadIdx.x) * kEstimateStride;
+    Quat u, v;
+    const bool ok = load_circle(x, y, n, i, u, v);
+    if (ok) {
+        for (int jb = 0; jb < J; jb += kSplit) {
+            uint32_t cur = 0xFFFFFFFFu;
+            // samples of one lane only: the loop bounds are uniform, the body divergent-free
+            for_samples<true>(u, v, table, jb, min(J, jb + kSplit), H, gm, [&](const Cell& c, int) {
+                const uint32_t pc = packed_coords(c);
+                if (pc != cur) {
+                    atomicAdd(&s_est[brick_of(pc, nba)], 1u);
+                    cur = pc;
+                }
+            });
+        }
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < nb; b += 256)
+        if (s_est[b])
+            atomicAdd(est + b, s_est[b]);
+}
+
+// ----------------------------------------------------------------- plan
+
+// One block.  cap = 1.15 x the estimated runs of the brick spread over the
+// queue sets, plus slack, in multiples of 64 runs (queues start 256-byte
+// aligned); scaled down if the pool cannot hold them all.  Resets the fill
+// counters, the overflow flags and the estimate for the next solve.
+__global__ __launch_bounds__(kMaxBricks) void k_bin_plan(BinArgs a, int nb)
+{
+    __shared__ uint64_t s_scan[kMaxBricks];
+    __shared__ uint64_t s_total;
+    const int b = threadIdx.x;
+    uint64_t capq = 0;
+    if (b < nb) {
+        const uint64_t e = (uint64_t)a.est[b] * kEstimateStride;
+        capq = (e * 115 / 100) / kSets + 256;
+        capq = (capq + 63) & ~63ull;
+    }
+    s_scan[b] = capq;
+    __syncthreads();
+    // inclusive scan (Hillis-Steele)
+    for (int off = 1; off < kMaxBricks; off <<= 1) {
+        const uint64_t t = b >= off ? s_scan[b - off] : 0;
+        __syncthreads();
+        s_scan[b] += t;
+        __syncthreads();
+    }
+    if (b == kMaxBricks - 1)
+        s_total = s_scan[b];
+    __syncthreads();
+    uint64_t total = s_total * kSets;
+    uint64_t excl = s_scan[b] - capq;
+    if (total > a.pool_runs) {
+        // proportional shrink, still in multiples of 64 runs
+        const double f = (double)a.pool_runs / (double)total;
+        capq = (uint64_t)((double)capq * f) & ~63ull;
+        s_scan[b] = capq;
+        __syncthreads();
+        for (int off = 1; off < kMaxBricks; off <<= 1) {
+            const uint64_t t = b >= off ? s_scan[b - off] : 0;
+            __syncthreads();
+            s_scan[b] += t;
+            __syncthreads();
+        }
+        if (b == kMaxBricks - 1)
+            s_total = s_scan[b];
+        __syncthreads();
+        excl = s_scan[b] - capq;
+        total = s_total * kSets;
+    }
+    if (b < nb) {
+        a.cap[b] = (uint32_t)capq;
+        for (int xs = 0; xs < kSets; ++xs) {
+            a.qbase[xs * kMaxBricks + b] = (uint32_t)(xs * s_total + excl);
+            a.fill[xs * kMaxBricks + b] = 0u;
+        }
+        a.flags[b] = 0u;
+        a.est[b] = 0u;
+    }
+}
+
+// ------------------------------------------------------------ vote + bin
+
+// Staged runs: cell packed one byte per axis, run length in the top byte.
+// Flush: each run is rewritten as brick << 23 | length << 15 | local cell,
+// counted per brick, one reservation atomic per brick, then written to its
+// queue slot (or, past the queue's capacity, added to the overflow grid).
+__device__ __forceinline__ void bin_flush(uint32_t (*stage)[kStageCap], const uint32_t* s_fillw,
+                                          uint32_t* s_cnt, uint32_t* s_gbase,
+                                          const uint32_t* s_cap, const uint32_t* s_qbase,
+                                          int wave, int lane, int nb, int nba, int G, int xs,
+                                          const BinArgs& a)
+{
+    const uint32_t my = s_fillw[wave];
+    for (uint32_t k = lane; k < my; k += kWave) {
+        const uint32_t e = stage[wave][k];
+        const uint32_t pc = e & 0xFFFFFFu;
+        const uint32_t b = brick_of(pc, nba);
+        stage[wave][k] = (b << 23) | ((e >> 24) << 15) | local_of(pc);
+        atomicAdd(&s_cnt[b], 1u);
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < nb; b += kBinThreads) {
+        const uint32_t c = s_cnt[b];
+        if (c)
+            s_gbase[b] = atomicAdd(a.fill + xs * kMaxBricks + b, c);
+        s_cnt[b] = 0;
+    }
+    __syncthreads();
+    for (uint32_t k = lane; k < my; k += kWave) {
+        const uint32_t e = stage[wave][k];
+        const uint32_t b = e >> 23;
+        const uint32_t q = e & 0x7FFFFFu;
+        const uint32_t slot = s_gbase[b] + atomicAdd(&s_cnt[b], 1u);
+        if (slot < s_cap[b]) {
+            a.pool[(uint64_t)s_qbase[b] + slot] = q;
+        } else {
+            atomicAdd(a.ovf + global_of(b, q & 0x7FFFu, nba, G), (int32_t)(q >> 15));
+            a.flags[b] = 1u;
+        }
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < nb; b += kBinThreads)
+        s_cnt[b] = 0;
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(kBinThreads, 2) void k_vote_bin(const float* __restrict__ x,
+                                                              const float* __restrict__ y,
+                                                              int64_t n, int G, float H, float gm,
+                                                              int J, const float2* __restrict__ table,
+                                                              int nba, BinArgs a)
+{
+    __shared__ uint32_t stage[kBinWaves][kStageCap];
+    __shared__ uint32_t s_cnt[kMaxBricks];
+    __shared__ uint32_t s_gbase[kMaxBricks];
+    __shared__ uint32_t s_cap[kMaxBricks];
+    __shared__ uint32_t s_qbase[kMaxBricks];
+    // double-buffered by check parity: a wave that runs ahead writes the other
+    // half, so every wave reads the same counts and takes the same decision
+    __shared__ uint32_t s_fill[2][kBinWaves];
+    const int nb = nba * nba * nba;
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int xs = blockIdx.x & (kSets - 1);
+    for (int b = threadIdx.x; b < nb; b += kBinThreads) {
+        s_cnt[b] = 0;
+        s_cap[b] = a.cap[b];
+        s_qbase[b] = a.qbase[xs * kMaxBricks + b];
+    }
+    Quat u, v;
+    const bool ok = load_circle(x, y, n, (int64_t)blockIdx.x * kBinThreads + threadIdx.x, u, v);
+    const uint32_t inc = ok ? 1u : 0u;
+    uint32_t fill = 0;  // this wave's staged runs (wave-uniform)
+    uint32_t cur = 0xFFFFFFFFu;
+    uint32_t cnt = 0;
+    uint32_t* my_stage = stage[wave];
+    int parity = 0;
+
+    auto emit = [&](bool e) {
+        const uint64_t m = __ballot(e);
+        if (e) {
+            const uint32_t r = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                         __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+            my_stage[fill + r] = cur | (cnt << 24);
+        }
+        fill += (uint32_t)__popcll(m);
+    };
+
+    for (int jb = 0; jb < J; jb += kSplit) {
+        const int je = min(J, jb + kSplit);
+        for (int js = jb; js < je; js += kStep) {
+            for_samples<true>(u, v, table, js, min(je, js + kStep), H, gm, [&](const Cell& c, int) {
+                const uint32_t pc = packed_coords(c);
+                const bool change = pc != cur;
+                emit(change && cnt > 0);
+                cnt = change ? inc : cnt + inc;
+                cur = change ? pc : cur;
+            });
+            if (lane == 0)
+                s_fill[parity][wave] = fill;
+            __syncthreads();
+            bool need = false;
+#pragma unroll
+            for (int w = 0; w < kBinWaves; ++w)
+                need |= s_fill[parity][w] > (uint32_t)kFlushAt;
+            if (need) {
+                bin_flush(stage, s_fill[parity], s_cnt, s_gbase, s_cap, s_qbase, wave, lane, nb, nba,
+                          G, xs, a);
+                fill = 0;
+            }
+            parity ^= 1;
+        }
+        emit(cnt > 0);  // close every run at the block end
+        cur = 0xFFFFFFFFu;
+        cnt = 0;
+    }
+    if (lane == 0)
+        s_fill[parity][wave] = fill;
+    __syncthreads();
+    bool any = false;
+#pragma unroll
+    for (int w = 0; w < kBinWaves; ++w)
+        any |= s_fill[parity][w] > 0;
+    if (any)
+        bin_flush(stage, s_fill[parity], s_cnt, s_gbase, s_cap, s_qbase, wave, lane, nb, nba, G, xs,
+                  a);
+}
+
+// ----------------------------------------------------------- accumulate
+
+__global__ __launch_bounds__(kAccumThreads, 1) void k_brick_accum(BinArgs a, int G, int nba,
+                                                                   int32_t* __restrict__ grid,
+                                                                   uint64_t* __restrict__ partial)
+{
+    __shared__ uint32_t acc[kBrickCells];
+    __shared__ uint64_t lists[kAccumWaves][kWave];
+    const int b = blockIdx.x;
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int bx = b % nba, by = (b / nba) % nba, bz = b / (nba * nba);
+
+    uint4* acc4 = reinterpret_cast<uint4*>(acc);
+    for (int k = threadIdx.x; k < kBrickCells / 4; k += kAccumThreads)
+        acc4[k] = make_uint4(0u, 0u, 0u, 0u);
+    __syncthreads();
+
+    const uint32_t cap = a.cap[b];
+    for (int xs = 0; xs < kSets; ++xs) {
+        const uint32_t cnt = min(a.fill[xs * kMaxBricks + b], cap);
+        const uint32_t* q = a.pool + a.qbase[xs * kMaxBricks + b];
+        // queues start on 64-run boundaries and their capacity is a multiple
+        // of 64, so the vector loads stay inside the queue
+        for (uint32_t k = threadIdx.x * 4; k < cnt; k += kAccumThreads * 4) {
+            const uint4 r = *reinterpret_cast<const uint4*>(q + k);
+            atomicAdd(&acc[r.x & 0x7FFFu], r.x >> 15);
+            if (k + 1 < cnt) atomicAdd(&acc[r.y & 0x7FFFu], r.y >> 15);
+            if (k + 2 < cnt) atomicAdd(&acc[r.z & 0x7FFFu], r.z >> 15);
+            if (k + 3 < cnt) atomicAdd(&acc[r.w & 0x7FFFu], r.w >> 15);
+        }
+    }
+    __syncthreads();
+
+    const bool overflowed = a.flags[b] != 0u;
+    const bool vec = (G % 4) == 0;
+    uint64_t list = 0;
+    for (int c = threadIdx.x * 4; c < kBrickCells; c += kAccumThreads * 4) {
+        const int lx = c & 31, ly = (c >> 5) & 31, lz = c >> 10;
+        const int gx = bx * kEdge + lx, gy = by * kEdge + ly, gz = bz * kEdge + lz;
+        uint32_t val[4] = {0u, 0u, 0u, 0u};
+        uint32_t idx0 = 0;
+        const bool row = gy < G && gz < G;
+        if (row) {
+            const uint4 v4 = acc4[c >> 2];
+            val[0] = v4.x; val[1] = v4.y; val[2] = v4.z; val[3] = v4.w;
+            const int64_t g0 = ((int64_t)gz * G + gy) * G + gx;
+            idx0 = (uint32_t)g0;
+            if (overflowed) {
+#pragma unroll
+                for (int s = 0; s < 4; ++s)
+                    if (gx + s < G) {
+                        val[s] += (uint32_t)a.ovf[g0 + s];
+                        a.ovf[g0 + s] = 0;
+                    }
+            }
+            if (vec && gx + 3 < G) {
+                *reinterpret_cast<int4*>(grid + g0) =
+                    make_int4((int)val[0], (int)val[1], (int)val[2], (int)val[3]);
+            } else {
+#pragma unroll
+                for (int s = 0; s < 4; ++s)
+                    if (gx + s < G)
+                        grid[g0 + s] = (int32_t)val[s];
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const bool in = row && gx + s < G;
+            list = wave_insert(list, in ? cell_key(val[s], idx0 + s) : 0ull, lane);
+        }
+    }
+    list = block_merge<kAccumWaves>(list, lists, wave, lane);
+    if (wave == 0)
+        partial[(int64_t)b * kWave + lane] = list;
+}
+
+// ------------------------------------------------------------- launchers
+
+int brick_axis(int G) { return (G + kEdge - 1) / kEdge; }
+
+hipError_t launch_bin_prepare(const float* x, const float* y, int64_t n, int G, int J,
+                              const float2* table, const BinArgs& a, hipStream_t s)
+{
+    const int nba = brick_axis(G);
+    const int nb = nba * nba * nba;
+    if (G > kMaxBrickGrid || nb > kMaxBricks)
+        return hipErrorInvalidValue;
+    const float H = (float)G * 0.5f;
+    const float gm = (float)G - 0.5f;
+    if (n > 0) {
+        const int64_t nsamp = (n + kEstimateStride - 1) / kEstimateStride;
+        const int eblocks = (int)((nsamp + 255) / 256);
+        hipLaunchKernelGGL(k_bin_estimate, dim3(eblocks), dim3(256), 0, s, x, y, n, H, gm, J, table,
+                           nba, a.est);
+        if (hipError_t e = hipGetLastError(); e != hipSuccess)
+            return e;
+    }
+    hipLaunchKernelGGL(k_bin_plan, dim3(1), dim3(kMaxBricks), 0, s, a, nb);
+    return hipGetLastError();
+}
+
+hipError_t launch_bin_vote(const float* x, const float* y, int64_t n, int G, int J,
+                           const float2* table, const BinArgs& a, hipStream_t s)
+{
+    if (n <= 0)
+        return hipSuccess;
+    const int64_t blocks = (n + kBinThreads - 1) / kBinThreads;
+    if (blocks > INT32_MAX || G > kMaxBrickGrid)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_vote_bin, dim3((unsigned)blocks), dim3(kBinThreads), 0, s, x, y, n, G,
+                       (float)G * 0.5f, (float)G - 0.5f, J, table, brick_axis(G), a);
+    return hipGetLastError();
+}
+
+hipError_t launch_brick_accum(int G, int32_t* grid, uint64_t* partial, const BinArgs& a,
+                              hipStream_t s)
+{
+    const int nba = brick_axis(G);
+    const int nb = nba * nba * nba;
+    if (G > kMaxBrickGrid || nb > kMaxBricks)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_brick_accum, dim3(nb), dim3(kAccumThreads), 0, s, a, G, nba, grid, partial);
+    return hipGetLastError();
+}
+
+}  // namespace rv

@@ -106,8 +106,12 @@ __device__ __forceinline__ float recip_1_2(float d)
 // the cube [-1, 1]^3 at G steps per axis, x fastest.  The sign is folded into
 // the chart scale: fma(-q_c, rh, H) == fma(q_c, -rh, H) exactly, and
 // 1 + |w| is the canonical denominator in every case, w = -0 included.
+struct Cell {
+    unsigned x, y, z;
+};
+
 template <bool kFastRecip>
-__device__ __forceinline__ int cell_index(float qw, float qx, float qy, float qz, float H, int G)
+__device__ __forceinline__ Cell cell_coords(float qw, float qx, float qy, float qz, float H, float gm)
 {
     bool neg = qw < 0.0f;
     if (qw == 0.0f)
@@ -119,25 +123,97 @@ __device__ __forceinline__ int cell_index(float qw, float qx, float qy, float qz
     const float tx = __builtin_fmaf(qx, srh, H);
     const float ty = __builtin_fmaf(qy, srh, H);
     const float tz = __builtin_fmaf(qz, srh, H);
-    // floor-then-clamp to [0, G-1] equals truncate-then-clamp for every finite
-    // t: they differ only on (-1, 0), where both clamp to 0.
-    const int ix = min(max((int)tx, 0), G - 1);
-    const int iy = min(max((int)ty, 0), G - 1);
-    const int iz = min(max((int)tz, 0), G - 1);
-    return (iz * G + iy) * G + ix;
+    // clamp(floor(t), 0, G-1) == trunc(med3(t, 0, G - 1/2)) for every finite t:
+    // below 0 both give 0, on [0, G-1/2] trunc is floor, above both give G-1.
+    Cell c;
+    c.x = (unsigned)__builtin_amdgcn_fmed3f(tx, 0.0f, gm);
+    c.y = (unsigned)__builtin_amdgcn_fmed3f(ty, 0.0f, gm);
+    c.z = (unsigned)__builtin_amdgcn_fmed3f(tz, 0.0f, gm);
+    return c;
+}
+
+// Linear cell index, x fastest; G <= 1024 keeps every factor in 24 bits.
+__device__ __forceinline__ unsigned linear_index(const Cell& c, unsigned G)
+{
+    return __umul24(__umul24(c.z, G) + c.y, G) + c.x;
+}
+
+// Cell coordinates packed one byte each (G <= 256): a key that is unique per
+// cell and cheap to build and to take apart.
+__device__ __forceinline__ unsigned packed_coords(const Cell& c)
+{
+    return c.x | (c.y << 8) | (c.z << 16);
+}
+
+template <bool kFastRecip>
+__device__ __forceinline__ int cell_index(float qw, float qx, float qy, float qz, float H, float gm,
+                                          int G)
+{
+    return (int)linear_index(cell_coords<kFastRecip>(qw, qx, qy, qz, H, gm), (unsigned)G);
 }
 
 // Sample j of the circle: q = cos(theta_j) u + sin(theta_j) v, per component
 // fma(C, u_c, S * v_c) (Alg. 1, q(alpha) with theta = alpha / 2).
 template <bool kFastRecip>
-__device__ __forceinline__ int sample_cell(const Quat& u, const Quat& v, float C, float S, float H,
-                                           int G)
+__device__ __forceinline__ Cell sample_cell(const Quat& u, const Quat& v, float C, float S, float H,
+                                            float gm)
 {
     const float qw = __builtin_fmaf(C, u.w, S * v.w);
     const float qx = __builtin_fmaf(C, u.x, S * v.x);
     const float qy = __builtin_fmaf(C, u.y, S * v.y);
     const float qz = __builtin_fmaf(C, u.z, S * v.z);
-    return cell_index<kFastRecip>(qw, qx, qy, qz, H, G);
+    return cell_coords<kFastRecip>(qw, qx, qy, qz, H, gm);
+}
+
+// Calls f(cell, j) for the samples j in [ja, jb) of the circle (u, v).  The
+// (cos, sin) table index is wave-uniform, so the table is read with scalar
+// loads, eight entries at a time; ja must be a multiple of 8.
+template <bool kFastRecip, class F>
+__device__ __forceinline__ void for_samples(const Quat& u, const Quat& v,
+                                            const float2* __restrict__ table, int ja, int jb,
+                                            float H, float gm, F&& f)
+{
+    const float4* __restrict__ t4 = reinterpret_cast<const float4*>(table);
+    int j = ja;
+    for (; j + 8 <= jb; j += 8) {
+        const float4 c0 = t4[(j >> 1) + 0];
+        const float4 c1 = t4[(j >> 1) + 1];
+        const float4 c2 = t4[(j >> 1) + 2];
+        const float4 c3 = t4[(j >> 1) + 3];
+        f(sample_cell<kFastRecip>(u, v, c0.x, c0.y, H, gm), j + 0);
+        f(sample_cell<kFastRecip>(u, v, c0.z, c0.w, H, gm), j + 1);
+        f(sample_cell<kFastRecip>(u, v, c1.x, c1.y, H, gm), j + 2);
+        f(sample_cell<kFastRecip>(u, v, c1.z, c1.w, H, gm), j + 3);
+        f(sample_cell<kFastRecip>(u, v, c2.x, c2.y, H, gm), j + 4);
+        f(sample_cell<kFastRecip>(u, v, c2.z, c2.w, H, gm), j + 5);
+        f(sample_cell<kFastRecip>(u, v, c3.x, c3.y, H, gm), j + 6);
+        f(sample_cell<kFastRecip>(u, v, c3.z, c3.w, H, gm), j + 7);
+    }
+    for (; j < jb; ++j) {
+        const float2 cs = table[j];
+        f(sample_cell<kFastRecip>(u, v, cs.x, cs.y, H, gm), j);
+    }
+}
+
+// Loads correspondence i (if i < n) and builds its circle basis.  Unusable or
+// absent correspondences get the basis of a = b = e_x and report false.
+__device__ __forceinline__ bool load_circle(const float* __restrict__ x, const float* __restrict__ y,
+                                            int64_t n, int64_t i, Quat& u, Quat& v)
+{
+    float a[3] = {1.0f, 0.0f, 0.0f};
+    float b[3] = {1.0f, 0.0f, 0.0f};
+    bool ok = false;
+    if (i < n) {
+        const bool oka = load_unit(x, n, i, a);
+        const bool okb = load_unit(y, n, i, b);
+        ok = oka && okb;
+    }
+    if (!ok) {
+        a[0] = 1.0f; a[1] = 0.0f; a[2] = 0.0f;
+        b[0] = 1.0f; b[1] = 0.0f; b[2] = 0.0f;
+    }
+    circle_basis(a, b, u, v);
+    return ok;
 }
 
 __device__ __forceinline__ void canonical(Quat& q)

@@ -24,7 +24,7 @@ struct Candidates {
 };
 
 constexpr int kMaxTopK = 64;
-constexpr int kTopkMaxBlocks = 256;
+constexpr int kTopkMaxBlocks = 512;   // also the largest brick count
 
 hipError_t launch_fill(int32_t* p, int64_t count, int32_t value, hipStream_t s);
 
@@ -39,6 +39,33 @@ hipError_t launch_topk_partial(const int32_t* hist, int64_t ncell, int nblocks,
                                uint64_t* partial, hipStream_t s);
 hipError_t launch_topk_final(const uint64_t* partial, int nblocks, int K, int G,
                              const Candidates& c, hipStream_t s);
+
+// Brick-binned vote (G <= 256): estimate, plan, binned vote, brick accumulation.
+constexpr int kQueueSets = 8;        // one queue per brick per XCD
+constexpr int kMaxBricks = 512;      // (256 / 32)^3
+constexpr int kMaxBrickGrid = 256;   // cell coordinates packed in one byte each
+constexpr int kEstimateStride = 32;  // the estimate samples every 32nd correspondence
+
+struct BinArgs {
+    uint32_t* pool;      // run queues; entry = local cell | run length << 15
+    uint32_t* fill;      // [kQueueSets][kMaxBricks] runs appended per queue
+    uint32_t* qbase;     // [kQueueSets][kMaxBricks] first pool slot of each queue
+    uint32_t* cap;       // [kMaxBricks] capacity of each of the brick's queues
+    uint32_t* est;       // [kMaxBricks] estimated runs (sampled), zero between solves
+    uint32_t* flags;     // [kMaxBricks] set when a brick's queue overflowed
+    int32_t* ovf;        // G^3 overflow grid, zero between solves
+    uint64_t pool_runs;  // pool capacity in runs (< 2^32)
+};
+
+int brick_axis(int G);
+// estimate + plan (queue capacities); then the binned vote; then per-brick
+// accumulation, which writes every cell of the grid and one top-64 list per brick
+hipError_t launch_bin_prepare(const float* x, const float* y, int64_t n, int G, int J,
+                              const float2* table, const BinArgs& a, hipStream_t s);
+hipError_t launch_bin_vote(const float* x, const float* y, int64_t n, int G, int J,
+                           const float2* table, const BinArgs& a, hipStream_t s);
+hipError_t launch_brick_accum(int G, int32_t* grid, uint64_t* partial, const BinArgs& a,
+                              hipStream_t s);
 
 hipError_t launch_rescore(const float* x, const float* y, int64_t n, float T2,
                           const Candidates& c, hipStream_t s);

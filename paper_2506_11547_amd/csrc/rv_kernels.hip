@@ -7,6 +7,7 @@
 // The vote is scatter/count work, not a dense contraction, so no MFMA is used.
 #include "rv_device.h"
 #include "rv_internal.h"
+#include "rv_topk.h"
 
 namespace rv {
 
@@ -48,10 +49,9 @@ __device__ __forceinline__ void atomic_add_relaxed(int32_t* p, int32_t v)
 // samples of one circle usually fall in the same cell, so each lane merges
 // them into a run and adds the run length with one atomic when the cell
 // changes.  The sum over runs equals one vote per sample exactly.
-template <bool kFastRecip>
 __global__ __launch_bounds__(256) void k_vote_global(const float* __restrict__ x,
                                                      const float* __restrict__ y, int64_t n,
-                                                     int G, float H, int J, int chunk,
+                                                     int G, float H, float gm, int J, int chunk,
                                                      int ngroups, int nwaves,
                                                      const float2* __restrict__ table,
                                                      int32_t* __restrict__ hist)
@@ -64,29 +64,13 @@ __global__ __launch_bounds__(256) void k_vote_global(const float* __restrict__ x
     const int g = wave - c * ngroups;
     const int j0 = c * chunk;
     const int j1 = min(J, j0 + chunk);
-    const int64_t i = (int64_t)g * kWave + lane;
-
-    float a[3], b[3];
-    bool ok = false;
-    if (i < n) {
-        const bool oka = load_unit(x, n, i, a);
-        const bool okb = load_unit(y, n, i, b);
-        ok = oka && okb;
-    }
-    if (!ok) {
-        a[0] = 1.0f; a[1] = 0.0f; a[2] = 0.0f;
-        b[0] = 1.0f; b[1] = 0.0f; b[2] = 0.0f;
-    }
-    const int inc = ok ? 1 : 0;
     Quat u, v;
-    circle_basis(a, b, u, v);
-
-    int cur = 0;
+    const bool ok = load_circle(x, y, n, (int64_t)g * kWave + lane, u, v);
+    const int inc = ok ? 1 : 0;
+    unsigned cur = 0xFFFFFFFFu;
     int cnt = 0;
-#pragma unroll 4
-    for (int j = j0; j < j1; ++j) {
-        const float2 cs = table[j];
-        const int idx = sample_cell<kFastRecip>(u, v, cs.x, cs.y, H, G);
+    for_samples<true>(u, v, table, j0, j1, H, gm, [&](const Cell& cell, int) {
+        const unsigned idx = linear_index(cell, (unsigned)G);
         if (idx != cur) {
             if (cnt > 0)
                 atomic_add_relaxed(hist + cur, cnt);
@@ -94,7 +78,7 @@ __global__ __launch_bounds__(256) void k_vote_global(const float* __restrict__ x
             cnt = 0;
         }
         cnt += inc;
-    }
+    });
     if (cnt > 0)
         atomic_add_relaxed(hist + cur, cnt);
 }
@@ -104,8 +88,10 @@ hipError_t launch_vote_global(const float* x, const float* y, int64_t n, int G, 
 {
     if (n <= 0 || J <= 0)
         return hipSuccess;
-    if (chunk <= 0 || chunk > J)
+    if (chunk <= 0 || chunk >= J)
         chunk = J;
+    else
+        chunk = (chunk + 7) & ~7;  // sample chunks start on table rows of 8
     const int64_t ngroups = (n + kWave - 1) / kWave;
     const int64_t nchunks = (J + chunk - 1) / chunk;
     const int64_t nwaves = ngroups * nchunks;
@@ -113,107 +99,19 @@ hipError_t launch_vote_global(const float* x, const float* y, int64_t n, int G, 
         return hipErrorInvalidValue;
     const int blocks = (int)((nwaves + 3) / 4);
     const float H = (float)G * 0.5f;
-    hipLaunchKernelGGL(k_vote_global<false>, dim3(blocks), dim3(256), 0, s, x, y, n, G, H, J,
-                       chunk, (int)ngroups, (int)nwaves, table, hist);
+    const float gm = (float)G - 0.5f;
+    hipLaunchKernelGGL(k_vote_global, dim3(blocks), dim3(256), 0, s, x, y, n, G, H, gm, J, chunk,
+                       (int)ngroups, (int)nwaves, table, hist);
     return hipGetLastError();
 }
 
 // -------------------------------------------------------------------- top-K
 //
-// Keys pack (count, index) so that one unsigned compare orders cells by count
-// descending, then index ascending: key = count << 32 | (0xFFFFFFFF - idx).
-// Empty cells have key 0 and are never candidates.  Each wave keeps its best
-// 64 keys sorted descending across its 64 lanes; a batch of 64 new keys is
-// skipped unless one beats the current 64th key, else it is bitonic-sorted
-// and merged in (max against the reversed batch, then a bitonic clean).
-
-__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m)
-{
-    const int lo = __shfl_xor((int)(uint32_t)v, m);
-    const int hi = __shfl_xor((int)(uint32_t)(v >> 32), m);
-    return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
-}
-
-__device__ __forceinline__ uint64_t shfl_u64(uint64_t v, int src)
-{
-    const int lo = __shfl((int)(uint32_t)v, src);
-    const int hi = __shfl((int)(uint32_t)(v >> 32), src);
-    return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
-}
-
-__device__ __forceinline__ uint64_t lane_u64(uint64_t v, int src)
-{
-    const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)v, src);
-    const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), src);
-    return ((uint64_t)hi << 32) | lo;
-}
-
-__device__ __forceinline__ uint64_t umax64(uint64_t a, uint64_t b) { return a > b ? a : b; }
-__device__ __forceinline__ uint64_t umin64(uint64_t a, uint64_t b) { return a < b ? a : b; }
-
-__device__ __forceinline__ uint64_t wave_sort_desc(uint64_t key, int lane)
-{
-#pragma unroll
-    for (int k = 2; k <= kWave; k <<= 1) {
-#pragma unroll
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            const uint64_t o = shfl_xor_u64(key, j);
-            const bool keep_max = ((lane & j) == 0) == ((lane & k) == 0);
-            key = keep_max ? umax64(key, o) : umin64(key, o);
-        }
-    }
-    return key;
-}
-
-// list and batch both sorted descending; returns the best 64 of both, sorted.
-__device__ __forceinline__ uint64_t wave_merge_sorted(uint64_t list, uint64_t batch, int lane)
-{
-    uint64_t t = umax64(list, shfl_u64(batch, kWave - 1 - lane));
-#pragma unroll
-    for (int j = kWave / 2; j > 0; j >>= 1) {
-        const uint64_t o = shfl_xor_u64(t, j);
-        t = ((lane & j) == 0) ? umax64(t, o) : umin64(t, o);
-    }
-    return t;
-}
-
-__device__ __forceinline__ uint64_t wave_insert(uint64_t list, uint64_t key, int lane)
-{
-    const uint64_t thr = lane_u64(list, kWave - 1);
-    if (__ballot(key > thr) == 0)
-        return list;
-    return wave_merge_sorted(list, wave_sort_desc(key, lane), lane);
-}
-
-__device__ __forceinline__ uint64_t wave_insert_sorted(uint64_t list, uint64_t sorted, int lane)
-{
-    const uint64_t thr = lane_u64(list, kWave - 1);
-    if (__ballot(sorted > thr) == 0)
-        return list;
-    return wave_merge_sorted(list, sorted, lane);
-}
-
-__device__ __forceinline__ uint64_t cell_key(int32_t count, int64_t idx)
-{
-    return count > 0 ? (((uint64_t)(uint32_t)count << 32) | (uint32_t)(0xFFFFFFFFu - (uint32_t)idx))
-                     : 0ull;
-}
+// Per-block sorted top-64 lists over disjoint parts of the grid, then one
+// block merges the lists, decodes the K best cells and clears their counters.
 
 constexpr int kTopkThreads = 1024;
 constexpr int kTopkWaves = kTopkThreads / kWave;
-
-// Merges the block's per-wave lists (in lists[]) into wave 0's register list.
-__device__ __forceinline__ uint64_t block_merge(uint64_t list, uint64_t (*lists)[kWave], int wave,
-                                                int lane)
-{
-    lists[wave][lane] = list;
-    __syncthreads();
-    if (wave == 0) {
-        for (int w = 1; w < kTopkWaves; ++w)
-            list = wave_insert_sorted(list, lists[w][lane], lane);
-    }
-    return list;
-}
 
 __global__ __launch_bounds__(kTopkThreads) void k_topk_partial(const int32_t* __restrict__ hist,
                                                                int64_t ncell,
@@ -240,7 +138,7 @@ __global__ __launch_bounds__(kTopkThreads) void k_topk_partial(const int32_t* __
         uint64_t k[4];
 #pragma unroll
         for (int s = 0; s < 4; ++s)
-            k[s] = cell_key(h[s], base + s);
+            k[s] = h[s] > 0 ? cell_key((uint32_t)h[s], (uint32_t)(base + s)) : 0ull;
         const uint64_t thr = lane_u64(list, kWave - 1);
         const bool any = (k[0] > thr) | (k[1] > thr) | (k[2] > thr) | (k[3] > thr);
         if (__ballot(any) != 0) {
@@ -249,7 +147,7 @@ __global__ __launch_bounds__(kTopkThreads) void k_topk_partial(const int32_t* __
                 list = wave_insert(list, k[s], lane);
         }
     }
-    list = block_merge(list, lists, wave, lane);
+    list = block_merge<kTopkWaves>(list, lists, wave, lane);
     if (wave == 0)
         partial[(int64_t)blockIdx.x * kWave + lane] = list;
 }
@@ -277,9 +175,19 @@ __global__ __launch_bounds__(kTopkThreads) void k_topk_final(const uint64_t* __r
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     uint64_t list = 0;
-    for (int b = wave; b < nblocks; b += kTopkWaves)
-        list = wave_insert_sorted(list, partial[(int64_t)b * kWave + lane], lane);
-    list = block_merge(list, lists, wave, lane);
+    // eight lists in flight per wave, so the merge does not wait on each load
+    for (int b0 = wave; b0 < nblocks; b0 += kTopkWaves * 8) {
+        uint64_t pre[8];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const int b = b0 + r * kTopkWaves;
+            pre[r] = b < nblocks ? partial[(int64_t)b * kWave + lane] : 0ull;
+        }
+#pragma unroll
+        for (int r = 0; r < 8; ++r)
+            list = wave_insert_sorted(list, pre[r], lane);
+    }
+    list = block_merge<kTopkWaves>(list, lists, wave, lane);
     if (wave != 0)
         return;
     const bool valid = lane < K && list != 0;

@@ -44,7 +44,7 @@ __global__ void k_cells(const float* q, int64_t n, int G, int* out)
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n)
         out[i] = rv::cell_index<kFast>(q[4 * i], q[4 * i + 1], q[4 * i + 2], q[4 * i + 3],
-                                       (float)G * 0.5f, G);
+                                       (float)G * 0.5f, (float)G - 0.5f, G);
 }
 
 __global__ void k_decode(const int* idx, int64_t n, int G, float* q)

@@ -27,7 +27,7 @@ STRATEGY_NAMES = {v: k for k, v in STRATEGIES.items()}
 FLAG_TIMING = 1
 MAX_TOPK = 64
 NUM_STAGES = 6
-STAGE_NAMES = ("clear", "vote", "topk_partial", "topk_final", "rescore", "mask")
+STAGE_NAMES = ("prepare", "vote", "reduce", "topk", "rescore", "mask")
 
 # Names the C header declares; the CPU test suite checks the library exports each.
 EXPORTS = ("rot_vote_default_config", "rot_vote_create", "rot_vote_destroy",

@@ -79,28 +79,77 @@ def test_small_workload_matches_golden_and_oracle(rv, orc):
     assert g["plan"]["samples_per_circle"] == w.samples
 
 
+STRATEGIES = ["global", "brick"]
+
+
+@pytest.mark.parametrize("strategy", STRATEGIES)
 @pytest.mark.parametrize("G,J,n,K", [(1, 5, 33, 4), (2, 7, 100, 8), (3, 16, 65, 64),
                                      (5, 33, 129, 16), (7, 100, 1000, 64), (16, 64, 777, 10),
-                                     (31, 250, 4097, 16), (64, 512, 3000, 16),
-                                     (100, 801, 2000, 33), (128, 1024, 5000, 64)])
-def test_random_shapes(rv, orc, G, J, n, K):
+                                     (31, 250, 4097, 16), (33, 241, 1500, 8),
+                                     (64, 512, 3000, 16), (100, 801, 2000, 33),
+                                     (128, 1024, 5000, 64), (250, 300, 3001, 64),
+                                     (256, 2048, 1000, 64)])
+def test_random_shapes(rv, orc, G, J, n, K, strategy):
     inst = datagen.make_instance(n, 0.7, 1.0, 1000 + G, radii=(0.3, 3.0))
     eps = 2.0
-    g = run_gpu(rv, inst.x, inst.y, G, J, eps, K)
+    g = run_gpu(rv, inst.x, inst.y, G, J, eps, K, strategy)
+    assert g["plan"]["strategy"] == strategy
     o = orc.solve(inst.x, inst.y, G, J, eps_rad(rv, eps), K)
     check_parity(g, o, G)
 
 
-def test_medium_workload(rv, orc):
+@pytest.mark.parametrize("strategy", STRATEGIES)
+def test_medium_workload(rv, orc, strategy):
     w, inst = datagen.make_workload("medium")
-    g = run_gpu(rv, inst.x, inst.y, w.grid, w.samples, w.eps_deg, w.topk)
+    g = run_gpu(rv, inst.x, inst.y, w.grid, w.samples, w.eps_deg, w.topk, strategy)
     o = orc.solve(inst.x, inst.y, w.grid, w.samples, eps_rad(rv, w.eps_deg), w.topk,
                   nthreads=oracle.threads())
     check_parity(g, o, w.grid)
     assert datagen.rotation_error_deg(g["q"], inst.q_gt) < 4 * math.sqrt(3) / w.grid * 180 / math.pi + 1.5
 
 
-def test_degenerate_and_unusable_inputs(rv, orc):
+def test_large_workload_full_parity(rv, orc):
+    """The headline solve (N = 1e6, 99 % outliers, G = 256, J = 2048, K = 64)
+    in the configuration the benchmark times, against the oracle in full."""
+    w, inst = datagen.make_workload("large")
+    g = run_gpu(rv, inst.x, inst.y, w.grid, w.samples, w.eps_deg, w.topk)
+    assert g["plan"]["strategy"] == "brick"
+    o = orc.solve(inst.x, inst.y, w.grid, w.samples, eps_rad(rv, w.eps_deg), w.topk,
+                  nthreads=oracle.threads())
+    check_parity(g, o, w.grid)
+    assert datagen.rotation_error_deg(g["q"], inst.q_gt) < 1.5
+
+
+def test_auto_strategy_choice(rv):
+    inst = datagen.make_instance(2000, 0.5, 1.0, 11)
+    for G, want in ((8, "global"), (64, "global"), (72, "brick"), (128, "brick"), (256, "brick")):
+        g = run_gpu(rv, inst.x, inst.y, G, 8 * G, 1.0, 8)
+        assert g["plan"]["strategy"] == want, G
+
+
+def test_brick_queue_overflow_is_exact(rv, orc):
+    """Queue capacities come from every 32nd correspondence; here all the
+    others are one repeated correspondence, so its bricks overflow and their
+    excess runs take the atomic overflow path.  The histogram must not change."""
+    n = 64 * 256
+    r = np.random.default_rng(9)
+    x = r.normal(size=(3, n)).astype(np.float32)
+    y = r.normal(size=(3, n)).astype(np.float32)
+    rep = np.arange(n) % 32 != 0
+    x[:, rep] = np.float32([[0.3], [-0.5], [0.8]])
+    y[:, rep] = np.float32([[0.9], [0.1], [-0.2]])
+    G, J = 128, 1024
+    o = orc.solve(x, y, G, J, eps_rad(rv, 1.0), 16, nthreads=oracle.threads())
+    with rv.Solver(max_n=n, max_grid=G, topk=16, samples_per_circle=J, strategy="brick") as s:
+        for _ in range(2):  # the overflow grid must be left zeroed for the next solve
+            q, cnt, mask = s.solve(dev(x), dev(y), G, 1.0)
+            g = dict(q=np.array(q, np.float32), count=cnt, mask=mask.cpu().numpy(),
+                     hist=s.histogram().cpu().numpy(), top=s.topk(), plan=s.plan())
+            check_parity(g, o, G)
+
+
+@pytest.mark.parametrize("strategy", STRATEGIES)
+def test_degenerate_and_unusable_inputs(rv, orc, strategy):
     r = np.random.default_rng(5)
     n = 700
     x = r.normal(size=(3, n))
@@ -115,29 +164,31 @@ def test_degenerate_and_unusable_inputs(rv, orc):
     x[:, 250:260] = [[3e-39], [1e-39], [0]]
     x, y = x.astype(np.float32), y.astype(np.float32)
     for G in (8, 64):
-        g = run_gpu(rv, x, y, G, 8 * G, 3.0, 16)
+        g = run_gpu(rv, x, y, G, 8 * G, 3.0, 16, strategy)
         o = orc.solve(x, y, G, 8 * G, eps_rad(rv, 3.0), 16)
         check_parity(g, o, G)
 
 
-def test_all_unusable_and_empty(rv):
+@pytest.mark.parametrize("strategy", STRATEGIES)
+def test_all_unusable_and_empty(rv, strategy):
     n = 100
     x = np.zeros((3, n), np.float32)
     y = np.ones((3, n), np.float32)
-    g = run_gpu(rv, x, y, 16, 128, 1.0, 8)
+    g = run_gpu(rv, x, y, 16, 128, 1.0, 8, strategy)
     assert g["count"] == 0 and g["hist"].sum() == 0
     assert g["q"].tolist() == [1.0, 0.0, 0.0, 0.0]
     assert not g["mask"].any() and g["top"]["winner"] == -1
-    with rv.Solver(max_n=10, max_grid=16, topk=4) as s:
+    with rv.Solver(max_n=10, max_grid=16, topk=4, strategy=strategy) as s:
         e = torch.empty(3, 0, dtype=torch.float32, device="cuda")
         q, cnt, mask = s.solve(e, e, 16, 1.0)
         assert q == [1.0, 0.0, 0.0, 0.0] and cnt == 0 and mask.numel() == 0
         assert int(s.histogram().sum()) == 0
 
 
-def test_noise_free_recovers_rotation_exactly_in_cell(rv, orc):
+@pytest.mark.parametrize("strategy", STRATEGIES)
+def test_noise_free_recovers_rotation_exactly_in_cell(rv, orc, strategy):
     inst = datagen.make_instance(5000, 0.0, 0.0, 77)
-    g = run_gpu(rv, inst.x, inst.y, 64, 512, 0.5, 16)
+    g = run_gpu(rv, inst.x, inst.y, 64, 512, 0.5, 16, strategy)
     o = orc.solve(inst.x, inst.y, 64, 512, eps_rad(rv, 0.5), 16)
     check_parity(g, o, 64)
     ic_gt = orc.cell_of(np.float32(inst.q_gt), 64)[3]
