@@ -122,6 +122,7 @@ void release(rv_handle* h)
     (void)hipFree(h->bin.cap);
     (void)hipFree(h->bin.est);
     (void)hipFree(h->bin.flags);
+    (void)hipFree(h->bin.order);
     (void)hipFree(h->d_ovf);
     (void)hipHostFree(h->h_result);
     (void)hipHostFree(h->h_table);
@@ -252,6 +253,7 @@ RV_API rv_status rot_vote_create(rv_handle** out, const rv_config* cfg)
             (e = hipMalloc(&h->bin.cap, rv::kMaxBricks * sizeof(uint32_t))) != hipSuccess ||
             (e = hipMalloc(&h->bin.est, rv::kMaxBricks * sizeof(uint32_t))) != hipSuccess ||
             (e = hipMalloc(&h->bin.flags, rv::kMaxBricks * sizeof(uint32_t))) != hipSuccess ||
+            (e = hipMalloc(&h->bin.order, rv::kMaxBricks * sizeof(uint32_t))) != hipSuccess ||
             (e = hipMalloc(&h->d_ovf, ncell * sizeof(int32_t))) != hipSuccess)
             return bail(e, "brick scratch");
         if ((e = hipMemset(h->bin.est, 0, rv::kMaxBricks * sizeof(uint32_t))) != hipSuccess ||

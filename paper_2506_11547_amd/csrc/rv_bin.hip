@@ -36,6 +36,9 @@ constexpr int kSplit = 240;      // runs are cut every 240 samples: counts fit 8
 // flush before a step could overflow a wave's staging: one step adds at most
 // kWave * kStep runs and a run-block boundary at most kWave more.
 constexpr int kFlushAt = kStageCap - kWave * kStep - kWave;
+// Marks a dropped zero-length staged run.  A rewritten entry never equals it:
+// its length field (bits 15..22) is at most 240, never 0xFF.
+constexpr uint32_t kDropped = 0xFFFFFFFFu;
 constexpr int kAccumThreads = 1024;
 constexpr int kAccumWaves = kAccumThreads / kWave;
 
@@ -64,10 +67,16 @@ __device__ __forceinline__ int64_t global_of(uint32_t b, uint32_t loc, int nba, 
 
 // ------------------------------------------------------------- estimate
 
+// Runs per brick of every kEstimateStride-th correspondence.  One wave per
+// (64 sampled correspondences, chunk of kEstChunk samples), so the table
+// index stays wave-uniform and the work spreads over the whole GPU.
+constexpr int kEstChunk = 256;
+
 __global__ __launch_bounds__(256) void k_bin_estimate(const float* __restrict__ x,
                                                       const float* __restrict__ y, int64_t n,
                                                       float H, float gm, int J,
                                                       const float2* __restrict__ table, int nba,
+                                                      int ngroups, int nwaves,
                                                       uint32_t* __restrict__ est)
 {
     __shared__ uint32_t s_est[kMaxBricks];
@@ -75,21 +84,21 @@ __global__ __launch_bounds__(256) void k_bin_estimate(const float* __restrict__ 
     for (int b = threadIdx.x; b < nb; b += 256)
         s_est[b] = 0;
     __syncthreads();
-    const int64_t i = ((int64_t)blockIdx.x * 256 + threadIdx.x) * kEstimateStride;
-    Quat u, v;
-    const bool ok = load_circle(x, y, n, i, u, v);
-    if (ok) {
-        for (int jb = 0; jb < J; jb += kSplit) {
-            uint32_t cur = 0xFFFFFFFFu;
-            // samples of one lane only: the loop bounds are uniform, the body divergent-free
-            for_samples<true>(u, v, table, jb, min(J, jb + kSplit), H, gm, [&](const Cell& c, int) {
-                const uint32_t pc = packed_coords(c);
-                if (pc != cur) {
-                    atomicAdd(&s_est[brick_of(pc, nba)], 1u);
-                    cur = pc;
-                }
-            });
-        }
+    const int wave = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
+    if (wave < nwaves) {
+        const int c = wave / ngroups;
+        const int g = wave - c * ngroups;
+        const int64_t i = ((int64_t)g * kWave + (threadIdx.x & 63)) * kEstimateStride;
+        Quat u, v;
+        const bool ok = load_circle(x, y, n, i, u, v);
+        uint32_t cur = 0xFFFFFFFFu;
+        for_samples<true>(u, v, table, c * kEstChunk, min(J, (c + 1) * kEstChunk), H, gm,
+                          [&](const Cell& cell, int) {
+                              const uint32_t pc = packed_coords(cell);
+                              if (ok && pc != cur)
+                                  atomicAdd(&s_est[brick_of(pc, nba)], 1u);
+                              cur = pc;
+                          });
     }
     __syncthreads();
     for (int b = threadIdx.x; b < nb; b += 256)
@@ -107,6 +116,7 @@ __global__ __launch_bounds__(kMaxBricks) void k_bin_plan(BinArgs a, int nb)
 {
     __shared__ uint64_t s_scan[kMaxBricks];
     __shared__ uint64_t s_total;
+    __shared__ uint64_t s_sort[kMaxBricks];
     const int b = threadIdx.x;
     uint64_t capq = 0;
     if (b < nb) {
@@ -146,6 +156,25 @@ __global__ __launch_bounds__(kMaxBricks) void k_bin_plan(BinArgs a, int nb)
         excl = s_scan[b] - capq;
         total = s_total * kSets;
     }
+    // accumulation order: heaviest bricks first (bitonic sort of cap << 16 | b)
+    s_sort[b] = b < nb ? ((capq << 16) | (uint64_t)b) : 0ull;
+    __syncthreads();
+    for (int k = 2; k <= kMaxBricks; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            const int o = b ^ j;
+            if (o > b) {
+                const uint64_t p = s_sort[b], q = s_sort[o];
+                const bool desc = (b & k) == 0;
+                if (desc ? (p < q) : (p > q)) {
+                    s_sort[b] = q;
+                    s_sort[o] = p;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    if (b < nb)
+        a.order[b] = (uint32_t)(s_sort[b] & 0xFFFFu);
     if (b < nb) {
         a.cap[b] = (uint32_t)capq;
         for (int xs = 0; xs < kSets; ++xs) {
@@ -172,6 +201,10 @@ __device__ __forceinline__ void bin_flush(uint32_t (*stage)[kStageCap], const ui
     const uint32_t my = s_fillw[wave];
     for (uint32_t k = lane; k < my; k += kWave) {
         const uint32_t e = stage[wave][k];
+        if ((e >> 24) == 0u) {
+            stage[wave][k] = kDropped;
+            continue;
+        }
         const uint32_t pc = e & 0xFFFFFFu;
         const uint32_t b = brick_of(pc, nba);
         stage[wave][k] = (b << 23) | ((e >> 24) << 15) | local_of(pc);
@@ -187,6 +220,8 @@ __device__ __forceinline__ void bin_flush(uint32_t (*stage)[kStageCap], const ui
     __syncthreads();
     for (uint32_t k = lane; k < my; k += kWave) {
         const uint32_t e = stage[wave][k];
+        if (e == kDropped)
+            continue;
         const uint32_t b = e >> 23;
         const uint32_t q = e & 0x7FFFFFu;
         const uint32_t slot = s_gbase[b] + atomicAdd(&s_cnt[b], 1u);
@@ -217,8 +252,9 @@ __global__ __launch_bounds__(kBinThreads, 2) void k_vote_bin(const float* __rest
     // double-buffered by check parity: a wave that runs ahead writes the other
     // half, so every wave reads the same counts and takes the same decision
     __shared__ uint32_t s_fill[2][kBinWaves];
+    __shared__ uint32_t s_dummy[kBinWaves][kWave];
     const int nb = nba * nba * nba;
-    const int wave = threadIdx.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
     const int xs = blockIdx.x & (kSets - 1);
     for (int b = threadIdx.x; b < nb; b += kBinThreads) {
@@ -228,20 +264,28 @@ __global__ __launch_bounds__(kBinThreads, 2) void k_vote_bin(const float* __rest
     }
     Quat u, v;
     const bool ok = load_circle(x, y, n, (int64_t)blockIdx.x * kBinThreads + threadIdx.x, u, v);
-    const uint32_t inc = ok ? 1u : 0u;
     uint32_t fill = 0;  // this wave's staged runs (wave-uniform)
-    uint32_t cur = 0xFFFFFFFFu;
-    uint32_t cnt = 0;
+    // The open run of each lane: its cell and length.  A run is emitted when
+    // the cell changes and at every run-block end, where its length restarts
+    // from 0; a block whose first sample leaves that cell emits a zero-length
+    // entry, which the flush drops.  The first run starts with a real cell of
+    // zero length for the same reason.
+    uint32_t cur = 0u;
+    uint32_t cnt = 0u;
     uint32_t* my_stage = stage[wave];
     int parity = 0;
 
-    auto emit = [&](bool e) {
-        const uint64_t m = __ballot(e);
-        if (e) {
-            const uint32_t r = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
-                                                         __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-            my_stage[fill + r] = cur | (cnt << 24);
-        }
+    // Branch-free emission: the ballot of the bare compare stays a scalar
+    // mask (usable lanes are masked in the scalar domain); lanes that do not
+    // emit store to a private dummy slot instead of taking a branch.
+    const uint64_t okmask = __builtin_amdgcn_ballot_w64(ok);
+    uint32_t* my_dummy = &s_dummy[wave][lane];
+    auto emit = [&](bool change) {
+        const uint64_t m = __builtin_amdgcn_ballot_w64(change) & okmask;
+        const uint32_t r = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+        const bool mine = change && ok;
+        *(mine ? (my_stage + fill + r) : my_dummy) = cur | (cnt << 24);
         fill += (uint32_t)__popcll(m);
     };
 
@@ -251,8 +295,8 @@ __global__ __launch_bounds__(kBinThreads, 2) void k_vote_bin(const float* __rest
             for_samples<true>(u, v, table, js, min(je, js + kStep), H, gm, [&](const Cell& c, int) {
                 const uint32_t pc = packed_coords(c);
                 const bool change = pc != cur;
-                emit(change && cnt > 0);
-                cnt = change ? inc : cnt + inc;
+                emit(change);
+                cnt = change ? 1u : cnt + 1u;
                 cur = change ? pc : cur;
             });
             if (lane == 0)
@@ -269,9 +313,8 @@ __global__ __launch_bounds__(kBinThreads, 2) void k_vote_bin(const float* __rest
             }
             parity ^= 1;
         }
-        emit(cnt > 0);  // close every run at the block end
-        cur = 0xFFFFFFFFu;
-        cnt = 0;
+        emit(true);  // close every run at the block end (run lengths stay below 256)
+        cnt = 0u;
     }
     if (lane == 0)
         s_fill[parity][wave] = fill;
@@ -293,7 +336,7 @@ __global__ __launch_bounds__(kAccumThreads, 1) void k_brick_accum(BinArgs a, int
 {
     __shared__ uint32_t acc[kBrickCells];
     __shared__ uint64_t lists[kAccumWaves][kWave];
-    const int b = blockIdx.x;
+    const int b = (int)a.order[blockIdx.x];
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     const int bx = b % nba, by = (b / nba) % nba, bz = b / (nba * nba);
@@ -304,17 +347,29 @@ __global__ __launch_bounds__(kAccumThreads, 1) void k_brick_accum(BinArgs a, int
     __syncthreads();
 
     const uint32_t cap = a.cap[b];
+    constexpr int kUnroll = 4;
+    constexpr uint32_t kStride = kAccumThreads * 4;
     for (int xs = 0; xs < kSets; ++xs) {
         const uint32_t cnt = min(a.fill[xs * kMaxBricks + b], cap);
         const uint32_t* q = a.pool + a.qbase[xs * kMaxBricks + b];
         // queues start on 64-run boundaries and their capacity is a multiple
         // of 64, so the vector loads stay inside the queue
-        for (uint32_t k = threadIdx.x * 4; k < cnt; k += kAccumThreads * 4) {
-            const uint4 r = *reinterpret_cast<const uint4*>(q + k);
-            atomicAdd(&acc[r.x & 0x7FFFu], r.x >> 15);
-            if (k + 1 < cnt) atomicAdd(&acc[r.y & 0x7FFFu], r.y >> 15);
-            if (k + 2 < cnt) atomicAdd(&acc[r.z & 0x7FFFu], r.z >> 15);
-            if (k + 3 < cnt) atomicAdd(&acc[r.w & 0x7FFFu], r.w >> 15);
+        for (uint32_t k0 = threadIdx.x * 4; k0 < cnt; k0 += kStride * kUnroll) {
+            uint4 r[kUnroll];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                const uint32_t k = k0 + u * kStride;
+                r[u] = k < cnt ? *reinterpret_cast<const uint4*>(q + k) : make_uint4(0u, 0u, 0u, 0u);
+            }
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                const uint32_t k = k0 + u * kStride;
+                // entries past cnt (and zero-length entries) add nothing
+                if (k < cnt) atomicAdd(&acc[r[u].x & 0x7FFFu], r[u].x >> 15);
+                if (k + 1 < cnt) atomicAdd(&acc[r[u].y & 0x7FFFu], r[u].y >> 15);
+                if (k + 2 < cnt) atomicAdd(&acc[r[u].z & 0x7FFFu], r[u].z >> 15);
+                if (k + 3 < cnt) atomicAdd(&acc[r[u].w & 0x7FFFu], r[u].w >> 15);
+            }
         }
     }
     __syncthreads();
@@ -377,9 +432,13 @@ hipError_t launch_bin_prepare(const float* x, const float* y, int64_t n, int G, 
     const float gm = (float)G - 0.5f;
     if (n > 0) {
         const int64_t nsamp = (n + kEstimateStride - 1) / kEstimateStride;
-        const int eblocks = (int)((nsamp + 255) / 256);
-        hipLaunchKernelGGL(k_bin_estimate, dim3(eblocks), dim3(256), 0, s, x, y, n, H, gm, J, table,
-                           nba, a.est);
+        const int64_t ngroups = (nsamp + kWave - 1) / kWave;
+        const int64_t nchunks = (J + kEstChunk - 1) / kEstChunk;
+        const int64_t nwaves = ngroups * nchunks;
+        if (nwaves > (int64_t)INT32_MAX - 4)
+            return hipErrorInvalidValue;
+        hipLaunchKernelGGL(k_bin_estimate, dim3((unsigned)((nwaves + 3) / 4)), dim3(256), 0, s, x,
+                           y, n, H, gm, J, table, nba, (int)ngroups, (int)nwaves, a.est);
         if (hipError_t e = hipGetLastError(); e != hipSuccess)
             return e;
     }

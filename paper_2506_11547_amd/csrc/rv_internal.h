@@ -44,7 +44,7 @@ hipError_t launch_topk_final(const uint64_t* partial, int nblocks, int K, int G,
 constexpr int kQueueSets = 8;        // one queue per brick per XCD
 constexpr int kMaxBricks = 512;      // (256 / 32)^3
 constexpr int kMaxBrickGrid = 256;   // cell coordinates packed in one byte each
-constexpr int kEstimateStride = 32;  // the estimate samples every 32nd correspondence
+constexpr int kEstimateStride = 64;  // the estimate samples every 64th correspondence
 
 struct BinArgs {
     uint32_t* pool;      // run queues; entry = local cell | run length << 15
@@ -53,6 +53,7 @@ struct BinArgs {
     uint32_t* cap;       // [kMaxBricks] capacity of each of the brick's queues
     uint32_t* est;       // [kMaxBricks] estimated runs (sampled), zero between solves
     uint32_t* flags;     // [kMaxBricks] set when a brick's queue overflowed
+    uint32_t* order;     // [kMaxBricks] bricks by decreasing capacity (accumulation order)
     int32_t* ovf;        // G^3 overflow grid, zero between solves
     uint64_t pool_runs;  // pool capacity in runs (< 2^32)
 };
