@@ -49,7 +49,23 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=150_000,
                     help="correspondences of the workload the CPU oracle times")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run plain device-to-device copies of MIB MiB (profiler "
+                         "calibration of the HBM byte counters) and exit")
     return ap.parse_args()
+
+
+def copy_calibration(mib: int):
+    """Plain copies of a known size: a profiler's byte counters for these
+    dispatches give the scale factor for the solve's kernels."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes": n * 4, "dispatches": 5}), flush=True)
 
 
 def cpu_baseline(w, inst, n_sample: int) -> dict:
@@ -73,6 +89,9 @@ def cpu_baseline(w, inst, n_sample: int) -> dict:
 
 def main():
     args = parse()
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (this build has no multi-GPU path); "
               f"got --gpus {args.gpus}", file=sys.stderr)

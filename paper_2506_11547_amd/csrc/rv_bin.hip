@@ -238,10 +238,13 @@ __device__ __forceinline__ void bin_flush(uint32_t (*stage)[kStageCap], const ui
     __syncthreads();
 }
 
+// One block per (512 correspondences, chunk of samples); chunks are whole run
+// blocks, so splitting J across blocks only adds run boundaries.
 __global__ __launch_bounds__(kBinThreads, 2) void k_vote_bin(const float* __restrict__ x,
                                                               const float* __restrict__ y,
                                                               int64_t n, int G, float H, float gm,
-                                                              int J, const float2* __restrict__ table,
+                                                              int J, int chunk, int ngroups,
+                                                              const float2* __restrict__ table,
                                                               int nba, BinArgs a)
 {
     __shared__ uint32_t stage[kBinWaves][kStageCap];
@@ -262,8 +265,12 @@ __global__ __launch_bounds__(kBinThreads, 2) void k_vote_bin(const float* __rest
         s_cap[b] = a.cap[b];
         s_qbase[b] = a.qbase[xs * kMaxBricks + b];
     }
+    const int cb = blockIdx.x / ngroups;
+    const int gb = blockIdx.x - cb * ngroups;
+    const int j0 = cb * chunk;
+    const int j1 = min(J, j0 + chunk);
     Quat u, v;
-    const bool ok = load_circle(x, y, n, (int64_t)blockIdx.x * kBinThreads + threadIdx.x, u, v);
+    const bool ok = load_circle(x, y, n, (int64_t)gb * kBinThreads + threadIdx.x, u, v);
     uint32_t fill = 0;  // this wave's staged runs (wave-uniform)
     // The open run of each lane: its cell and length.  A run is emitted when
     // the cell changes and at every run-block end, where its length restarts
@@ -289,8 +296,8 @@ __global__ __launch_bounds__(kBinThreads, 2) void k_vote_bin(const float* __rest
         fill += (uint32_t)__popcll(m);
     };
 
-    for (int jb = 0; jb < J; jb += kSplit) {
-        const int je = min(J, jb + kSplit);
+    for (int jb = j0; jb < j1; jb += kSplit) {
+        const int je = min(j1, jb + kSplit);
         for (int js = jb; js < je; js += kStep) {
             for_samples<true>(u, v, table, js, min(je, js + kStep), H, gm, [&](const Cell& c, int) {
                 const uint32_t pc = packed_coords(c);
@@ -347,29 +354,44 @@ __global__ __launch_bounds__(kAccumThreads, 1) void k_brick_accum(BinArgs a, int
     __syncthreads();
 
     const uint32_t cap = a.cap[b];
-    constexpr int kUnroll = 4;
+    // Software-pipelined queue reads: the next 8 KiB per wave are in flight
+    // while the current ones are added into LDS.  Queues start on 64-run
+    // boundaries and their capacity is a multiple of 64, so vector loads of
+    // 4 runs starting below the fill count stay inside the queue.
+    constexpr int kUnroll = 8;
     constexpr uint32_t kStride = kAccumThreads * 4;
     for (int xs = 0; xs < kSets; ++xs) {
         const uint32_t cnt = min(a.fill[xs * kMaxBricks + b], cap);
         const uint32_t* q = a.pool + a.qbase[xs * kMaxBricks + b];
-        // queues start on 64-run boundaries and their capacity is a multiple
-        // of 64, so the vector loads stay inside the queue
-        for (uint32_t k0 = threadIdx.x * 4; k0 < cnt; k0 += kStride * kUnroll) {
-            uint4 r[kUnroll];
+        if (cnt == 0)
+            continue;
+        // loads are unconditional (clamped to the queue's last vector) so the
+        // compiler can keep the next batch in flight across the LDS atomics
+        const uint32_t last = (cnt - 1u) & ~3u;
+        uint4 cur[kUnroll], nxt[kUnroll];
+        uint32_t k0 = threadIdx.x * 4;
+        auto load = [&](uint4 (&r)[kUnroll], uint32_t base) {
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u)
+                r[u] = *reinterpret_cast<const uint4*>(q + min(base + u * kStride, last));
+        };
+        load(cur, k0);
+        while (k0 < cnt) {
+            const uint32_t kn = k0 + kStride * kUnroll;
+            load(nxt, kn);
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
                 const uint32_t k = k0 + u * kStride;
-                r[u] = k < cnt ? *reinterpret_cast<const uint4*>(q + k) : make_uint4(0u, 0u, 0u, 0u);
+                // entries past cnt add nothing
+                if (k < cnt) atomicAdd(&acc[cur[u].x & 0x7FFFu], cur[u].x >> 15);
+                if (k + 1 < cnt) atomicAdd(&acc[cur[u].y & 0x7FFFu], cur[u].y >> 15);
+                if (k + 2 < cnt) atomicAdd(&acc[cur[u].z & 0x7FFFu], cur[u].z >> 15);
+                if (k + 3 < cnt) atomicAdd(&acc[cur[u].w & 0x7FFFu], cur[u].w >> 15);
             }
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u) {
-                const uint32_t k = k0 + u * kStride;
-                // entries past cnt (and zero-length entries) add nothing
-                if (k < cnt) atomicAdd(&acc[r[u].x & 0x7FFFu], r[u].x >> 15);
-                if (k + 1 < cnt) atomicAdd(&acc[r[u].y & 0x7FFFu], r[u].y >> 15);
-                if (k + 2 < cnt) atomicAdd(&acc[r[u].z & 0x7FFFu], r[u].z >> 15);
-                if (k + 3 < cnt) atomicAdd(&acc[r[u].w & 0x7FFFu], r[u].w >> 15);
-            }
+            for (int u = 0; u < kUnroll; ++u)
+                cur[u] = nxt[u];
+            k0 = kn;
         }
     }
     __syncthreads();
@@ -451,11 +473,20 @@ hipError_t launch_bin_vote(const float* x, const float* y, int64_t n, int G, int
 {
     if (n <= 0)
         return hipSuccess;
-    const int64_t blocks = (n + kBinThreads - 1) / kBinThreads;
+    const int64_t ngroups = (n + kBinThreads - 1) / kBinThreads;
+    // at least ~4 rounds of blocks over the GPU (2 resident per CU), by
+    // splitting J into whole run blocks when there are few correspondences
+    const int64_t want = 4 * 2 * 256;
+    const int64_t nblk = (J + kSplit - 1) / kSplit;
+    const int64_t split = std::max<int64_t>(1, std::min<int64_t>(nblk, want / ngroups));
+    const int chunk = (int)(((nblk + split - 1) / split) * kSplit);
+    const int64_t nchunks = (J + chunk - 1) / chunk;
+    const int64_t blocks = ngroups * nchunks;
     if (blocks > INT32_MAX || G > kMaxBrickGrid)
         return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_vote_bin, dim3((unsigned)blocks), dim3(kBinThreads), 0, s, x, y, n, G,
-                       (float)G * 0.5f, (float)G - 0.5f, J, table, brick_axis(G), a);
+                       (float)G * 0.5f, (float)G - 0.5f, J, chunk, (int)ngroups, table,
+                       brick_axis(G), a);
     return hipGetLastError();
 }
 

@@ -113,13 +113,15 @@ struct Cell {
 template <bool kFastRecip>
 __device__ __forceinline__ Cell cell_coords(float qw, float qx, float qy, float qz, float H, float gm)
 {
-    bool neg = qw < 0.0f;
-    if (qw == 0.0f)
-        neg = (qx != 0.0f) ? (qx < 0.0f) : ((qy != 0.0f) ? (qy < 0.0f) : (qz < 0.0f));
     const float den = 1.0f + __builtin_fabsf(qw);
     const float r = kFastRecip ? recip_1_2(den) : 1.0f / den;
     const float rh = r * H;
-    const float srh = neg ? -rh : rh;
+    // w != 0: the sign of w decides; w = +-0: the first nonzero of x, y, z
+    float srh = __builtin_copysignf(rh, qw);
+    if (qw == 0.0f) {
+        const bool neg = (qx != 0.0f) ? (qx < 0.0f) : ((qy != 0.0f) ? (qy < 0.0f) : (qz < 0.0f));
+        srh = neg ? -rh : rh;
+    }
     const float tx = __builtin_fmaf(qx, srh, H);
     const float ty = __builtin_fmaf(qy, srh, H);
     const float tz = __builtin_fmaf(qz, srh, H);
