@@ -68,6 +68,29 @@ def copy_calibration(mib: int):
     print(json.dumps({"copy_calibration_bytes": n * 4, "dispatches": 5}), flush=True)
 
 
+TRAFFIC_RECORD = ROOT / "profiles" / "vote_bin__large_traffic.json"
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per launch of the vote kernel from the committed FETCH_SIZE /
+    WRITE_SIZE profile (scaled by the copy calibration), or None when the
+    profile is of another workload or the kernel's sources changed since."""
+    import hashlib
+    try:
+        rec = json.loads(TRAFFIC_RECORD.read_text())
+    except (OSError, ValueError):
+        return None
+    if rec.get("workload") != workload:
+        return None
+    for path, digest in rec["sources_sha256"].items():
+        try:
+            if hashlib.sha256((ROOT / path).read_bytes()).hexdigest() != digest:
+                return None
+        except OSError:
+            return None
+    return float(rec["traffic_bytes_per_launch"])
+
+
 def cpu_baseline(w, inst, n_sample: int) -> dict:
     """The oracle, as it is, on the first n_sample correspondences."""
     import oracle
@@ -152,8 +175,9 @@ def main():
         "stage_ms": stage_ms,
         "roofline": {"bound": "alu", "kernel": "vote", "achieved": achieved / 1e3,
                      "peak": ALU_PEAK_GOPS / 1e3, "unit": "TOP/s", "frac": achieved / ALU_PEAK_GOPS,
-                     "traffic": None,
-                     "ops_per_sample": OPS_PER_SAMPLE, "samples_per_launch": samples},
+                     "traffic": measured_traffic(w.name) if plan["strategy"] == "brick" else None,
+                     "ops_per_sample": OPS_PER_SAMPLE, "samples_per_launch": samples,
+                     "vote_ms": stage_ms["vote"]},
         "result": {"q": q, "inliers": cnt, "e_R_deg": datagen.rotation_error_deg(q, inst.q_gt),
                    "winner": top["winner"], "true_inliers": int(inst.inlier.sum())},
     }
