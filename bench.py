@@ -9,6 +9,11 @@ Prints one JSON line.  ``value`` is circle-sample votes per second of the whole
 solve (N * J / seconds per solve); solves/s, the per-stage device times (HIP
 events recorded on the solve stream inside the timed region), the roofline of
 the dominant kernel and the CPU oracle's rate on a bounded sample ride along.
+
+``--workload batch`` times the batched solve instead: a step is one
+rot_vote_solve_batch over 4096 instances (N log-uniform on [100, 20000], G =
+64, J = 512), reported with the same fields plus the one-solve-per-call loop
+over the same instances.
 """
 from __future__ import annotations
 
@@ -49,6 +54,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=150_000,
                     help="correspondences of the workload the CPU oracle times")
+    ap.add_argument("--cpu-instances", type=int, default=1000,
+                    help="batch workload: instances the CPU oracle times")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run plain device-to-device copies of MIB MiB (profiler "
                          "calibration of the HBM byte counters) and exit")
@@ -68,7 +75,8 @@ def copy_calibration(mib: int):
     print(json.dumps({"copy_calibration_bytes": n * 4, "dispatches": 5}), flush=True)
 
 
-TRAFFIC_RECORD = ROOT / "profiles" / "vote_bin__large_traffic.json"
+TRAFFIC_RECORDS = {"large": ROOT / "profiles" / "vote_bin__large_traffic.json",
+                   "batch": ROOT / "profiles" / "vote_bin__batch_traffic.json"}
 
 
 def measured_traffic(workload: str):
@@ -77,8 +85,8 @@ def measured_traffic(workload: str):
     profile is of another workload or the kernel's sources changed since."""
     import hashlib
     try:
-        rec = json.loads(TRAFFIC_RECORD.read_text())
-    except (OSError, ValueError):
+        rec = json.loads(TRAFFIC_RECORDS[workload].read_text())
+    except (KeyError, OSError, ValueError):
         return None
     if rec.get("workload") != workload:
         return None
@@ -110,6 +118,117 @@ def cpu_baseline(w, inst, n_sample: int) -> dict:
                       f"OpenMP threads, top-K and rescoring single-threaded; {dt:.2f} s"}
 
 
+def cpu_baseline_batch(w, bt, max_instances: int) -> dict:
+    """The oracle, as it is, on the first instances of the batch."""
+    import oracle
+    o = oracle.get()
+    threads = oracle.threads()
+    eps = float(__import__("ctypes").c_float(w.eps_deg * math.pi / 180.0).value)
+    m = min(max_instances, bt.B)
+    t0 = time.perf_counter()
+    for b in range(m):
+        xb, yb = bt.instance(b)
+        o.solve(xb, yb, w.grid, w.samples, eps, w.topk, nthreads=threads)
+    dt = time.perf_counter() - t0
+    n = int(bt.offsets[m])
+    return {"value": n * w.samples / dt, "unit": "votes/s", "cores": threads, "kind": "oracle",
+            "solves_per_s": m / dt,
+            "sample": f"first {m} of the {bt.B} instances ({n} correspondences), one oracle "
+                      f"solve each; vote loop on {threads} OpenMP threads; {dt:.2f} s"}
+
+
+def run_batch(args):
+    import numpy as np
+    import torch
+
+    from paper_2506_11547_amd import datagen, rotvote
+
+    w = datagen.BATCH_WORKLOADS[args.workload]
+    bt = w.batch()
+    dev = torch.device("cuda", 0)
+    x = torch.from_numpy(bt.x).to(dev)
+    y = torch.from_numpy(bt.y).to(dev)
+    n = int(bt.offsets[-1])
+    mask = torch.empty(n, dtype=torch.bool, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    offs = bt.offsets.tolist()
+    solver = rotvote.Solver(device=0, max_n=n, max_grid=w.grid, topk=w.topk,
+                            samples_per_circle=w.samples, timing=True, stream=stream,
+                            max_batch=bt.B)
+    for _ in range(args.warmup):
+        solver.solve_batch(x, y, offs, w.grid, w.eps_deg, mask=mask)
+    stage = {k: 0.0 for k in rotvote.STAGE_NAMES}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        q, cnt, _ = solver.solve_batch(x, y, offs, w.grid, w.eps_deg, mask=mask)
+        for k, v in solver.timings().items():
+            stage[k] += v
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+
+    # The same instances one rot_vote_solve call each (one pass, after one
+    # untimed pass), on a handle made for single solves.
+    single = rotvote.Solver(device=0, max_n=int(np.diff(bt.offsets).max()), max_grid=w.grid,
+                            topk=w.topk, samples_per_circle=w.samples, stream=stream)
+    views = [(x[:, offs[b]:offs[b + 1]], y[:, offs[b]:offs[b + 1]], mask[offs[b]:offs[b + 1]])
+             for b in range(bt.B)]
+    for xb, yb, mb in views[:64]:
+        single.solve(xb, yb, w.grid, w.eps_deg, mask=mb)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    loop_same = 0
+    for b, (xb, yb, mb) in enumerate(views):
+        qb, cb, _ = single.solve(xb, yb, w.grid, w.eps_deg, mask=mb)
+        loop_same += int(qb == q[b] and cb == cnt[b])
+    torch.cuda.synchronize()
+    dt_loop = time.perf_counter() - t1
+    loop_plan = single.plan()
+    single.close()
+    solver.close()
+
+    steps = args.steps
+    samples = n * w.samples
+    stage_ms = {k: v / steps for k, v in stage.items()}
+    vote_s = stage_ms["vote"] * 1e-3
+    achieved = OPS_PER_SAMPLE * samples / vote_s / 1e9
+    err = [datagen.rotation_error_deg(q[b], bt.q_gt[b]) for b in range(bt.B)]
+    out = {
+        "metric": METRIC,
+        "value": samples / (dt / steps),
+        "unit": "votes/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt / steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "instances": bt.B, "n_total": n, "n_lo": w.n_lo,
+                   "n_hi": w.n_hi, "outlier_ratio": [w.rho_lo, w.rho_hi],
+                   "sigma_deg": w.sigma_deg, "grid": w.grid, "samples_per_circle": w.samples,
+                   "eps_deg": w.eps_deg, "topk": w.topk, "seed": w.seed,
+                   "vote_strategy": "brick (batched)"},
+        "solves_per_s": bt.B * steps / dt,
+        "stage_ms": stage_ms,
+        "loop": {"solves_per_s": bt.B / dt_loop, "votes_per_s": samples / dt_loop,
+                 "ms": dt_loop * 1e3, "vote_strategy": loop_plan["strategy"],
+                 "identical_results": loop_same, "speedup_of_batch": (bt.B * steps / dt) /
+                 (bt.B / dt_loop)},
+        "roofline": {"bound": "alu", "kernel": "vote (batched)", "achieved": achieved / 1e3,
+                     "peak": ALU_PEAK_GOPS / 1e3, "unit": "TOP/s", "frac": achieved / ALU_PEAK_GOPS,
+                     "traffic": measured_traffic(w.name), "ops_per_sample": OPS_PER_SAMPLE,
+                     "samples_per_launch": samples, "vote_ms": stage_ms["vote"]},
+        "result": {"median_e_R_deg": float(np.median(err)), "p99_e_R_deg": float(np.percentile(err, 99)),
+                   "inliers_total": int(sum(cnt))},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_batch(w, bt, args.cpu_instances)
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.copy_calibration:
@@ -119,10 +238,14 @@ def main():
         print(f"bench.py measures one GPU only (this build has no multi-GPU path); "
               f"got --gpus {args.gpus}", file=sys.stderr)
         sys.exit(2)
+    from paper_2506_11547_amd import datagen
+    if args.workload in datagen.BATCH_WORKLOADS:
+        run_batch(args)
+        return
     import numpy as np
     import torch
 
-    from paper_2506_11547_amd import datagen, rotvote
+    from paper_2506_11547_amd import rotvote
 
     w, inst = datagen.make_workload(args.workload)
     dev = torch.device("cuda", 0)

@@ -58,10 +58,11 @@ typedef enum rv_vote_strategy {
 } rv_vote_strategy;
 
 enum {
-    RV_FLAG_TIMING = 1u    /* record per-stage HIP events (rot_vote_get_timings) */
+    RV_FLAG_TIMING = 1u,       /* record per-stage HIP events (rot_vote_get_timings) */
+    RV_FLAG_BATCH_GRIDS = 2u   /* keep every batch instance's vote grid (test hook) */
 };
 
-enum { RV_MAX_TOPK = 64, RV_MAX_GRID = 1024, RV_NUM_STAGES = 6 };
+enum { RV_MAX_TOPK = 64, RV_MAX_GRID = 1024, RV_NUM_STAGES = 6, RV_MAX_BATCH_GRID = 64 };
 
 typedef struct rv_config {
     int32_t device;              /* HIP device ordinal */
@@ -72,11 +73,12 @@ typedef struct rv_config {
     int32_t topk;                /* K candidates rescored, 1..RV_MAX_TOPK */
     int32_t vote_strategy;       /* rv_vote_strategy */
     uint32_t flags;              /* RV_FLAG_* */
-    int32_t reserved[4];         /* must be 0 */
+    int32_t max_batch;           /* largest B of rot_vote_solve_batch (0: no batches) */
+    int32_t reserved[3];         /* must be 0 */
 } rv_config;
 
 /* Fills *cfg with: device 0, null stream, max_n 1<<20, max_grid 256, J = 8G,
- * K = 16, automatic vote strategy, no flags. */
+ * K = 16, automatic vote strategy, no flags, no batches. */
 void rot_vote_default_config(rv_config *cfg);
 
 /* Creates a handle on cfg->device and allocates all device scratch for the
@@ -111,6 +113,31 @@ rv_status rot_vote_set_stream(rv_handle *h, void *stream);
 rv_status rot_vote_solve(rv_handle *h, const float *x, const float *y, int64_t n, int32_t grid,
                          float eps_rad, float q_out[4], int64_t *inlier_count,
                          uint8_t *inlier_mask);
+
+/* Many independent solves in one pass (Alg. 1 and the rescoring for each
+ * instance; the instances share grid, J, K and eps).  Instance b is the
+ * column range [offsets[b], offsets[b+1]) of the SoA arrays x and y, which
+ * hold n = offsets[B] columns; each instance gets exactly the result a
+ * separate rot_vote_solve on its columns would give.
+ *   offsets       host int64[B+1], offsets[0] = 0, nondecreasing, offsets[B] <= max_n.
+ *   B             0..max_batch instances (0 is a no-op).
+ *   grid          1..min(max_grid, RV_MAX_BATCH_GRID).
+ *   q_out         host float[4*B]; inlier_count host int64[B];
+ *   inlier_mask   device uint8[offsets[B]].
+ * RV_EUNSUPPORTED if an instance's n*J exceeds 2^31-1 or the handle was
+ * created without batches (max_batch = 0) or with vote_strategy global.
+ * Synchronous on the handle's stream. */
+rv_status rot_vote_solve_batch(rv_handle *h, const float *x, const float *y, const int64_t *offsets,
+                               int32_t B, int32_t grid, float eps_rad, float *q_out,
+                               int64_t *inlier_count, uint8_t *inlier_mask);
+
+/* Test hook (RV_FLAG_BATCH_GRIDS): copies instance b's vote grid of the last
+ * batch to the device buffer dst (grid^3 int32). */
+rv_status rot_vote_get_batch_histogram(rv_handle *h, int32_t b, int32_t *dst_device);
+
+/* Test hook: instance b's candidates of the last batch, as rot_vote_get_topk. */
+rv_status rot_vote_get_batch_topk(rv_handle *h, int32_t b, int32_t *n_cand, int32_t *votes,
+                                  int32_t *cell_idx, int64_t *inliers, int32_t *winner);
 
 /* Test hook: copies the last solve's vote grid (G^3 int32, x fastest) to the
  * device buffer dst.  RV_EINVAL before the first solve. */

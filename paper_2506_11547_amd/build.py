@@ -39,7 +39,8 @@ def build(verbose: bool = False) -> list[Path]:
     """Build librotvote.so and librotvote_probe.so next to this file."""
     hipcc = _hipcc()
     jobs = [
-        (LIB, [CSRC / "rv_kernels.hip", CSRC / "rv_bin.hip", CSRC / "rv_api.cpp"]),
+        (LIB, [CSRC / "rv_kernels.hip", CSRC / "rv_bin.hip", CSRC / "rv_batch.hip",
+               CSRC / "rv_api.cpp"]),
         (PROBE_LIB, [CSRC / "rv_probe.hip"]),
     ]
     out = []

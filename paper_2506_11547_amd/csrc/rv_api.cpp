@@ -21,6 +21,18 @@ constexpr int kStages = RV_NUM_STAGES;
 // Below this grid the whole int32 grid (<= 1.4 MiB at 72^3) sits in every
 // XCD's L2 and run-coalesced atomics straight into it beat binning.
 constexpr int kBrickMinGrid = 72;
+// Batch queue capacities: a brick's share of the instance's expected runs,
+// times this factor (the heaviest brick of an instance with half inliers
+// holds about 1.75 shares at G = 64), plus a fixed slack.
+constexpr double kBatchCapFactor = 1.75;
+constexpr uint32_t kBatchCapSlack = 256;
+
+// Expected runs of one circle: about 1.7 G cell changes (at most J), plus
+// the cuts every 240 samples.
+int64_t runs_per_circle(int G, int J)
+{
+    return std::min<int64_t>(J, (int64_t)(1.7 * G) + J / 240 + 2);
+}
 
 std::string g_create_error;  // reason of the last failed create (NULL handle)
 
@@ -52,6 +64,29 @@ struct rv_handle {
     rv::BinArgs bin{};
     int32_t* d_ovf = nullptr;           // max_grid^3, zero between solves
 
+    // batch scratch (max_batch > 0)
+    int32_t max_batch = 0;
+    int32_t batch_grid = 0;             // largest grid of a batch
+    int64_t max_units = 0;
+    bool batch_grids = false;           // RV_FLAG_BATCH_GRIDS
+    rv::Unit* d_units = nullptr;        // max_units
+    rv::Unit* h_units = nullptr;        // pinned staging
+    uint32_t* d_bplan = nullptr;        // [cap | qbase], 2 * max_batch * 8
+    uint32_t* h_bplan = nullptr;        // pinned staging
+    int64_t* d_offsets = nullptr;       // max_batch + 1
+    int64_t* h_offsets = nullptr;       // pinned staging
+    uint32_t* d_bfill = nullptr;        // max_batch * 8
+    uint32_t* d_bflags = nullptr;       // max_batch * 8
+    uint64_t* d_bpartial = nullptr;     // max_batch * 8 * 64
+    float4* d_bcand_q = nullptr;        // max_batch * 64
+    int32_t* d_bcand_votes = nullptr;
+    int32_t* d_bcand_idx = nullptr;
+    uint32_t* d_bcand_inl = nullptr;
+    rv::Result* d_bresult = nullptr;    // max_batch
+    rv::Result* h_bresult = nullptr;    // pinned
+    int32_t* d_bovf = nullptr;          // max_batch * batch_grid^3, zero between batches
+    int32_t* d_bgrids = nullptr;        // max_batch * batch_grid^3 (RV_FLAG_BATCH_GRIDS)
+
     hipEvent_t ev[kStages + 1] = {};
     bool timing = false;
     bool events_recorded = false;
@@ -64,6 +99,10 @@ struct rv_handle {
     int32_t last_ncand = 0;
     int32_t last_winner = -1;
     int64_t last_count = 0;
+    // last batch
+    bool batched = false;
+    int32_t last_B = 0;
+    int32_t last_bgrid = 0;
 
     std::string err;
 };
@@ -124,6 +163,23 @@ void release(rv_handle* h)
     (void)hipFree(h->bin.flags);
     (void)hipFree(h->bin.order);
     (void)hipFree(h->d_ovf);
+    (void)hipFree(h->d_units);
+    (void)hipFree(h->d_bplan);
+    (void)hipFree(h->d_offsets);
+    (void)hipFree(h->d_bfill);
+    (void)hipFree(h->d_bflags);
+    (void)hipFree(h->d_bpartial);
+    (void)hipFree(h->d_bcand_q);
+    (void)hipFree(h->d_bcand_votes);
+    (void)hipFree(h->d_bcand_idx);
+    (void)hipFree(h->d_bcand_inl);
+    (void)hipFree(h->d_bresult);
+    (void)hipFree(h->d_bovf);
+    (void)hipFree(h->d_bgrids);
+    (void)hipHostFree(h->h_units);
+    (void)hipHostFree(h->h_bplan);
+    (void)hipHostFree(h->h_offsets);
+    (void)hipHostFree(h->h_bresult);
     (void)hipHostFree(h->h_result);
     (void)hipHostFree(h->h_table);
     for (auto& e : h->ev)
@@ -169,6 +225,7 @@ RV_API void rot_vote_default_config(rv_config* cfg)
     cfg->topk = 16;
     cfg->vote_strategy = RV_VOTE_AUTO;
     cfg->flags = 0;
+    cfg->max_batch = 0;
 }
 
 RV_API rv_status rot_vote_create(rv_handle** out, const rv_config* cfg)
@@ -185,8 +242,13 @@ RV_API rv_status rot_vote_create(rv_handle** out, const rv_config* cfg)
         return fail(nullptr, RV_EINVAL, "rot_vote_create: topk outside 1..64");
     if (cfg->vote_strategy < RV_VOTE_AUTO || cfg->vote_strategy > RV_VOTE_BRICK)
         return fail(nullptr, RV_EINVAL, "rot_vote_create: unknown vote_strategy");
-    if (cfg->flags & ~(uint32_t)RV_FLAG_TIMING)
+    if (cfg->flags & ~(uint32_t)(RV_FLAG_TIMING | RV_FLAG_BATCH_GRIDS))
         return fail(nullptr, RV_EINVAL, "rot_vote_create: unknown flags");
+    if (cfg->max_batch < 0)
+        return fail(nullptr, RV_EINVAL, "rot_vote_create: max_batch < 0");
+    if (cfg->max_batch > 0 && cfg->vote_strategy == RV_VOTE_GLOBAL)
+        return fail(nullptr, RV_EUNSUPPORTED,
+                    "rot_vote_create: batches use the brick strategy (vote_strategy global)");
     for (int r : cfg->reserved)
         if (r != 0)
             return fail(nullptr, RV_EINVAL, "rot_vote_create: reserved fields must be 0");
@@ -237,17 +299,36 @@ RV_API rv_status rot_vote_create(rv_handle** out, const rv_config* cfg)
     for (auto& ev : h->ev)
         if ((e = hipEventCreate(&ev)) != hipSuccess)
             return bail(e, "events");
-    if (cfg->vote_strategy != RV_VOTE_GLOBAL && h->max_grid <= rv::kMaxBrickGrid) {
-        // Run pool: about 1.7 G runs per circle are expected at J = 8 G (at
+    h->max_batch = cfg->max_batch;
+    h->batch_grid = std::min(h->max_grid, rv::kMaxBatchGrid);
+    h->batch_grids = (cfg->flags & RV_FLAG_BATCH_GRIDS) != 0;
+    const bool want_brick = cfg->vote_strategy != RV_VOTE_GLOBAL && h->max_grid <= rv::kMaxBrickGrid;
+    uint64_t runs = 0;
+    if (want_brick) {
+        // One solve: about 1.7 G runs per circle are expected at J = 8 G (at
         // most J); room for 3 G per circle plus the per-queue slack.
         const uint64_t per_circle = (uint64_t)std::min<int64_t>(h->max_J, 3 * (int64_t)h->max_grid);
-        uint64_t runs = (uint64_t)h->max_n * per_circle +
-                        (uint64_t)rv::kQueueSets * rv::kMaxBricks * 320u;
-        runs = std::min<uint64_t>(runs, 0xFFFFFFFFull - 64);
-        h->bin.pool_runs = runs;
+        runs = (uint64_t)h->max_n * per_circle + (uint64_t)rv::kQueueSets * rv::kMaxBricks * 320u;
+    }
+    if (h->max_batch > 0) {
+        // A batch reserves kBatchCapFactor expected runs per circle plus the
+        // slack and rounding of every queue.
+        const uint64_t per_circle =
+            (uint64_t)std::ceil(kBatchCapFactor * (double)runs_per_circle(h->batch_grid, h->max_J));
+        const uint64_t b = (uint64_t)h->max_n * per_circle +
+                           (uint64_t)h->max_batch * rv::kMaxBatchBricks * (kBatchCapSlack + 128u);
+        runs = std::max(runs, b);
+    }
+    runs = std::min<uint64_t>(runs, 0xFFFFFFFFull - 64);
+    h->bin.pool_runs = runs;
+    if (runs > 0 && (e = hipMalloc(&h->bin.pool, runs * sizeof(uint32_t))) != hipSuccess)
+        return bail(e, "brick run pool");
+    h->bin.nsets = rv::kQueueSets;
+    h->bin.qstride = rv::kMaxBricks;
+    h->bin.units = nullptr;
+    h->bin.batch = 0;
+    if (want_brick) {
         const size_t nq = (size_t)rv::kQueueSets * rv::kMaxBricks;
-        if ((e = hipMalloc(&h->bin.pool, runs * sizeof(uint32_t))) != hipSuccess)
-            return bail(e, "brick run pool");
         if ((e = hipMalloc(&h->bin.fill, nq * sizeof(uint32_t))) != hipSuccess ||
             (e = hipMalloc(&h->bin.qbase, nq * sizeof(uint32_t))) != hipSuccess ||
             (e = hipMalloc(&h->bin.cap, rv::kMaxBricks * sizeof(uint32_t))) != hipSuccess ||
@@ -262,6 +343,40 @@ RV_API rv_status rot_vote_create(rv_handle** out, const rv_config* cfg)
             return bail(e, "brick scratch init");
         h->bin.ovf = h->d_ovf;
         h->brick_ok = true;
+    }
+    if (h->max_batch > 0) {
+        const int64_t B = h->max_batch;
+        const int64_t nq = B * rv::kMaxBatchBricks;
+        const int64_t bg = h->batch_grid;
+        const size_t gcells = (size_t)B * (size_t)(bg * bg * bg);
+        h->max_units = (h->max_n + rv::kUnitSize - 1) / rv::kUnitSize + B;
+        if ((e = hipMalloc(&h->d_units, (size_t)h->max_units * sizeof(rv::Unit))) != hipSuccess ||
+            (e = hipMalloc(&h->d_bplan, (size_t)(2 * nq) * sizeof(uint32_t))) != hipSuccess ||
+            (e = hipMalloc(&h->d_offsets, (size_t)(B + 1) * sizeof(int64_t))) != hipSuccess ||
+            (e = hipMalloc(&h->d_bfill, (size_t)nq * sizeof(uint32_t))) != hipSuccess ||
+            (e = hipMalloc(&h->d_bflags, (size_t)nq * sizeof(uint32_t))) != hipSuccess ||
+            (e = hipMalloc(&h->d_bpartial, (size_t)nq * 64 * sizeof(uint64_t))) != hipSuccess ||
+            (e = hipMalloc(&h->d_bcand_q, (size_t)B * 64 * sizeof(float4))) != hipSuccess ||
+            (e = hipMalloc(&h->d_bcand_votes, (size_t)B * 64 * sizeof(int32_t))) != hipSuccess ||
+            (e = hipMalloc(&h->d_bcand_idx, (size_t)B * 64 * sizeof(int32_t))) != hipSuccess ||
+            (e = hipMalloc(&h->d_bcand_inl, (size_t)B * 64 * sizeof(uint32_t))) != hipSuccess ||
+            (e = hipMalloc(&h->d_bresult, (size_t)B * sizeof(rv::Result))) != hipSuccess ||
+            (e = hipMalloc(&h->d_bovf, gcells * sizeof(int32_t))) != hipSuccess)
+            return bail(e, "batch scratch");
+        if (h->batch_grids && (e = hipMalloc(&h->d_bgrids, gcells * sizeof(int32_t))) != hipSuccess)
+            return bail(e, "batch grids");
+        if ((e = hipHostMalloc(&h->h_units, (size_t)h->max_units * sizeof(rv::Unit),
+                               hipHostMallocDefault)) != hipSuccess ||
+            (e = hipHostMalloc(&h->h_bplan, (size_t)(2 * nq) * sizeof(uint32_t),
+                               hipHostMallocDefault)) != hipSuccess ||
+            (e = hipHostMalloc(&h->h_offsets, (size_t)(B + 1) * sizeof(int64_t),
+                               hipHostMallocDefault)) != hipSuccess ||
+            (e = hipHostMalloc(&h->h_bresult, (size_t)B * sizeof(rv::Result),
+                               hipHostMallocDefault)) != hipSuccess)
+            return bail(e, "pinned batch staging");
+        if ((e = hipMemset(h->d_bovf, 0, gcells * sizeof(int32_t))) != hipSuccess ||
+            (e = hipDeviceSynchronize()) != hipSuccess)
+            return bail(e, "batch scratch init");
     }
     *out = h;
     return RV_OK;
@@ -401,6 +516,207 @@ RV_API rv_status rot_vote_solve(rv_handle* h, const float* x, const float* y, in
     h->last_ncand = r.n_cand;
     h->last_winner = r.winner;
     h->last_count = r.count;
+    return RV_OK;
+}
+
+RV_API rv_status rot_vote_solve_batch(rv_handle* h, const float* x, const float* y,
+                                      const int64_t* offsets, int32_t B, int32_t grid, float eps_rad,
+                                      float* q_out, int64_t* inlier_count, uint8_t* inlier_mask)
+{
+    if (!h)
+        return RV_EINVAL;
+    h->err.clear();
+    if (h->max_batch == 0)
+        return fail(h, RV_EUNSUPPORTED, "rot_vote_solve_batch: handle created with max_batch = 0");
+    if (B < 0 || B > h->max_batch)
+        return fail(h, RV_EINVAL, "rot_vote_solve_batch: B outside 0..max_batch");
+    if (B == 0)
+        return RV_OK;
+    if (!offsets || !q_out || !inlier_count)
+        return fail(h, RV_EINVAL, "rot_vote_solve_batch: offsets, q_out and inlier_count must not be NULL");
+    if (grid < 1 || grid > h->batch_grid)
+        return fail(h, RV_EINVAL, "rot_vote_solve_batch: grid outside 1..min(max_grid, 64)");
+    if (!(eps_rad > 0.0f) || !(eps_rad <= (float)M_PI))
+        return fail(h, RV_EINVAL, "rot_vote_solve_batch: eps_rad outside (0, pi]");
+    const int32_t J = h->cfg.samples_per_circle > 0 ? h->cfg.samples_per_circle : 8 * grid;
+    if (J > h->max_J)
+        return fail(h, RV_EINVAL, "rot_vote_solve_batch: J = 8*grid exceeds the table sized at create");
+    if (offsets[0] != 0)
+        return fail(h, RV_EINVAL, "rot_vote_solve_batch: offsets[0] must be 0");
+    for (int32_t b = 0; b < B; ++b) {
+        const int64_t nb = offsets[b + 1] - offsets[b];
+        if (nb < 0)
+            return fail(h, RV_EINVAL, "rot_vote_solve_batch: offsets must be nondecreasing");
+        if (offsets[b + 1] > h->max_n)
+            return fail(h, RV_EINVAL, "rot_vote_solve_batch: offsets[B] exceeds the handle's max_n");
+        if (nb * (int64_t)J > (int64_t)INT32_MAX)
+            return fail(h, RV_EUNSUPPORTED, "rot_vote_solve_batch: an instance's n*J exceeds int32 vote counts");
+    }
+    const int64_t n = offsets[B];
+    if (n > 0) {
+        if (!x || !y || !inlier_mask)
+            return fail(h, RV_EINVAL, "rot_vote_solve_batch: x, y and inlier_mask must not be NULL");
+        if (!is_device_memory(x) || !is_device_memory(y) || !is_device_memory(inlier_mask))
+            return fail(h, RV_EINVAL, "rot_vote_solve_batch: x, y and inlier_mask must be device memory");
+    }
+    RV_HIP(h, hipSetDevice(h->device), "hipSetDevice");
+    hipStream_t s = h->stream;
+    const float T2 = residual_bound(eps_rad);
+    const int nba = rv::brick_axis(grid);
+    const int nb = nba * nba * nba;
+    const int64_t nq = (int64_t)B * nb;
+
+    // The staging buffers are reused: nothing of an earlier call may still read them.
+    RV_HIP(h, hipStreamSynchronize(s), "sync before batch plan");
+    if (h->table_J != J) {
+        fill_table(h->h_table, J);
+        RV_HIP(h, hipMemcpyAsync(h->d_table, h->h_table, (size_t)J * sizeof(float2),
+                                 hipMemcpyHostToDevice, s),
+               "table upload");
+        h->table_J = J;
+    }
+    // Host plan: work units of up to kUnitSize correspondences, and queue
+    // capacities from each instance's expected runs (overflowing runs go to
+    // the instance's overflow grid, so the plan bounds speed, not results).
+    const double share = kBatchCapFactor * (double)runs_per_circle(grid, J) / (double)nb;
+    uint32_t* cap = h->h_bplan;
+    uint32_t* qbase = h->h_bplan + nq;
+    uint64_t total = 0;
+    int64_t nunits = 0;
+    for (int32_t b = 0; b < B; ++b) {
+        const int64_t lo = offsets[b], hi = offsets[b + 1];
+        for (int64_t f = lo; f < hi; f += rv::kUnitSize)
+            h->h_units[nunits++] = rv::Unit{b, (int32_t)std::min<int64_t>(rv::kUnitSize, hi - f), f};
+        const uint64_t c = hi > lo ? (((uint64_t)std::ceil(share * (double)(hi - lo)) + kBatchCapSlack + 63u) & ~63ull)
+                                   : 0u;
+        for (int k = 0; k < nb; ++k)
+            cap[(int64_t)b * nb + k] = (uint32_t)std::min<uint64_t>(c, 0x7FFFFFC0u);
+        total += c * (uint64_t)nb;
+    }
+    if (total > h->bin.pool_runs) {  // cannot happen within max_n; keep every queue inside the pool
+        const double f = (double)h->bin.pool_runs / (double)total;
+        for (int64_t k = 0; k < nq; ++k)
+            cap[k] = (uint32_t)((uint64_t)((double)cap[k] * f) & ~63ull);
+    }
+    uint64_t at = 0;
+    for (int64_t k = 0; k < nq; ++k) {
+        qbase[k] = (uint32_t)at;
+        at += cap[k];
+    }
+    for (int32_t b = 0; b <= B; ++b)
+        h->h_offsets[b] = offsets[b];
+
+    const bool tm = h->timing;
+    h->batched = true;
+    h->last_B = B;
+    h->last_bgrid = grid;
+    h->last_J = J;
+    h->last_strategy = RV_VOTE_BRICK;
+    if (tm)
+        RV_HIP(h, hipEventRecord(h->ev[0], s), "event");
+    if (nunits > 0)
+        RV_HIP(h, hipMemcpyAsync(h->d_units, h->h_units, (size_t)nunits * sizeof(rv::Unit),
+                                 hipMemcpyHostToDevice, s),
+               "unit upload");
+    RV_HIP(h, hipMemcpyAsync(h->d_bplan, h->h_bplan, (size_t)(2 * nq) * sizeof(uint32_t),
+                             hipMemcpyHostToDevice, s),
+           "plan upload");
+    RV_HIP(h, hipMemcpyAsync(h->d_offsets, h->h_offsets, (size_t)(B + 1) * sizeof(int64_t),
+                             hipMemcpyHostToDevice, s),
+           "offsets upload");
+    RV_HIP(h, rv::launch_fill((int32_t*)h->d_bfill, nq, 0, s), "clear queue fills");
+    RV_HIP(h, rv::launch_fill((int32_t*)h->d_bflags, nq, 0, s), "clear overflow flags");
+    if (tm)
+        RV_HIP(h, hipEventRecord(h->ev[1], s), "event");
+
+    rv::BinArgs a = h->bin;
+    a.fill = h->d_bfill;
+    a.qbase = h->d_bplan + nq;
+    a.cap = h->d_bplan;
+    a.flags = h->d_bflags;
+    a.ovf = h->d_bovf;
+    a.units = h->d_units;
+    a.nsets = 1;
+    a.qstride = (int32_t)nq;
+    a.batch = B;
+    RV_HIP(h, rv::launch_bin_vote_batch(x, y, n, grid, J, h->d_table, a, (int)nunits, s), "batch vote");
+    if (tm)
+        RV_HIP(h, hipEventRecord(h->ev[2], s), "event");
+    RV_HIP(h, rv::launch_brick_accum(grid, h->batch_grids ? h->d_bgrids : nullptr, h->d_bpartial, a, s),
+           "batch brick accumulate");
+    if (tm)
+        RV_HIP(h, hipEventRecord(h->ev[3], s), "event");
+    const rv::Candidates c{h->d_bcand_q, h->d_bcand_votes, h->d_bcand_idx, h->d_bcand_inl, h->d_bresult};
+    RV_HIP(h, rv::launch_batch_finish(x, y, n, T2, B, nb, h->K, grid, h->d_bpartial, h->d_units,
+                                      (int)nunits, h->d_offsets, c, inlier_mask, s,
+                                      tm ? h->ev[4] : nullptr, tm ? h->ev[5] : nullptr),
+           "batch top-K, rescore and mask");
+    if (tm)
+        RV_HIP(h, hipEventRecord(h->ev[6], s), "event");
+    RV_HIP(h, hipMemcpyAsync(h->h_bresult, h->d_bresult, (size_t)B * sizeof(rv::Result),
+                             hipMemcpyDeviceToHost, s),
+           "result readback");
+    RV_HIP(h, hipStreamSynchronize(s), "sync");
+    h->events_recorded = tm;
+    for (int32_t b = 0; b < B; ++b) {
+        const rv::Result& r = h->h_bresult[b];
+        std::memcpy(q_out + 4 * (int64_t)b, r.q, sizeof(r.q));
+        inlier_count[b] = r.count;
+    }
+    return RV_OK;
+}
+
+RV_API rv_status rot_vote_get_batch_histogram(rv_handle* h, int32_t b, int32_t* dst_device)
+{
+    if (!h)
+        return RV_EINVAL;
+    if (!h->batched)
+        return fail(h, RV_EINVAL, "rot_vote_get_batch_histogram: no batch yet");
+    if (!h->batch_grids)
+        return fail(h, RV_EINVAL, "rot_vote_get_batch_histogram: create with RV_FLAG_BATCH_GRIDS");
+    if (b < 0 || b >= h->last_B)
+        return fail(h, RV_EINVAL, "rot_vote_get_batch_histogram: b outside the last batch");
+    if (!dst_device || !is_device_memory(dst_device))
+        return fail(h, RV_EINVAL, "rot_vote_get_batch_histogram: dst must be device memory");
+    const int64_t g = h->last_bgrid;
+    const size_t cells = (size_t)(g * g * g);
+    RV_HIP(h, hipSetDevice(h->device), "hipSetDevice");
+    RV_HIP(h, hipMemcpyAsync(dst_device, h->d_bgrids + (size_t)b * cells, cells * sizeof(int32_t),
+                             hipMemcpyDeviceToDevice, h->stream),
+           "histogram copy");
+    RV_HIP(h, hipStreamSynchronize(h->stream), "sync");
+    return RV_OK;
+}
+
+RV_API rv_status rot_vote_get_batch_topk(rv_handle* h, int32_t b, int32_t* n_cand, int32_t* votes,
+                                         int32_t* cell_idx, int64_t* inliers, int32_t* winner)
+{
+    if (!h)
+        return RV_EINVAL;
+    if (!h->batched)
+        return fail(h, RV_EINVAL, "rot_vote_get_batch_topk: no batch yet");
+    if (b < 0 || b >= h->last_B)
+        return fail(h, RV_EINVAL, "rot_vote_get_batch_topk: b outside the last batch");
+    if (!n_cand || !votes || !cell_idx || !inliers || !winner)
+        return fail(h, RV_EINVAL, "rot_vote_get_batch_topk: NULL argument");
+    const rv::Result& r = h->h_bresult[b];
+    const int m = r.n_cand;
+    if (m > 0) {
+        int32_t v[64], ix[64];
+        uint32_t in[64];
+        const size_t o = (size_t)b * 64;
+        RV_HIP(h, hipSetDevice(h->device), "hipSetDevice");
+        RV_HIP(h, hipMemcpy(v, h->d_bcand_votes + o, m * sizeof(int32_t), hipMemcpyDeviceToHost), "copy");
+        RV_HIP(h, hipMemcpy(ix, h->d_bcand_idx + o, m * sizeof(int32_t), hipMemcpyDeviceToHost), "copy");
+        RV_HIP(h, hipMemcpy(in, h->d_bcand_inl + o, m * sizeof(uint32_t), hipMemcpyDeviceToHost), "copy");
+        for (int k = 0; k < m; ++k) {
+            votes[k] = v[k];
+            cell_idx[k] = ix[k];
+            inliers[k] = in[k];
+        }
+    }
+    *n_cand = m;
+    *winner = r.winner;
     return RV_OK;
 }
 

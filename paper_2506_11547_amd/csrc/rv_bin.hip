@@ -30,6 +30,7 @@ constexpr int kBrickCells = kEdge * kEdge * kEdge;
 constexpr int kSets = kQueueSets;
 constexpr int kBinWaves = 8;
 constexpr int kBinThreads = kBinWaves * kWave;
+static_assert(kBinThreads == kUnitSize, "a batch work unit is one vote block");
 constexpr int kStageCap = 2048;  // runs staged per wave between flushes
 constexpr int kStep = 16;        // samples per lane between flush checks
 constexpr int kSplit = 240;      // runs are cut every 240 samples: counts fit 8 bits
@@ -196,7 +197,7 @@ __device__ __forceinline__ void bin_flush(uint32_t (*stage)[kStageCap], const ui
                                           uint32_t* s_cnt, uint32_t* s_gbase,
                                           const uint32_t* s_cap, const uint32_t* s_qbase,
                                           int wave, int lane, int nb, int nba, int G, int xs,
-                                          const BinArgs& a)
+                                          int qoff, int64_t ovf_off, const BinArgs& a)
 {
     const uint32_t my = s_fillw[wave];
     for (uint32_t k = lane; k < my; k += kWave) {
@@ -214,7 +215,7 @@ __device__ __forceinline__ void bin_flush(uint32_t (*stage)[kStageCap], const ui
     for (int b = threadIdx.x; b < nb; b += kBinThreads) {
         const uint32_t c = s_cnt[b];
         if (c)
-            s_gbase[b] = atomicAdd(a.fill + xs * kMaxBricks + b, c);
+            s_gbase[b] = atomicAdd(a.fill + (int64_t)xs * a.qstride + qoff + b, c);
         s_cnt[b] = 0;
     }
     __syncthreads();
@@ -228,8 +229,8 @@ __device__ __forceinline__ void bin_flush(uint32_t (*stage)[kStageCap], const ui
         if (slot < s_cap[b]) {
             a.pool[(uint64_t)s_qbase[b] + slot] = q;
         } else {
-            atomicAdd(a.ovf + global_of(b, q & 0x7FFFu, nba, G), (int32_t)(q >> 15));
-            a.flags[b] = 1u;
+            atomicAdd(a.ovf + ovf_off + global_of(b, q & 0x7FFFu, nba, G), (int32_t)(q >> 15));
+            a.flags[qoff + b] = 1u;
         }
     }
     __syncthreads();
@@ -259,18 +260,33 @@ __global__ __launch_bounds__(kBinThreads, 2) void k_vote_bin(const float* __rest
     const int nb = nba * nba * nba;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
-    const int xs = blockIdx.x & (kSets - 1);
+    const int xs = a.nsets > 1 ? (int)(blockIdx.x & (kSets - 1)) : 0;
+    int inst = 0, j0, j1;
+    int64_t i0, iend;
+    if (a.units) {  // batch: one unit of one instance, every sample
+        const Unit un = a.units[blockIdx.x];
+        inst = un.inst;
+        i0 = un.first;
+        iend = un.first + un.count;
+        j0 = 0;
+        j1 = J;
+    } else {
+        const int cb = blockIdx.x / ngroups;
+        const int gb = blockIdx.x - cb * ngroups;
+        i0 = (int64_t)gb * kBinThreads;
+        iend = n;
+        j0 = cb * chunk;
+        j1 = min(J, j0 + chunk);
+    }
+    const int qoff = inst * nb;
+    const int64_t ovf_off = (int64_t)inst * G * G * G;
     for (int b = threadIdx.x; b < nb; b += kBinThreads) {
         s_cnt[b] = 0;
-        s_cap[b] = a.cap[b];
-        s_qbase[b] = a.qbase[xs * kMaxBricks + b];
+        s_cap[b] = a.cap[qoff + b];
+        s_qbase[b] = a.qbase[(int64_t)xs * a.qstride + qoff + b];
     }
-    const int cb = blockIdx.x / ngroups;
-    const int gb = blockIdx.x - cb * ngroups;
-    const int j0 = cb * chunk;
-    const int j1 = min(J, j0 + chunk);
     Quat u, v;
-    const bool ok = load_circle(x, y, n, (int64_t)gb * kBinThreads + threadIdx.x, u, v);
+    const bool ok = load_circle(x, y, n, i0 + threadIdx.x, u, v) && (i0 + threadIdx.x < iend);
     uint32_t fill = 0;  // this wave's staged runs (wave-uniform)
     // The open run of each lane: its cell and length.  A run is emitted when
     // the cell changes and at every run-block end, where its length restarts
@@ -315,7 +331,7 @@ __global__ __launch_bounds__(kBinThreads, 2) void k_vote_bin(const float* __rest
                 need |= s_fill[parity][w] > (uint32_t)kFlushAt;
             if (need) {
                 bin_flush(stage, s_fill[parity], s_cnt, s_gbase, s_cap, s_qbase, wave, lane, nb, nba,
-                          G, xs, a);
+                          G, xs, qoff, ovf_off, a);
                 fill = 0;
             }
             parity ^= 1;
@@ -332,7 +348,7 @@ __global__ __launch_bounds__(kBinThreads, 2) void k_vote_bin(const float* __rest
         any |= s_fill[parity][w] > 0;
     if (any)
         bin_flush(stage, s_fill[parity], s_cnt, s_gbase, s_cap, s_qbase, wave, lane, nb, nba, G, xs,
-                  a);
+                  qoff, ovf_off, a);
 }
 
 // ----------------------------------------------------------- accumulate
@@ -343,7 +359,17 @@ __global__ __launch_bounds__(kAccumThreads, 1) void k_brick_accum(BinArgs a, int
 {
     __shared__ uint32_t acc[kBrickCells];
     __shared__ uint64_t lists[kAccumWaves][kWave];
-    const int b = (int)a.order[blockIdx.x];
+    const int nb = nba * nba * nba;
+    int inst, b;
+    if (a.batch) {
+        inst = blockIdx.x / nb;
+        b = blockIdx.x - inst * nb;
+    } else {
+        inst = 0;
+        b = (int)a.order[blockIdx.x];
+    }
+    const int qoff = inst * nb;
+    const int64_t gofs = (int64_t)inst * G * G * G;  // this instance's grid and overflow grid
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     const int bx = b % nba, by = (b / nba) % nba, bz = b / (nba * nba);
@@ -353,16 +379,16 @@ __global__ __launch_bounds__(kAccumThreads, 1) void k_brick_accum(BinArgs a, int
         acc4[k] = make_uint4(0u, 0u, 0u, 0u);
     __syncthreads();
 
-    const uint32_t cap = a.cap[b];
+    const uint32_t cap = a.cap[qoff + b];
     // Software-pipelined queue reads: the next 8 KiB per wave are in flight
     // while the current ones are added into LDS.  Queues start on 64-run
     // boundaries and their capacity is a multiple of 64, so vector loads of
     // 4 runs starting below the fill count stay inside the queue.
     constexpr int kUnroll = 8;
     constexpr uint32_t kStride = kAccumThreads * 4;
-    for (int xs = 0; xs < kSets; ++xs) {
-        const uint32_t cnt = min(a.fill[xs * kMaxBricks + b], cap);
-        const uint32_t* q = a.pool + a.qbase[xs * kMaxBricks + b];
+    for (int xs = 0; xs < a.nsets; ++xs) {
+        const uint32_t cnt = min(a.fill[(int64_t)xs * a.qstride + qoff + b], cap);
+        const uint32_t* q = a.pool + a.qbase[(int64_t)xs * a.qstride + qoff + b];
         if (cnt == 0)
             continue;
         // loads are unconditional (clamped to the queue's last vector) so the
@@ -396,7 +422,7 @@ __global__ __launch_bounds__(kAccumThreads, 1) void k_brick_accum(BinArgs a, int
     }
     __syncthreads();
 
-    const bool overflowed = a.flags[b] != 0u;
+    const bool overflowed = a.flags[qoff + b] != 0u;
     const bool vec = (G % 4) == 0;
     uint64_t list = 0;
     for (int c = threadIdx.x * 4; c < kBrickCells; c += kAccumThreads * 4) {
@@ -414,18 +440,20 @@ __global__ __launch_bounds__(kAccumThreads, 1) void k_brick_accum(BinArgs a, int
 #pragma unroll
                 for (int s = 0; s < 4; ++s)
                     if (gx + s < G) {
-                        val[s] += (uint32_t)a.ovf[g0 + s];
-                        a.ovf[g0 + s] = 0;
+                        val[s] += (uint32_t)a.ovf[gofs + g0 + s];
+                        a.ovf[gofs + g0 + s] = 0;
                     }
             }
-            if (vec && gx + 3 < G) {
-                *reinterpret_cast<int4*>(grid + g0) =
+            if (grid == nullptr) {
+                // batch without grids: only the top-64 list leaves the CU
+            } else if (vec && gx + 3 < G) {
+                *reinterpret_cast<int4*>(grid + gofs + g0) =
                     make_int4((int)val[0], (int)val[1], (int)val[2], (int)val[3]);
             } else {
 #pragma unroll
                 for (int s = 0; s < 4; ++s)
                     if (gx + s < G)
-                        grid[g0 + s] = (int32_t)val[s];
+                        grid[gofs + g0 + s] = (int32_t)val[s];
             }
         }
 #pragma unroll
@@ -436,7 +464,7 @@ __global__ __launch_bounds__(kAccumThreads, 1) void k_brick_accum(BinArgs a, int
     }
     list = block_merge<kAccumWaves>(list, lists, wave, lane);
     if (wave == 0)
-        partial[(int64_t)b * kWave + lane] = list;
+        partial[(int64_t)(qoff + b) * kWave + lane] = list;
 }
 
 // ------------------------------------------------------------- launchers
@@ -497,7 +525,21 @@ hipError_t launch_brick_accum(int G, int32_t* grid, uint64_t* partial, const Bin
     const int nb = nba * nba * nba;
     if (G > kMaxBrickGrid || nb > kMaxBricks)
         return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_brick_accum, dim3(nb), dim3(kAccumThreads), 0, s, a, G, nba, grid, partial);
+    const int blocks = a.batch ? a.batch * nb : nb;
+    hipLaunchKernelGGL(k_brick_accum, dim3(blocks), dim3(kAccumThreads), 0, s, a, G, nba, grid,
+                       partial);
+    return hipGetLastError();
+}
+
+hipError_t launch_bin_vote_batch(const float* x, const float* y, int64_t n, int G, int J,
+                                 const float2* table, const BinArgs& a, int nunits, hipStream_t s)
+{
+    if (nunits <= 0)
+        return hipSuccess;
+    if (G > kMaxBrickGrid || !a.units)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_vote_bin, dim3((unsigned)nunits), dim3(kBinThreads), 0, s, x, y, n, G,
+                       (float)G * 0.5f, (float)G - 0.5f, J, J, 1, table, brick_axis(G), a);
     return hipGetLastError();
 }
 

@@ -46,16 +46,30 @@ constexpr int kMaxBricks = 512;      // (256 / 32)^3
 constexpr int kMaxBrickGrid = 256;   // cell coordinates packed in one byte each
 constexpr int kEstimateStride = 64;  // the estimate samples every 64th correspondence
 
+// A batch work unit: up to 512 consecutive correspondences of one instance.
+struct Unit {
+    int32_t inst;
+    int32_t count;
+    int64_t first;
+};
+
+// Queues are indexed [set][instance * nb + brick]: one solve uses kQueueSets
+// sets (one per XCD) and qstride = kMaxBricks; a batch uses one set and
+// qstride = B * nb.
 struct BinArgs {
     uint32_t* pool;      // run queues; entry = local cell | run length << 15
-    uint32_t* fill;      // [kQueueSets][kMaxBricks] runs appended per queue
-    uint32_t* qbase;     // [kQueueSets][kMaxBricks] first pool slot of each queue
-    uint32_t* cap;       // [kMaxBricks] capacity of each of the brick's queues
+    uint32_t* fill;      // [nsets][qstride] runs appended per queue
+    uint32_t* qbase;     // [nsets][qstride] first pool slot of each queue
+    uint32_t* cap;       // [qstride] capacity of each queue of the brick
     uint32_t* est;       // [kMaxBricks] estimated runs (sampled), zero between solves
-    uint32_t* flags;     // [kMaxBricks] set when a brick's queue overflowed
-    uint32_t* order;     // [kMaxBricks] bricks by decreasing capacity (accumulation order)
-    int32_t* ovf;        // G^3 overflow grid, zero between solves
+    uint32_t* flags;     // [qstride] set when a brick's queue overflowed
+    uint32_t* order;     // [kMaxBricks] one solve: bricks by decreasing capacity
+    int32_t* ovf;        // [instances][G^3] overflow grids, zero between solves
     uint64_t pool_runs;  // pool capacity in runs (< 2^32)
+    const Unit* units;   // batch: work units of the binned vote (null for one solve)
+    int32_t nsets;
+    int32_t qstride;
+    int32_t batch;       // number of instances (0 for one solve)
 };
 
 int brick_axis(int G);
@@ -67,6 +81,18 @@ hipError_t launch_bin_vote(const float* x, const float* y, int64_t n, int G, int
                            const float2* table, const BinArgs& a, hipStream_t s);
 hipError_t launch_brick_accum(int G, int32_t* grid, uint64_t* partial, const BinArgs& a,
                               hipStream_t s);
+
+// Batches (G <= kMaxBatchGrid): the binned vote over work units, then the
+// per-instance top-K merge, rescore and mask.
+constexpr int kMaxBatchGrid = 64;
+constexpr int kMaxBatchBricks = 8;   // (64 / 32)^3
+constexpr int kUnitSize = 512;       // correspondences per work unit
+hipError_t launch_bin_vote_batch(const float* x, const float* y, int64_t n, int G, int J,
+                                 const float2* table, const BinArgs& a, int nunits, hipStream_t s);
+hipError_t launch_batch_finish(const float* x, const float* y, int64_t n, float T2, int B, int nb,
+                               int K, int G, const uint64_t* partial, const Unit* units, int nunits,
+                               const int64_t* offsets, const Candidates& c, uint8_t* mask,
+                               hipStream_t s, hipEvent_t after_topk, hipEvent_t after_rescore);
 
 hipError_t launch_rescore(const float* x, const float* y, int64_t n, float T2,
                           const Candidates& c, hipStream_t s);

@@ -31,6 +31,10 @@ __all__ = [
     "WORKLOADS",
     "make_instance",
     "make_workload",
+    "BatchWorkload",
+    "BATCH_WORKLOADS",
+    "Batch",
+    "make_batch",
     "quat_to_matrix",
     "rotation_error_deg",
 ]
@@ -90,6 +94,78 @@ WORKLOADS = {
 def make_workload(name: str) -> tuple[Workload, Instance]:
     w = WORKLOADS[name]
     return w, w.instance()
+
+
+@dataclass
+class Batch:
+    x: np.ndarray          # float32 [3, sum N_b], instances back to back
+    y: np.ndarray
+    offsets: np.ndarray    # int64 [B + 1]; instance b is columns offsets[b]:offsets[b+1]
+    q_gt: np.ndarray       # float64 [B, 4]
+    outlier_ratio: np.ndarray  # float64 [B]
+
+    @property
+    def B(self) -> int:
+        return len(self.offsets) - 1
+
+    def instance(self, b: int):
+        lo, hi = int(self.offsets[b]), int(self.offsets[b + 1])
+        return self.x[:, lo:hi], self.y[:, lo:hi]
+
+
+@dataclass
+class BatchWorkload:
+    """Many independent instances solved together (same G, J, K, eps): N is
+    log-uniform on [n_lo, n_hi], the outlier ratio uniform on [rho_lo, rho_hi]."""
+    name: str
+    instances: int
+    n_lo: int
+    n_hi: int
+    rho_lo: float
+    rho_hi: float
+    sigma_deg: float
+    grid: int
+    samples: int
+    eps_deg: float
+    topk: int
+    seed: int
+
+    def batch(self, instances: int | None = None) -> Batch:
+        return make_batch(self.instances if instances is None else instances, self.n_lo,
+                          self.n_hi, self.rho_lo, self.rho_hi, self.sigma_deg, self.seed)
+
+
+BATCH_WORKLOADS = {
+    # 4096 uneven instances: N spans 200x (mean about 3756, about 1.54e7 in all).
+    "batch": BatchWorkload("batch", instances=4096, n_lo=100, n_hi=20_000, rho_lo=0.5,
+                           rho_hi=0.99, sigma_deg=0.5, grid=64, samples=512, eps_deg=1.0,
+                           topk=16, seed=3),
+}
+
+
+def make_batch(instances: int, n_lo: int, n_hi: int, rho_lo: float, rho_hi: float,
+               sigma_deg: float, seed: int) -> Batch:
+    """Draw order (fixed): every N_b (log-uniform, rounded down), every outlier
+    ratio, every instance seed; then the instances in order (make_instance)."""
+    rng = np.random.default_rng(seed)
+    if n_lo > 0:
+        ns = np.floor(np.exp(rng.uniform(math.log(n_lo), math.log(n_hi + 1), size=instances)))
+        ns = np.minimum(ns, n_hi).astype(np.int64)
+    else:
+        ns = rng.integers(0, n_hi + 1, size=instances).astype(np.int64)
+    rhos = rng.uniform(rho_lo, rho_hi, size=instances)
+    seeds = rng.integers(0, 2**62, size=instances)
+    offsets = np.zeros(instances + 1, np.int64)
+    offsets[1:] = np.cumsum(ns)
+    x = np.empty((3, int(offsets[-1])), np.float32)
+    y = np.empty_like(x)
+    q = np.empty((instances, 4))
+    for b in range(instances):
+        inst = make_instance(int(ns[b]), float(rhos[b]), sigma_deg, int(seeds[b]))
+        x[:, offsets[b]:offsets[b + 1]] = inst.x
+        y[:, offsets[b]:offsets[b + 1]] = inst.y
+        q[b] = inst.q_gt
+    return Batch(x, y, offsets, q, rhos)
 
 
 def quat_to_matrix(q) -> np.ndarray:

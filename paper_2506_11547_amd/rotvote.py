@@ -25,7 +25,9 @@ STATUS_NAMES = {0: "RV_OK", -1: "RV_EINVAL", -2: "RV_ENOMEM", -3: "RV_EDEVICE",
 STRATEGIES = {"auto": 0, "global": 1, "brick": 2}
 STRATEGY_NAMES = {v: k for k, v in STRATEGIES.items()}
 FLAG_TIMING = 1
+FLAG_BATCH_GRIDS = 2
 MAX_TOPK = 64
+MAX_BATCH_GRID = 64
 NUM_STAGES = 6
 STAGE_NAMES = ("prepare", "vote", "reduce", "topk", "rescore", "mask")
 
@@ -33,14 +35,15 @@ STAGE_NAMES = ("prepare", "vote", "reduce", "topk", "rescore", "mask")
 EXPORTS = ("rot_vote_default_config", "rot_vote_create", "rot_vote_destroy",
            "rot_vote_last_error", "rot_vote_set_stream", "rot_vote_solve",
            "rot_vote_get_histogram", "rot_vote_get_topk", "rot_vote_get_plan",
-           "rot_vote_get_timings")
+           "rot_vote_get_timings", "rot_vote_solve_batch", "rot_vote_get_batch_histogram",
+           "rot_vote_get_batch_topk")
 
 
 class RvConfig(ct.Structure):
     _fields_ = [("device", ct.c_int32), ("stream", ct.c_void_p), ("max_n", ct.c_int64),
                 ("max_grid", ct.c_int32), ("samples_per_circle", ct.c_int32),
                 ("topk", ct.c_int32), ("vote_strategy", ct.c_int32), ("flags", ct.c_uint32),
-                ("reserved", ct.c_int32 * 4)]
+                ("max_batch", ct.c_int32), ("reserved", ct.c_int32 * 3)]
 
 
 class RotVoteError(RuntimeError):
@@ -85,6 +88,15 @@ def load_library(path: Path | str = LIB_PATH) -> ct.CDLL:
     L.rot_vote_get_plan.restype = i32
     L.rot_vote_get_timings.argtypes = [vp, ct.POINTER(f32 * NUM_STAGES)]
     L.rot_vote_get_timings.restype = i32
+    L.rot_vote_solve_batch.argtypes = [vp, vp, vp, ct.POINTER(i64), i32, i32, f32,
+                                       ct.POINTER(f32), ct.POINTER(i64), vp]
+    L.rot_vote_solve_batch.restype = i32
+    L.rot_vote_get_batch_histogram.argtypes = [vp, i32, vp]
+    L.rot_vote_get_batch_histogram.restype = i32
+    L.rot_vote_get_batch_topk.argtypes = [vp, i32, ct.POINTER(i32), ct.POINTER(i32 * MAX_TOPK),
+                                          ct.POINTER(i32 * MAX_TOPK), ct.POINTER(i64 * MAX_TOPK),
+                                          ct.POINTER(i32)]
+    L.rot_vote_get_batch_topk.restype = i32
     _lib = L
     return L
 
@@ -99,7 +111,8 @@ class Solver:
 
     def __init__(self, device: int = 0, max_n: int = 1 << 20, max_grid: int = 256,
                  topk: int = 16, samples_per_circle: int = 0, strategy: str = "auto",
-                 timing: bool = False, stream: torch.cuda.Stream | None = None):
+                 timing: bool = False, stream: torch.cuda.Stream | None = None,
+                 max_batch: int = 0, batch_grids: bool = False):
         if not torch.cuda.is_available():
             raise RuntimeError("rotvote needs a HIP GPU; none is visible")
         self._lib = load_library()
@@ -114,7 +127,8 @@ class Solver:
         cfg.samples_per_circle = samples_per_circle
         cfg.topk = topk
         cfg.vote_strategy = STRATEGIES[strategy]
-        cfg.flags = FLAG_TIMING if timing else 0
+        cfg.flags = (FLAG_TIMING if timing else 0) | (FLAG_BATCH_GRIDS if batch_grids else 0)
+        cfg.max_batch = max_batch
         h = ct.c_void_p()
         st = self._lib.rot_vote_create(ct.byref(h), ct.byref(cfg))
         if st != RV_OK:
@@ -125,6 +139,8 @@ class Solver:
         self.max_grid = max_grid
         self._stream = s
         self._last_grid = None
+        self._last_bgrid = None
+        self.max_batch = max_batch
 
     # ---- lifetime
     def close(self):
@@ -181,7 +197,61 @@ class Solver:
                                 mask.data_ptr() if n else 0)
         return q, cnt, mask
 
+    def solve_batch_raw(self, x_ptr: int, y_ptr: int, offsets, grid: int, eps_rad: float,
+                        mask_ptr: int):
+        """Direct C-ABI call: offsets is a sequence of B+1 ints.  Returns (q [B,4], counts [B])."""
+        B = len(offsets) - 1
+        offs = (ct.c_int64 * (B + 1))(*[int(o) for o in offsets])
+        q = (ct.c_float * (4 * max(B, 1)))()
+        cnt = (ct.c_int64 * max(B, 1))()
+        self._check(self._lib.rot_vote_solve_batch(self._h, ct.c_void_p(x_ptr), ct.c_void_p(y_ptr),
+                                                   offs, B, grid, ct.c_float(eps_rad), q, cnt,
+                                                   ct.c_void_p(mask_ptr)))
+        self._last_bgrid = grid
+        return [list(q[4 * b:4 * b + 4]) for b in range(B)], [int(c) for c in cnt[:B]]
+
+    def solve_batch(self, x: torch.Tensor, y: torch.Tensor, offsets, grid: int, eps_deg: float,
+                    mask: torch.Tensor | None = None):
+        """Instances are the column ranges [offsets[b], offsets[b+1]) of x, y
+        (float32 [3, N] device tensors).  Returns (q [B][4], counts [B], mask)."""
+        for t, nm in ((x, "x"), (y, "y")):
+            if t.dtype != torch.float32 or t.dim() != 2 or t.shape[0] != 3 or not t.is_cuda:
+                raise ValueError(f"{nm} must be a float32 [3, N] device tensor")
+        if x.shape != y.shape:
+            raise ValueError("x and y must have the same shape")
+        offsets = [int(o) for o in offsets]
+        if not offsets or offsets[-1] > x.shape[1]:
+            raise ValueError("offsets must hold B+1 entries with offsets[B] <= N")
+        x = x.contiguous()
+        y = y.contiguous()
+        n = offsets[-1]
+        if mask is None:
+            mask = torch.empty(x.shape[1], dtype=torch.bool, device=x.device)
+        q, cnt = self.solve_batch_raw(x.data_ptr(), y.data_ptr(), offsets, grid,
+                                      eps_deg_to_rad(eps_deg), mask.data_ptr() if n else 0)
+        return q, cnt, mask
+
     # ---- test hooks
+    def batch_histogram(self, b: int) -> torch.Tensor:
+        g = self._last_bgrid
+        if g is None:
+            raise RuntimeError("no batch yet")
+        out = torch.empty(g ** 3, dtype=torch.int32, device=self.device)
+        self._check(self._lib.rot_vote_get_batch_histogram(self._h, b, ct.c_void_p(out.data_ptr())))
+        return out
+
+    def batch_topk(self, b: int) -> dict:
+        nc = ct.c_int32()
+        votes = (ct.c_int32 * MAX_TOPK)()
+        idx = (ct.c_int32 * MAX_TOPK)()
+        inl = (ct.c_int64 * MAX_TOPK)()
+        win = ct.c_int32()
+        self._check(self._lib.rot_vote_get_batch_topk(self._h, b, ct.byref(nc), ct.byref(votes),
+                                                      ct.byref(idx), ct.byref(inl), ct.byref(win)))
+        m = nc.value
+        return dict(votes=list(votes[:m]), idx=list(idx[:m]), inliers=list(inl[:m]),
+                    winner=win.value)
+
     def histogram(self) -> torch.Tensor:
         g = self._last_grid
         if g is None:

@@ -89,3 +89,16 @@ def test_default_config_and_create_without_gpu(lib_path):
     assert lib.rot_vote_create(ct.byref(h), ct.byref(bad)) == -1
     assert b"topk" in lib.rot_vote_last_error(None)
     assert not h.value
+    cfg_sz = ct.sizeof(RvConfig)
+    assert cfg_sz == 64, cfg_sz  # rv_config: 4 + 4 pad + 8 + 8 + 4*4 + 4 + 4 + 12 + 4 pad
+    bad = RvConfig()
+    lib.rot_vote_default_config(ct.byref(bad))
+    assert bad.max_batch == 0
+    bad.max_batch = 4
+    bad.vote_strategy = 1  # global: batches need the brick strategy
+    assert lib.rot_vote_create(ct.byref(h), ct.byref(bad)) == -4
+    assert b"batch" in lib.rot_vote_last_error(None)
+    bad.max_batch = -1
+    bad.vote_strategy = 0
+    assert lib.rot_vote_create(ct.byref(h), ct.byref(bad)) == -1
+    assert not h.value

@@ -1,0 +1,196 @@
+"""GPU: batched solves (rot_vote_solve_batch) against the CPU oracle, instance
+by instance.  Every instance of a batch must give exactly what the oracle
+gives on its own columns: vote grid, candidates, candidate inlier counts,
+winner, rotation bits, inlier count and mask.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2506_11547_amd import datagen
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def rv():
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    from paper_2506_11547_amd import rotvote
+    return rotvote
+
+
+@pytest.fixture(scope="module")
+def orc():
+    return oracle.get()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def concat(instances):
+    offsets = np.zeros(len(instances) + 1, np.int64)
+    offsets[1:] = np.cumsum([x.shape[1] for x, _ in instances])
+    x = np.concatenate([x for x, _ in instances], axis=1) if offsets[-1] else np.zeros((3, 0), np.float32)
+    y = np.concatenate([y for _, y in instances], axis=1) if offsets[-1] else np.zeros((3, 0), np.float32)
+    return np.ascontiguousarray(x, np.float32), np.ascontiguousarray(y, np.float32), offsets
+
+
+def check_instance(rv, s, b, q, cnt, mask, x, y, G, J, eps_deg, K, orc, grids=True):
+    o = orc.solve(x, y, G, J, rv.eps_deg_to_rad(eps_deg), K)
+    if grids:
+        h = s.batch_histogram(b).cpu().numpy()
+        assert np.array_equal(h, o["hist"]), b
+    top = s.batch_topk(b)
+    assert top["votes"] == o["top_counts"].tolist(), b
+    assert top["idx"] == o["top_idx"].tolist(), b
+    assert top["inliers"] == o["cand_counts"].tolist(), b
+    assert top["winner"] == o["winner"], b
+    qb = np.array(q, np.float32)
+    assert np.array_equal(qb.view(np.uint32), o["q"].view(np.uint32)), b
+    assert cnt == o["count"], b
+    assert np.array_equal(mask, o["mask"]), b
+
+
+def mixed_instances(seed):
+    r = np.random.default_rng(seed)
+    sizes = [0, 1, 5, 511, 512, 513, 1000, 3000, 0, 77, 1025, 2]
+    out = []
+    for k, n in enumerate(sizes):
+        inst = datagen.make_instance(n, float(r.uniform(0.3, 0.95)), 0.5, seed * 100 + k,
+                                     radii=(0.5, 2.0))
+        out.append((inst.x, inst.y))
+    return out
+
+
+@pytest.mark.parametrize("G,J,K", [(1, 5, 4), (8, 64, 16), (33, 241, 8), (64, 512, 16),
+                                   (64, 300, 64)])
+def test_mixed_batch_matches_oracle(rv, orc, G, J, K):
+    inst = mixed_instances(G)
+    x, y, offs = concat(inst)
+    eps = 1.5
+    with rv.Solver(max_n=int(offs[-1]), max_grid=G, topk=K, samples_per_circle=J,
+                   max_batch=len(inst), batch_grids=True) as s:
+        q, cnt, mask = s.solve_batch(dev(x), dev(y), offs, G, eps)
+        m = mask.cpu().numpy()
+        for b, (xb, yb) in enumerate(inst):
+            check_instance(rv, s, b, q[b], cnt[b], m[offs[b]:offs[b + 1]], xb, yb, G, J, eps, K,
+                           orc)
+
+
+def test_handle_reuse_and_smaller_second_batch(rv, orc):
+    """Queue fills, overflow flags and overflow grids must be clean for the
+    next batch, which here has fewer instances and another grid."""
+    first = mixed_instances(7)
+    second = first[6:9] + [(datagen.make_instance(4000, 0.6, 0.5, 71).x,
+                            datagen.make_instance(4000, 0.6, 0.5, 71).y)]
+    with rv.Solver(max_n=20000, max_grid=64, topk=16, max_batch=16, batch_grids=True) as s:
+        for inst, G in ((first, 64), (second, 40), (first, 64)):
+            x, y, offs = concat(inst)
+            J = 8 * G
+            q, cnt, mask = s.solve_batch(dev(x), dev(y), offs, G, 1.0)
+            m = mask.cpu().numpy()
+            for b, (xb, yb) in enumerate(inst):
+                check_instance(rv, s, b, q[b], cnt[b], m[offs[b]:offs[b + 1]], xb, yb, G, J, 1.0,
+                               16, orc)
+
+
+def test_batch_queue_overflow_is_exact(rv, orc):
+    """One instance repeats a single correspondence, so its heaviest bricks get
+    several times the planned share of runs and the excess takes the
+    per-instance overflow grid; neighbours in the batch must be unaffected."""
+    n = 6000
+    xr = np.tile(np.float32([[0.3], [-0.5], [0.8]]), (1, n))
+    yr = np.tile(np.float32([[0.9], [0.1], [-0.2]]), (1, n))
+    a = datagen.make_instance(3000, 0.8, 0.5, 21)
+    c = datagen.make_instance(2500, 0.5, 0.5, 22)
+    inst = [(a.x, a.y), (xr, yr), (c.x, c.y), (xr[:, :1500], yr[:, :1500])]
+    x, y, offs = concat(inst)
+    with rv.Solver(max_n=int(offs[-1]), max_grid=64, topk=16, max_batch=4, batch_grids=True) as s:
+        for _ in range(2):  # overflow grids must be left zeroed
+            q, cnt, mask = s.solve_batch(dev(x), dev(y), offs, 64, 1.0)
+            m = mask.cpu().numpy()
+            for b, (xb, yb) in enumerate(inst):
+                check_instance(rv, s, b, q[b], cnt[b], m[offs[b]:offs[b + 1]], xb, yb, 64, 512,
+                               1.0, 16, orc)
+
+
+def test_batch_equals_single_solves(rv):
+    inst = mixed_instances(3)
+    x, y, offs = concat(inst)
+    with rv.Solver(max_n=int(offs[-1]), max_grid=64, topk=16, max_batch=len(inst)) as s:
+        q, cnt, mask = s.solve_batch(dev(x), dev(y), offs, 64, 1.0)
+        mb = mask.cpu().numpy()
+        for b, (xb, yb) in enumerate(inst):
+            q1, c1, m1 = s.solve(dev(xb), dev(yb), 64, 1.0)
+            assert q1 == q[b] and c1 == cnt[b], b
+            assert np.array_equal(m1.cpu().numpy(), mb[offs[b]:offs[b + 1]]), b
+
+
+def test_full_batch_workload_sampled(rv, orc):
+    """The 4096-instance batch (N log-uniform on [100, 20000]) in the
+    configuration the benchmark times (no grids kept): sampled instances,
+    including the smallest and largest, against the oracle."""
+    w = datagen.BATCH_WORKLOADS["batch"]
+    bt = w.batch()
+    n = int(bt.offsets[-1])
+    sizes = np.diff(bt.offsets)
+    with rv.Solver(max_n=n, max_grid=w.grid, topk=w.topk, samples_per_circle=w.samples,
+                   max_batch=bt.B) as s:
+        q, cnt, mask = s.solve_batch(dev(bt.x), dev(bt.y), bt.offsets, w.grid, w.eps_deg)
+        m = mask.cpu().numpy()
+        bound = 4 * math.sqrt(3) / w.grid * 180 / math.pi
+        err = np.array([datagen.rotation_error_deg(np.array(q[b]), bt.q_gt[b])
+                        for b in range(bt.B)])
+        enough = sizes * (1 - bt.outlier_ratio) >= 50
+        worst_enough = int(np.flatnonzero(enough)[np.argmax(err[enough])])
+        r = np.random.default_rng(0)
+        # sampled parity, including the smallest and largest instances and the
+        # least accurate ones (so that an accuracy miss is the method's, not the kernels')
+        pick = sorted(set([int(np.argmin(sizes)), int(np.argmax(sizes)), 0, bt.B - 1,
+                           int(np.argmax(err)), worst_enough] +
+                          r.choice(bt.B, 12, replace=False).tolist()))
+        for b in pick:
+            xb, yb = bt.instance(b)
+            check_instance(rv, s, b, q[b], cnt[b], m[bt.offsets[b]:bt.offsets[b + 1]], xb, yb,
+                           w.grid, w.samples, w.eps_deg, w.topk, orc, grids=False)
+        # every instance: the mask agrees with the count, the rotation is canonical
+        for b in range(bt.B):
+            assert int(m[bt.offsets[b]:bt.offsets[b + 1]].sum()) == cnt[b]
+            assert q[b][0] >= 0.0
+        # accuracy: the centre of the true rotation's cell is within 4 sqrt(3) / G
+        # rad of it (half a cell diagonal in the chart, at most doubled by the
+        # inverse projection, doubled again from quaternion to rotation angle);
+        # with noise the peak may be a neighbouring cell.  At 99 % outliers a
+        # few instances with about 50 inliers lose to an outlier peak.
+        assert np.mean(err[enough] < 3 * bound) > 0.99, np.sort(err[enough])[-5:]
+        assert np.mean(err < bound) > 0.95, np.mean(err < bound)
+
+
+def test_batch_error_conventions(rv):
+    import ctypes as ct
+    with rv.Solver(max_n=100, max_grid=128, topk=4, max_batch=3) as s:
+        x = torch.randn(3, 100, device="cuda")
+        mask = torch.empty(100, dtype=torch.bool, device="cuda")
+        for offs, G, status in [([0, 10, 20, 30, 40], 16, rv.RV_EINVAL),   # B > max_batch
+                                ([0, 10, 5], 16, rv.RV_EINVAL),            # decreasing
+                                ([1, 10], 16, rv.RV_EINVAL),               # offsets[0] != 0
+                                ([0, 101], 16, rv.RV_EINVAL),              # beyond max_n
+                                ([0, 10], 65, rv.RV_EINVAL),               # grid > 64
+                                ([0, 10], 0, rv.RV_EINVAL)]:
+            with pytest.raises(rv.RotVoteError) as e:
+                s.solve_batch_raw(x.data_ptr(), x.data_ptr(), offs, G, 0.01, mask.data_ptr())
+            assert e.value.status == status, offs
+        q, c = s.solve_batch_raw(x.data_ptr(), x.data_ptr(), [0], 16, 0.01, mask.data_ptr())
+        assert q == [] and c == []
+        q, c, m = s.solve_batch(x, x, [0, 0, 0], 16, 1.0)
+        assert q == [[1.0, 0.0, 0.0, 0.0]] * 2 and c == [0, 0]
+    with rv.Solver(max_n=100, max_grid=32, topk=4) as s:
+        with pytest.raises(rv.RotVoteError) as e:
+            s.solve_batch(x, x, [0, 10], 16, 1.0)
+        assert e.value.status == rv.RV_EUNSUPPORTED
