@@ -56,6 +56,8 @@ def parse():
                     help="correspondences of the workload the CPU oracle times")
     ap.add_argument("--cpu-instances", type=int, default=1000,
                     help="batch workload: instances the CPU oracle times")
+    ap.add_argument("--no-loop", action="store_true",
+                    help="batch workload: skip the one-solve-per-call comparison")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run plain device-to-device copies of MIB MiB (profiler "
                          "calibration of the HBM byte counters) and exit")
@@ -137,6 +139,35 @@ def cpu_baseline_batch(w, bt, max_instances: int) -> dict:
                       f"solve each; vote loop on {threads} OpenMP threads; {dt:.2f} s"}
 
 
+def loop_baseline(args, w, bt, x, y, mask, stream, q, cnt) -> dict:
+    """The same instances, one rot_vote_solve call each (one timed pass after
+    an untimed pass over the first 64), on a handle made for single solves."""
+    import numpy as np
+    import torch
+
+    from paper_2506_11547_amd import rotvote
+    offs = bt.offsets.tolist()
+    single = rotvote.Solver(device=0, max_n=int(np.diff(bt.offsets).max()), max_grid=w.grid,
+                            topk=w.topk, samples_per_circle=w.samples, stream=stream)
+    views = [(x[:, offs[b]:offs[b + 1]], y[:, offs[b]:offs[b + 1]], mask[offs[b]:offs[b + 1]])
+             for b in range(bt.B)]
+    for xb, yb, mb in views[:64]:
+        single.solve(xb, yb, w.grid, w.eps_deg, mask=mb)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    same = 0
+    for b, (xb, yb, mb) in enumerate(views):
+        qb, cb, _ = single.solve(xb, yb, w.grid, w.eps_deg, mask=mb)
+        same += int(qb == q[b] and cb == cnt[b])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t1
+    plan = single.plan()
+    single.close()
+    samples = int(bt.offsets[-1]) * w.samples
+    return {"solves_per_s": bt.B / dt, "votes_per_s": samples / dt, "ms": dt * 1e3,
+            "vote_strategy": plan["strategy"], "identical_results": same}
+
+
 def run_batch(args):
     import numpy as np
     import torch
@@ -167,24 +198,9 @@ def run_batch(args):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
 
-    # The same instances one rot_vote_solve call each (one pass, after one
-    # untimed pass), on a handle made for single solves.
-    single = rotvote.Solver(device=0, max_n=int(np.diff(bt.offsets).max()), max_grid=w.grid,
-                            topk=w.topk, samples_per_circle=w.samples, stream=stream)
-    views = [(x[:, offs[b]:offs[b + 1]], y[:, offs[b]:offs[b + 1]], mask[offs[b]:offs[b + 1]])
-             for b in range(bt.B)]
-    for xb, yb, mb in views[:64]:
-        single.solve(xb, yb, w.grid, w.eps_deg, mask=mb)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    loop_same = 0
-    for b, (xb, yb, mb) in enumerate(views):
-        qb, cb, _ = single.solve(xb, yb, w.grid, w.eps_deg, mask=mb)
-        loop_same += int(qb == q[b] and cb == cnt[b])
-    torch.cuda.synchronize()
-    dt_loop = time.perf_counter() - t1
-    loop_plan = single.plan()
-    single.close()
+    loop = None
+    if not args.no_loop:
+        loop = loop_baseline(args, w, bt, x, y, mask, stream, q, cnt)
     solver.close()
 
     steps = args.steps
@@ -213,10 +229,8 @@ def run_batch(args):
                    "vote_strategy": "brick (batched)"},
         "solves_per_s": bt.B * steps / dt,
         "stage_ms": stage_ms,
-        "loop": {"solves_per_s": bt.B / dt_loop, "votes_per_s": samples / dt_loop,
-                 "ms": dt_loop * 1e3, "vote_strategy": loop_plan["strategy"],
-                 "identical_results": loop_same, "speedup_of_batch": (bt.B * steps / dt) /
-                 (bt.B / dt_loop)},
+        "loop": loop if loop is None else dict(loop, speedup_of_batch=(bt.B * steps / dt) /
+                                                  loop["solves_per_s"]),
         "roofline": {"bound": "alu", "kernel": "vote (batched)", "achieved": achieved / 1e3,
                      "peak": ALU_PEAK_GOPS / 1e3, "unit": "TOP/s", "frac": achieved / ALU_PEAK_GOPS,
                      "traffic": measured_traffic(w.name), "ops_per_sample": OPS_PER_SAMPLE,

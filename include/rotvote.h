@@ -159,7 +159,7 @@ rv_status rot_vote_get_plan(rv_handle *h, int32_t *samples_per_circle, int32_t *
  *   0 prepare  (global: clear the grid; brick: size the brick queues)
  *   1 vote     (sample every circle and accumulate or bin its votes)
  *   2 reduce   (global: per-block top-64 scan; brick: accumulate bricks in LDS,
- *               write the grid, per-brick top-64)
+ *               write the grid, per-brick list of the K best)
  *   3 top-K    (merge the lists, decode the K candidates)
  *   4 rescore  (exact inlier count of every candidate)
  *   5 mask     (winner, inlier mask, result record) */

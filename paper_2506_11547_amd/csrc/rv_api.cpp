@@ -476,7 +476,7 @@ RV_API rv_status rot_vote_solve(rv_handle* h, const float* x, const float* y, in
         RV_HIP(h, hipEventRecord(h->ev[2], s), "event");
     int nlists;
     if (brick) {
-        RV_HIP(h, rv::launch_brick_accum(grid, h->d_hist, h->d_partial, h->bin, s), "brick accumulate");
+        RV_HIP(h, rv::launch_brick_accum(grid, h->K, h->d_hist, h->d_partial, h->bin, s), "brick accumulate");
         const int nba = rv::brick_axis(grid);
         nlists = nba * nba * nba;
     } else {
@@ -642,7 +642,7 @@ RV_API rv_status rot_vote_solve_batch(rv_handle* h, const float* x, const float*
     RV_HIP(h, rv::launch_bin_vote_batch(x, y, n, grid, J, h->d_table, a, (int)nunits, s), "batch vote");
     if (tm)
         RV_HIP(h, hipEventRecord(h->ev[2], s), "event");
-    RV_HIP(h, rv::launch_brick_accum(grid, h->batch_grids ? h->d_bgrids : nullptr, h->d_bpartial, a, s),
+    RV_HIP(h, rv::launch_brick_accum(grid, h->K, h->batch_grids ? h->d_bgrids : nullptr, h->d_bpartial, a, s),
            "batch brick accumulate");
     if (tm)
         RV_HIP(h, hipEventRecord(h->ev[3], s), "event");

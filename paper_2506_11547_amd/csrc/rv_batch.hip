@@ -2,7 +2,7 @@
 // contiguous column range of one SoA input.  The binned vote and the brick
 // accumulation are the one-solve kernels run over (instance, unit) and
 // (instance, brick); these kernels finish each instance: merge its bricks'
-// top-64 lists, rescore its candidates on its own correspondences, pick its
+// sorted lists, rescore its candidates on its own correspondences, pick its
 // winner and write its mask and result record.
 #include "rv_device.h"
 #include "rv_internal.h"

@@ -5,12 +5,12 @@
 // CU's LDS).  Each vote run (a cell and how many consecutive samples of one
 // circle fell in it) is routed to its brick's queue in HBM; a second kernel
 // accumulates each brick's queue in LDS and writes the finished brick out once,
-// keeping its 64 best cells for the top-K stage.
+// keeping its K best cells for the top-K stage.
 //
 //   k_bin_estimate  every 32nd circle, runs counted per brick (queue sizing)
 //   k_bin_plan      queue capacities and offsets in the run pool
 //   k_vote_bin      all circles: sample, bin (LDS staging), append to queues
-//   k_brick_accum   per brick: LDS histogram, write-out, top-64 list
+//   k_brick_accum   per brick: LDS histogram, write-out, sorted list of its K best
 //
 // Queues are kept per XCD (blockIdx % 8), so the reservation atomics and the
 // partial-line writes of a queue tail stay in one XCD's L2.  A queue that
@@ -353,12 +353,13 @@ __global__ __launch_bounds__(kBinThreads, 2) void k_vote_bin(const float* __rest
 
 // ----------------------------------------------------------- accumulate
 
-__global__ __launch_bounds__(kAccumThreads, 1) void k_brick_accum(BinArgs a, int G, int nba,
+__global__ __launch_bounds__(kAccumThreads, 1) void k_brick_accum(BinArgs a, int G, int nba, int K,
                                                                    int32_t* __restrict__ grid,
                                                                    uint64_t* __restrict__ partial)
 {
     __shared__ uint32_t acc[kBrickCells];
     __shared__ uint64_t lists[kAccumWaves][kWave];
+    __shared__ uint32_t s_floor;
     const int nb = nba * nba * nba;
     int inst, b;
     if (a.batch) {
@@ -377,6 +378,8 @@ __global__ __launch_bounds__(kAccumThreads, 1) void k_brick_accum(BinArgs a, int
     uint4* acc4 = reinterpret_cast<uint4*>(acc);
     for (int k = threadIdx.x; k < kBrickCells / 4; k += kAccumThreads)
         acc4[k] = make_uint4(0u, 0u, 0u, 0u);
+    if (threadIdx.x == 0)
+        s_floor = 0u;
     __syncthreads();
 
     const uint32_t cap = a.cap[qoff + b];
@@ -422,20 +425,20 @@ __global__ __launch_bounds__(kAccumThreads, 1) void k_brick_accum(BinArgs a, int
     }
     __syncthreads();
 
+    // Pass 1: final counts (overflow runs added and written back to LDS), the
+    // grid, and each lane's largest count.
     const bool overflowed = a.flags[qoff + b] != 0u;
     const bool vec = (G % 4) == 0;
-    uint64_t list = 0;
+    uint32_t lmax = 0;
     for (int c = threadIdx.x * 4; c < kBrickCells; c += kAccumThreads * 4) {
         const int lx = c & 31, ly = (c >> 5) & 31, lz = c >> 10;
         const int gx = bx * kEdge + lx, gy = by * kEdge + ly, gz = bz * kEdge + lz;
         uint32_t val[4] = {0u, 0u, 0u, 0u};
-        uint32_t idx0 = 0;
         const bool row = gy < G && gz < G;
         if (row) {
             const uint4 v4 = acc4[c >> 2];
             val[0] = v4.x; val[1] = v4.y; val[2] = v4.z; val[3] = v4.w;
             const int64_t g0 = ((int64_t)gz * G + gy) * G + gx;
-            idx0 = (uint32_t)g0;
             if (overflowed) {
 #pragma unroll
                 for (int s = 0; s < 4; ++s)
@@ -444,8 +447,10 @@ __global__ __launch_bounds__(kAccumThreads, 1) void k_brick_accum(BinArgs a, int
                         a.ovf[gofs + g0 + s] = 0;
                     }
             }
+            if (overflowed)
+                acc4[c >> 2] = make_uint4(val[0], val[1], val[2], val[3]);
             if (grid == nullptr) {
-                // batch without grids: only the top-64 list leaves the CU
+                // batch without grids: only the brick's list leaves the CU
             } else if (vec && gx + 3 < G) {
                 *reinterpret_cast<int4*>(grid + gofs + g0) =
                     make_int4((int)val[0], (int)val[1], (int)val[2], (int)val[3]);
@@ -456,10 +461,35 @@ __global__ __launch_bounds__(kAccumThreads, 1) void k_brick_accum(BinArgs a, int
                         grid[gofs + g0 + s] = (int32_t)val[s];
             }
         }
+        // cells past the grid's edge hold 0 and cannot raise the maximum
+        lmax = max(lmax, max(max(val[0], val[1]), max(val[2], val[3])));
+    }
+    // A floor for the top K: the K largest lane maxima of one wave are counts
+    // of K distinct cells, so the brick's K-th largest count is at least the
+    // K-th largest lane maximum of every wave.  Cells below the floor cannot
+    // be among the brick's K best and skip the list.
+    const uint32_t kth = (uint32_t)lane_u64(wave_sort_desc((uint64_t)lmax, lane), K - 1);
+    if (lane == 0)
+        atomicMax(&s_floor, kth);
+    __syncthreads();
+    const uint32_t floor_k = max(s_floor, 1u);
+
+    // Pass 2: the sorted list of the brick's best cells at or above the floor.
+    uint64_t list = 0;
+    for (int c = threadIdx.x * 4; c < kBrickCells; c += kAccumThreads * 4) {
+        const int lx = c & 31, ly = (c >> 5) & 31, lz = c >> 10;
+        const int gx = bx * kEdge + lx, gy = by * kEdge + ly, gz = bz * kEdge + lz;
+        const bool row = gy < G && gz < G;
+        const uint4 v4 = acc4[c >> 2];
+        const uint32_t val[4] = {v4.x, v4.y, v4.z, v4.w};
+        const bool hit = row && max(max(val[0], val[1]), max(val[2], val[3])) >= floor_k;
+        if (__ballot(hit) == 0)  // the common case: no cell of the wave's 256 qualifies
+            continue;
+        const uint32_t idx0 = (uint32_t)(((int64_t)gz * G + gy) * G + gx);
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
-            const bool in = row && gx + s < G;
-            list = wave_insert(list, in ? cell_key(val[s], idx0 + s) : 0ull, lane);
+            const bool in = row && gx + s < G && val[s] >= floor_k;
+            list = wave_insert_top(list, in ? cell_key(val[s], idx0 + s) : 0ull, lane, K);
         }
     }
     list = block_merge<kAccumWaves>(list, lists, wave, lane);
@@ -518,7 +548,7 @@ hipError_t launch_bin_vote(const float* x, const float* y, int64_t n, int G, int
     return hipGetLastError();
 }
 
-hipError_t launch_brick_accum(int G, int32_t* grid, uint64_t* partial, const BinArgs& a,
+hipError_t launch_brick_accum(int G, int K, int32_t* grid, uint64_t* partial, const BinArgs& a,
                               hipStream_t s)
 {
     const int nba = brick_axis(G);
@@ -526,7 +556,9 @@ hipError_t launch_brick_accum(int G, int32_t* grid, uint64_t* partial, const Bin
     if (G > kMaxBrickGrid || nb > kMaxBricks)
         return hipErrorInvalidValue;
     const int blocks = a.batch ? a.batch * nb : nb;
-    hipLaunchKernelGGL(k_brick_accum, dim3(blocks), dim3(kAccumThreads), 0, s, a, G, nba, grid,
+    if (K < 1 || K > kWave)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_brick_accum, dim3(blocks), dim3(kAccumThreads), 0, s, a, G, nba, K, grid,
                        partial);
     return hipGetLastError();
 }

@@ -74,12 +74,13 @@ struct BinArgs {
 
 int brick_axis(int G);
 // estimate + plan (queue capacities); then the binned vote; then per-brick
-// accumulation, which writes every cell of the grid and one top-64 list per brick
+// accumulation, which writes every cell of the grid and one sorted list per
+// brick that holds the brick's K best cells
 hipError_t launch_bin_prepare(const float* x, const float* y, int64_t n, int G, int J,
                               const float2* table, const BinArgs& a, hipStream_t s);
 hipError_t launch_bin_vote(const float* x, const float* y, int64_t n, int G, int J,
                            const float2* table, const BinArgs& a, hipStream_t s);
-hipError_t launch_brick_accum(int G, int32_t* grid, uint64_t* partial, const BinArgs& a,
+hipError_t launch_brick_accum(int G, int K, int32_t* grid, uint64_t* partial, const BinArgs& a,
                               hipStream_t s);
 
 // Batches (G <= kMaxBatchGrid): the binned vote over work units, then the

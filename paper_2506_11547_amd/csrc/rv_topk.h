@@ -104,6 +104,19 @@ __device__ __forceinline__ uint64_t wave_insert(uint64_t list, uint64_t key, int
     return wave_insert_each(list, key, m, lane);
 }
 
+// Same, for a list whose first K lanes are all that matter: keys that do not
+// beat lane K-1 are skipped (lanes K..63 then hold sorted leftovers, real
+// keys that no longer matter; lanes 0..K-1 stay the K best keys seen).
+__device__ __forceinline__ uint64_t wave_insert_top(uint64_t list, uint64_t key, int lane, int K)
+{
+    const uint64_t m = __ballot(key > lane_u64(list, K - 1));
+    if (m == 0)
+        return list;
+    if (__popcll(m) > 12)
+        return wave_merge_sorted(list, wave_sort_desc(key, lane), lane);
+    return wave_insert_each(list, key, m, lane);
+}
+
 // Same for a batch that is already sorted descending across the lanes.
 __device__ __forceinline__ uint64_t wave_insert_sorted(uint64_t list, uint64_t sorted, int lane)
 {
@@ -115,15 +128,24 @@ __device__ __forceinline__ uint64_t wave_insert_sorted(uint64_t list, uint64_t s
     return wave_insert_each(list, sorted, m, lane);
 }
 
-// Merges the lists of the block's waves (through LDS) into wave 0's list.
+// Merges the lists of the block's waves (through LDS) into wave 0's list, as
+// a tree: in each round the lower half of the remaining waves merges in the
+// upper half's lists (log2(kWaves) rounds instead of kWaves - 1 merges in one
+// wave while the others wait).
 template <int kWaves>
 __device__ __forceinline__ uint64_t block_merge(uint64_t list, uint64_t (*lists)[64], int wave, int lane)
 {
+    static_assert((kWaves & (kWaves - 1)) == 0, "power-of-two wave count");
     lists[wave][lane] = list;
     __syncthreads();
-    if (wave == 0) {
-        for (int w = 1; w < kWaves; ++w)
-            list = wave_insert_sorted(list, lists[w][lane], lane);
+#pragma unroll
+    for (int half = kWaves / 2; half >= 1; half >>= 1) {
+        // round readers use waves [half, 2 half), writers [0, half)
+        if (wave < half) {
+            list = wave_insert_sorted(list, lists[wave + half][lane], lane);
+            lists[wave][lane] = list;
+        }
+        __syncthreads();
     }
     return list;
 }
