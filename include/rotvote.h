@@ -62,7 +62,13 @@ enum {
     RV_FLAG_BATCH_GRIDS = 2u   /* keep every batch instance's vote grid (test hook) */
 };
 
-enum { RV_MAX_TOPK = 64, RV_MAX_GRID = 1024, RV_NUM_STAGES = 6, RV_MAX_BATCH_GRID = 64 };
+enum {
+    RV_MAX_TOPK = 64,
+    RV_MAX_GRID = 1024,
+    RV_NUM_STAGES = 6,
+    RV_MAX_BATCH_GRID = 64,
+    RV_MAX_REFINE_ROUNDS = 64
+};
 
 typedef struct rv_config {
     int32_t device;              /* HIP device ordinal */
@@ -113,6 +119,28 @@ rv_status rot_vote_set_stream(rv_handle *h, void *stream);
 rv_status rot_vote_solve(rv_handle *h, const float *x, const float *y, int64_t n, int32_t grid,
                          float eps_rad, float q_out[4], int64_t *inlier_count,
                          uint8_t *inlier_mask);
+
+/* Least-squares refinement on an inlier set (Sec. 4.2: the eigenvector of
+ * Q^T Q with the smallest eigenvalue, Q stacking the two hyperplane normals
+ * of every inlier's circle).  A round solves on the correspondences whose mask
+ * entry is nonzero, then rescores the refined rotation (|L_i q|^2 <= T2, as a
+ * solve does) into the mask; rounds repeat until a rescoring changes no mask
+ * entry or max_rounds have run.  A round whose system is ill-posed (its two
+ * smallest eigenvalues within 1e-6 * max(1, m) of each other, m the
+ * correspondences used: one correspondence, parallel ones, none) keeps the
+ * current rotation.  Normals, sums and the 4x4 eigenproblem are float64; the
+ * rotation is returned rounded to float32 with w >= 0.
+ *   q_io          host float[4]: in, the rotation kept by an ill-posed round
+ *                 (typically a solve's q); out, the refined rotation.
+ *   inlier_count  host int64: inliers of the returned rotation.
+ *   inlier_mask   device uint8[n]: in, the inlier set of the first round (any
+ *                 nonzero entry); out, the inliers of the returned rotation.
+ *   max_rounds    1..RV_MAX_REFINE_ROUNDS; rounds_run (host, may be NULL)
+ *                 receives the rounds that ran before convergence.
+ * n = 0 returns q_io unchanged and count 0.  Synchronous on the handle's stream. */
+rv_status rot_vote_refine(rv_handle *h, const float *x, const float *y, int64_t n, float eps_rad,
+                          int32_t max_rounds, float q_io[4], int64_t *inlier_count,
+                          uint8_t *inlier_mask, int32_t *rounds_run);
 
 /* Many independent solves in one pass (Alg. 1 and the rescoring for each
  * instance; the instances share grid, J, K and eps).  Instance b is the

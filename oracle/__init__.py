@@ -51,6 +51,8 @@ class Oracle:
         L.orc_residual_bound.restype = ct.c_float
         L.orc_normalise.argtypes = [_f32p, _f32p]
         L.orc_normalise.restype = ct.c_int32
+        L.orc_normalise_pairs.argtypes = [_f32p, _f32p, ct.c_int64, _f32p, _f32p, _u8p]
+        L.orc_normalise_pairs.restype = None
         L.orc_circle_basis.argtypes = [_f32p, _f32p, _f32p, _f32p]
         L.orc_circle_basis.restype = ct.c_int32
         L.orc_cell_of.argtypes = [_f32p, ct.c_int32, _f32p, _f32p, _i32p]
@@ -87,6 +89,17 @@ class Oracle:
         out = np.zeros(3, np.float32)
         ok = self.lib.orc_normalise(np.ascontiguousarray(v, np.float32), out)
         return bool(ok), out
+
+    def normalise_pairs(self, x, y):
+        """Step 1 for SoA [3, n] arrays: (a, b, ok) with a, b float32 [3, n]."""
+        x = np.ascontiguousarray(x, np.float32)
+        y = np.ascontiguousarray(y, np.float32)
+        n = x.shape[1]
+        a = np.empty((3, n), np.float32)
+        b = np.empty((3, n), np.float32)
+        ok = np.empty(n, np.uint8)
+        self.lib.orc_normalise_pairs(x, y, n, a, b, ok)
+        return a, b, ok.astype(bool)
 
     def circle_basis(self, a, b):
         u = np.empty(4, np.float32)

@@ -63,6 +63,26 @@ int32_t orc_normalise(const float v[3], float out[3])
     return 1;
 }
 
+void orc_normalise_pairs(const float *x, const float *y, int64_t n, float *a, float *b,
+                         uint8_t *ok)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        float xi[3] = {x[i], x[n + i], x[2 * n + i]};
+        float yi[3] = {y[i], y[n + i], y[2 * n + i]};
+        float ai[3] = {0.0f, 0.0f, 0.0f}, bi[3] = {0.0f, 0.0f, 0.0f};
+        int32_t good = orc_normalise(xi, ai) && orc_normalise(yi, bi);
+        if (!good) {
+            ai[0] = ai[1] = ai[2] = 0.0f;
+            bi[0] = bi[1] = bi[2] = 0.0f;
+        }
+        for (int c = 0; c < 3; ++c) {
+            a[c * n + i] = ai[c];
+            b[c * n + i] = bi[c];
+        }
+        ok[i] = (uint8_t)good;
+    }
+}
+
 /* ---- Step 2: circle basis ---------------------------------------------- */
 
 /* App. A: q^T M q = b^T R(q) a with M symmetric, eigenvalues (1,1,-1,-1);

@@ -25,6 +25,11 @@ float orc_residual_bound(float eps_rad);
 /* Step 1: returns 1 and writes the unit vector when the input is usable. */
 int32_t orc_normalise(const float v[3], float out[3]);
 
+/* Step 1 over SoA arrays [3][n]: unit a_i, b_i (zero when unusable) and the
+ * usable flag of every correspondence. */
+void orc_normalise_pairs(const float *x, const float *y, int64_t n, float *a, float *b,
+                         uint8_t *ok);
+
 /* Step 2: circle basis (u, v) of R q a = b; returns k*, the column used. */
 int32_t orc_circle_basis(const float a[3], const float b[3], float u[4], float v[4]);
 

@@ -87,6 +87,11 @@ struct rv_handle {
     int32_t* d_bovf = nullptr;          // max_batch * batch_grid^3, zero between batches
     int32_t* d_bgrids = nullptr;        // max_batch * batch_grid^3 (RV_FLAG_BATCH_GRIDS)
 
+    // refinement
+    rv::RefineState* d_rstate = nullptr;
+    rv::RefineState* h_rstate = nullptr;  // pinned
+    double* d_rpartial = nullptr;         // kRefineMaxBlocks * kRefineSums
+
     hipEvent_t ev[kStages + 1] = {};
     bool timing = false;
     bool events_recorded = false;
@@ -176,6 +181,9 @@ void release(rv_handle* h)
     (void)hipFree(h->d_bresult);
     (void)hipFree(h->d_bovf);
     (void)hipFree(h->d_bgrids);
+    (void)hipFree(h->d_rstate);
+    (void)hipFree(h->d_rpartial);
+    (void)hipHostFree(h->h_rstate);
     (void)hipHostFree(h->h_units);
     (void)hipHostFree(h->h_bplan);
     (void)hipHostFree(h->h_offsets);
@@ -299,6 +307,12 @@ RV_API rv_status rot_vote_create(rv_handle** out, const rv_config* cfg)
     for (auto& ev : h->ev)
         if ((e = hipEventCreate(&ev)) != hipSuccess)
             return bail(e, "events");
+    if ((e = hipMalloc(&h->d_rstate, sizeof(rv::RefineState))) != hipSuccess ||
+        (e = hipMalloc(&h->d_rpartial,
+                       (size_t)rv::kRefineMaxBlocks * rv::kRefineSums * sizeof(double))) != hipSuccess)
+        return bail(e, "refinement scratch");
+    if ((e = hipHostMalloc(&h->h_rstate, sizeof(rv::RefineState), hipHostMallocDefault)) != hipSuccess)
+        return bail(e, "pinned refinement state");
     h->max_batch = cfg->max_batch;
     h->batch_grid = std::min(h->max_grid, rv::kMaxBatchGrid);
     h->batch_grids = (cfg->flags & RV_FLAG_BATCH_GRIDS) != 0;
@@ -516,6 +530,51 @@ RV_API rv_status rot_vote_solve(rv_handle* h, const float* x, const float* y, in
     h->last_ncand = r.n_cand;
     h->last_winner = r.winner;
     h->last_count = r.count;
+    return RV_OK;
+}
+
+RV_API rv_status rot_vote_refine(rv_handle* h, const float* x, const float* y, int64_t n,
+                                 float eps_rad, int32_t max_rounds, float q_io[4],
+                                 int64_t* inlier_count, uint8_t* inlier_mask, int32_t* rounds_run)
+{
+    if (!h)
+        return RV_EINVAL;
+    h->err.clear();
+    if (!q_io || !inlier_count)
+        return fail(h, RV_EINVAL, "rot_vote_refine: q_io and inlier_count must not be NULL");
+    if (n < 0 || n > h->max_n)
+        return fail(h, RV_EINVAL, "rot_vote_refine: n outside 0..max_n");
+    if (!(eps_rad > 0.0f) || !(eps_rad <= (float)M_PI))
+        return fail(h, RV_EINVAL, "rot_vote_refine: eps_rad outside (0, pi]");
+    if (max_rounds < 1 || max_rounds > RV_MAX_REFINE_ROUNDS)
+        return fail(h, RV_EINVAL, "rot_vote_refine: max_rounds outside 1..64");
+    for (int k = 0; k < 4; ++k)
+        if (!std::isfinite(q_io[k]))
+            return fail(h, RV_EINVAL, "rot_vote_refine: q_io must be finite");
+    if (n == 0) {
+        *inlier_count = 0;
+        if (rounds_run)
+            *rounds_run = 0;
+        return RV_OK;
+    }
+    if (!x || !y || !inlier_mask)
+        return fail(h, RV_EINVAL, "rot_vote_refine: x, y and inlier_mask must not be NULL");
+    if (!is_device_memory(x) || !is_device_memory(y) || !is_device_memory(inlier_mask))
+        return fail(h, RV_EINVAL, "rot_vote_refine: x, y and inlier_mask must be device memory");
+    RV_HIP(h, hipSetDevice(h->device), "hipSetDevice");
+    hipStream_t s = h->stream;
+    RV_HIP(h, rv::launch_refine(x, y, n, residual_bound(eps_rad), max_rounds, q_io, inlier_mask,
+                                h->d_rstate, h->d_rpartial, s),
+           "refine");
+    RV_HIP(h, hipMemcpyAsync(h->h_rstate, h->d_rstate, sizeof(rv::RefineState),
+                             hipMemcpyDeviceToHost, s),
+           "refine readback");
+    RV_HIP(h, hipStreamSynchronize(s), "sync");
+    const rv::RefineState& st = *h->h_rstate;
+    std::memcpy(q_io, st.q, sizeof(st.q));
+    *inlier_count = (int64_t)st.count;
+    if (rounds_run)
+        *rounds_run = st.rounds;
     return RV_OK;
 }
 

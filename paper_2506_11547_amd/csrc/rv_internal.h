@@ -95,6 +95,28 @@ hipError_t launch_batch_finish(const float* x, const float* y, int64_t n, float 
                                const int64_t* offsets, const Candidates& c, uint8_t* mask,
                                hipStream_t s, hipEvent_t after_topk, hipEvent_t after_rescore);
 
+// Least-squares refinement on an inlier set (Sec. 4.2): device-resident state
+// of the rounds (rotation, counts, convergence), float64 block partials of the
+// 10 distinct entries of sum_i M_i and the inlier count.
+struct RefineState {
+    float q[4];
+    uint32_t done;        // the last round changed no mask entry
+    uint32_t ill_posed;   // the last solve kept the previous rotation
+    uint64_t count;       // inliers of the current rotation
+    uint64_t count_next;  // accumulators of the running round
+    uint64_t changed;
+    int64_t m;            // correspondences in the last solve
+    int32_t rounds;       // rounds that ran (a converged round ends the rest)
+    int32_t reserved;
+};
+constexpr int kRefineSums = 11;
+constexpr int kRefineMaxBlocks = 1024;
+constexpr double kRefineGapRel = 1e-6;  // ill-posed: two smallest eigenvalues this close (x max(1, m))
+int refine_blocks(int64_t n);
+hipError_t launch_refine(const float* x, const float* y, int64_t n, float T2, int rounds,
+                         const float q_in[4], uint8_t* mask, RefineState* st, double* partial,
+                         hipStream_t s);
+
 hipError_t launch_rescore(const float* x, const float* y, int64_t n, float T2,
                           const Candidates& c, hipStream_t s);
 hipError_t launch_mask(const float* x, const float* y, int64_t n, float T2, const Candidates& c,

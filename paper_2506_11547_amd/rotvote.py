@@ -28,6 +28,7 @@ FLAG_TIMING = 1
 FLAG_BATCH_GRIDS = 2
 MAX_TOPK = 64
 MAX_BATCH_GRID = 64
+MAX_REFINE_ROUNDS = 64
 NUM_STAGES = 6
 STAGE_NAMES = ("prepare", "vote", "reduce", "topk", "rescore", "mask")
 
@@ -36,7 +37,7 @@ EXPORTS = ("rot_vote_default_config", "rot_vote_create", "rot_vote_destroy",
            "rot_vote_last_error", "rot_vote_set_stream", "rot_vote_solve",
            "rot_vote_get_histogram", "rot_vote_get_topk", "rot_vote_get_plan",
            "rot_vote_get_timings", "rot_vote_solve_batch", "rot_vote_get_batch_histogram",
-           "rot_vote_get_batch_topk")
+           "rot_vote_get_batch_topk", "rot_vote_refine")
 
 
 class RvConfig(ct.Structure):
@@ -97,6 +98,9 @@ def load_library(path: Path | str = LIB_PATH) -> ct.CDLL:
                                           ct.POINTER(i32 * MAX_TOPK), ct.POINTER(i64 * MAX_TOPK),
                                           ct.POINTER(i32)]
     L.rot_vote_get_batch_topk.restype = i32
+    L.rot_vote_refine.argtypes = [vp, vp, vp, i64, f32, i32, ct.POINTER(f32 * 4), ct.POINTER(i64),
+                                  vp, ct.POINTER(i32)]
+    L.rot_vote_refine.restype = i32
     _lib = L
     return L
 
@@ -196,6 +200,37 @@ class Solver:
         q, cnt = self.solve_raw(x.data_ptr(), y.data_ptr(), n, grid, eps_deg_to_rad(eps_deg),
                                 mask.data_ptr() if n else 0)
         return q, cnt, mask
+
+    def refine_raw(self, x_ptr: int, y_ptr: int, n: int, eps_rad: float, max_rounds: int,
+                   q_in, mask_ptr: int):
+        """Direct C-ABI call; the mask at mask_ptr is read and rewritten.
+        Returns (q, count, rounds_run)."""
+        q = (ct.c_float * 4)(*[float(v) for v in q_in])
+        cnt = ct.c_int64()
+        rounds = ct.c_int32()
+        self._check(self._lib.rot_vote_refine(self._h, ct.c_void_p(x_ptr), ct.c_void_p(y_ptr), n,
+                                              ct.c_float(eps_rad), max_rounds, ct.byref(q),
+                                              ct.byref(cnt), ct.c_void_p(mask_ptr),
+                                              ct.byref(rounds)))
+        return [q[0], q[1], q[2], q[3]], int(cnt.value), int(rounds.value)
+
+    def refine(self, x: torch.Tensor, y: torch.Tensor, q, mask: torch.Tensor, eps_deg: float,
+               max_rounds: int = 8):
+        """Least-squares refinement (Sec. 4.2) starting from the inlier set
+        `mask` (bool/uint8 [N] device tensor, rewritten in place) and the
+        rotation q (kept by an ill-posed round).  Returns (q, count, rounds)."""
+        for t, nm in ((x, "x"), (y, "y")):
+            if t.dtype != torch.float32 or t.dim() != 2 or t.shape[0] != 3 or not t.is_cuda:
+                raise ValueError(f"{nm} must be a float32 [3, N] device tensor")
+        if x.shape != y.shape or mask.numel() != x.shape[1] or mask.element_size() != 1:
+            raise ValueError("x, y must match and mask must be a 1-byte [N] tensor")
+        if not mask.is_contiguous():
+            raise ValueError("mask must be contiguous (it is rewritten in place)")
+        x = x.contiguous()
+        y = y.contiguous()
+        n = x.shape[1]
+        return self.refine_raw(x.data_ptr(), y.data_ptr(), n, eps_deg_to_rad(eps_deg), max_rounds,
+                               q, mask.data_ptr() if n else 0)
 
     def solve_batch_raw(self, x_ptr: int, y_ptr: int, offsets, grid: int, eps_rad: float,
                         mask_ptr: int):

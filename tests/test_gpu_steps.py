@@ -131,3 +131,4 @@ def test_residual_matches_oracle(probe, orc):
         got = probe.residual(dev(x), dev(y), dev(q)).cpu().numpy()
         ref = np.array([orc.residual(x[:, i], y[:, i], q) for i in range(x.shape[1])], np.float32)
         assert np.array_equal(bits(got), bits(ref))
+
