@@ -243,6 +243,25 @@ def run_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def refine_leg(solver, x, y, q, mask, w, inst, reps: int = 5) -> dict:
+    """Least-squares refinement (up to 8 rounds) from the last solve's rotation
+    and inlier mask; wall time per call (synchronous) after one untimed call."""
+    import torch
+
+    from paper_2506_11547_amd import datagen
+    m = mask.clone()
+    solver.refine(x, y, q, m, w.eps_deg, max_rounds=8)
+    times = []
+    for _ in range(reps):
+        m = mask.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        qr, cr, rounds = solver.refine(x, y, q, m, w.eps_deg, max_rounds=8)
+        times.append(time.perf_counter() - t0)
+    return {"ms": sorted(times)[len(times) // 2] * 1e3, "rounds": rounds, "inliers": cr,
+            "q": qr, "e_R_deg": datagen.rotation_error_deg(qr, inst.q_gt)}
+
+
 def main():
     args = parse()
     if args.copy_calibration:
@@ -283,6 +302,7 @@ def main():
     dt = time.perf_counter() - t0
     plan = solver.plan()
     top = solver.topk()
+    refine = refine_leg(solver, x, y, q, mask, w, inst)
     solver.close()
 
     steps = args.steps
@@ -317,6 +337,7 @@ def main():
                      "vote_ms": stage_ms["vote"]},
         "result": {"q": q, "inliers": cnt, "e_R_deg": datagen.rotation_error_deg(q, inst.q_gt),
                    "winner": top["winner"], "true_inliers": int(inst.inlier.sum())},
+        "refine": refine,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, inst, args.cpu_sample)

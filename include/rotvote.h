@@ -120,6 +120,26 @@ rv_status rot_vote_solve(rv_handle *h, const float *x, const float *y, int64_t n
                          float eps_rad, float q_out[4], int64_t *inlier_count,
                          uint8_t *inlier_mask);
 
+/* Several rotations from one vote (Alg. 1 returning several high peaks; one
+ * cluster point per rotation motion in the scene).  The vote, top-K and decode
+ * are rot_vote_solve's; every candidate gets its exact inlier set (the solve's
+ * rescoring test).  Models are then chosen greedily: the candidate with the
+ * most inliers not claimed by an earlier model (ties to the earlier
+ * candidate) becomes the next model while that number is >= min_inliers; it
+ * claims those inliers and suppresses every candidate within sep_rad of it
+ * (|q_a . q_b| >= cos(sep_rad / 2), float32).  The first model is the single
+ * solve's result (rot_vote_get_topk reports the candidates' total counts).
+ *   max_models    1..topk;  sep_rad in [0, pi];  min_inliers >= 1.
+ *   q_out         host float[4 * max_models] (w >= 0), counts host
+ *                 int64[max_models] (claimed inliers), n_models host int32:
+ *                 entries past *n_models are untouched.
+ *   labels        device uint8[n]: 0 unclaimed, m + 1 claimed by model m.
+ * Synchronous on the handle's stream. */
+rv_status rot_vote_solve_multi(rv_handle *h, const float *x, const float *y, int64_t n,
+                               int32_t grid, float eps_rad, int32_t max_models, float sep_rad,
+                               int64_t min_inliers, float *q_out, int64_t *counts,
+                               int32_t *n_models, uint8_t *labels);
+
 /* Least-squares refinement on an inlier set (Sec. 4.2: the eigenvector of
  * Q^T Q with the smallest eigenvalue, Q stacking the two hyperplane normals
  * of every inlier's circle).  A round solves on the correspondences whose mask

@@ -87,6 +87,11 @@ struct rv_handle {
     int32_t* d_bovf = nullptr;          // max_batch * batch_grid^3, zero between batches
     int32_t* d_bgrids = nullptr;        // max_batch * batch_grid^3 (RV_FLAG_BATCH_GRIDS)
 
+    // several rotations
+    uint64_t* d_mbits = nullptr;          // max_n candidate sets
+    rv::MultiState* d_mstate = nullptr;
+    rv::MultiState* h_mstate = nullptr;   // pinned
+
     // refinement
     rv::RefineState* d_rstate = nullptr;
     rv::RefineState* h_rstate = nullptr;  // pinned
@@ -181,6 +186,9 @@ void release(rv_handle* h)
     (void)hipFree(h->d_bresult);
     (void)hipFree(h->d_bovf);
     (void)hipFree(h->d_bgrids);
+    (void)hipFree(h->d_mbits);
+    (void)hipFree(h->d_mstate);
+    (void)hipHostFree(h->h_mstate);
     (void)hipFree(h->d_rstate);
     (void)hipFree(h->d_rpartial);
     (void)hipHostFree(h->h_rstate);
@@ -313,6 +321,12 @@ RV_API rv_status rot_vote_create(rv_handle** out, const rv_config* cfg)
         return bail(e, "refinement scratch");
     if ((e = hipHostMalloc(&h->h_rstate, sizeof(rv::RefineState), hipHostMallocDefault)) != hipSuccess)
         return bail(e, "pinned refinement state");
+    if ((e = hipMalloc(&h->d_mbits, (size_t)std::max<int64_t>(1, h->max_n) * sizeof(uint64_t))) !=
+            hipSuccess ||
+        (e = hipMalloc(&h->d_mstate, sizeof(rv::MultiState))) != hipSuccess)
+        return bail(e, "model scratch");
+    if ((e = hipHostMalloc(&h->h_mstate, sizeof(rv::MultiState), hipHostMallocDefault)) != hipSuccess)
+        return bail(e, "pinned model state");
     h->max_batch = cfg->max_batch;
     h->batch_grid = std::min(h->max_grid, rv::kMaxBatchGrid);
     h->batch_grids = (cfg->flags & RV_FLAG_BATCH_GRIDS) != 0;
@@ -419,45 +433,51 @@ RV_API rv_status rot_vote_set_stream(rv_handle* h, void* stream)
     return RV_OK;
 }
 
-RV_API rv_status rot_vote_solve(rv_handle* h, const float* x, const float* y, int64_t n,
-                                int32_t grid, float eps_rad, float q_out[4],
-                                int64_t* inlier_count, uint8_t* inlier_mask)
+namespace {
+
+// Argument checks shared by the solve entry points; sets *J.
+rv_status check_solve(rv_handle* h, const char* fn, const float* x, const float* y, int64_t n,
+                      int32_t grid, float eps_rad, const void* out_mask, int32_t* J)
 {
-    if (!h)
-        return RV_EINVAL;
-    h->err.clear();
-    if (!q_out || !inlier_count)
-        return fail(h, RV_EINVAL, "rot_vote_solve: q_out and inlier_count must not be NULL");
+    const std::string f(fn);
     if (n < 0)
-        return fail(h, RV_EINVAL, "rot_vote_solve: n < 0");
+        return fail(h, RV_EINVAL, f + ": n < 0");
     if (n > h->max_n)
-        return fail(h, RV_EINVAL, "rot_vote_solve: n exceeds the handle's max_n");
+        return fail(h, RV_EINVAL, f + ": n exceeds the handle's max_n");
     if (grid < 1 || grid > h->max_grid)
-        return fail(h, RV_EINVAL, "rot_vote_solve: grid outside 1..max_grid");
+        return fail(h, RV_EINVAL, f + ": grid outside 1..max_grid");
     if (!(eps_rad > 0.0f) || !(eps_rad <= (float)M_PI))
-        return fail(h, RV_EINVAL, "rot_vote_solve: eps_rad outside (0, pi]");
-    const int32_t J = h->cfg.samples_per_circle > 0 ? h->cfg.samples_per_circle : 8 * grid;
-    if (J > h->max_J)
-        return fail(h, RV_EINVAL, "rot_vote_solve: J = 8*grid exceeds the table sized at create");
-    if ((int64_t)J * n > (int64_t)INT32_MAX)
-        return fail(h, RV_EUNSUPPORTED, "rot_vote_solve: n*J exceeds int32 vote counts");
+        return fail(h, RV_EINVAL, f + ": eps_rad outside (0, pi]");
+    *J = h->cfg.samples_per_circle > 0 ? h->cfg.samples_per_circle : 8 * grid;
+    if (*J > h->max_J)
+        return fail(h, RV_EINVAL, f + ": J = 8*grid exceeds the table sized at create");
+    if ((int64_t)*J * n > (int64_t)INT32_MAX)
+        return fail(h, RV_EUNSUPPORTED, f + ": n*J exceeds int32 vote counts");
     if (n > 0) {
-        if (!x || !y || !inlier_mask)
-            return fail(h, RV_EINVAL, "rot_vote_solve: x, y and inlier_mask must not be NULL");
-        if (!is_device_memory(x) || !is_device_memory(y) || !is_device_memory(inlier_mask))
-            return fail(h, RV_EINVAL, "rot_vote_solve: x, y and inlier_mask must be device memory");
+        if (!x || !y || !out_mask)
+            return fail(h, RV_EINVAL, f + ": x, y and the mask or labels must not be NULL");
+        if (!is_device_memory(x) || !is_device_memory(y) || !is_device_memory(out_mask))
+            return fail(h, RV_EINVAL, f + ": x, y and the mask or labels must be device memory");
     }
-    RV_HIP(h, hipSetDevice(h->device), "hipSetDevice");
+    return RV_OK;
+}
+
+// Stages 0-3 of a solve on the handle's stream: vote (either strategy),
+// reduce, and for n > 0 the decoded top-K candidates with cleared inlier
+// counters.  Records events 0..4 when timing.
+rv_status vote_candidates(rv_handle* h, const float* x, const float* y, int64_t n, int32_t grid,
+                          int32_t J, const char* fn)
+{
+    const std::string f(fn);
     hipStream_t s = h->stream;
     const int64_t ncell = (int64_t)grid * grid * grid;
-    const float T2 = residual_bound(eps_rad);
     int strategy = h->cfg.vote_strategy;
     if (strategy == RV_VOTE_AUTO)
         strategy = (h->brick_ok && grid >= kBrickMinGrid && grid <= rv::kMaxBrickGrid)
                        ? RV_VOTE_BRICK : RV_VOTE_GLOBAL;
     if (strategy == RV_VOTE_BRICK && !(h->brick_ok && grid <= rv::kMaxBrickGrid))
         return fail(h, RV_EUNSUPPORTED,
-                    "rot_vote_solve: the brick strategy needs grid <= 256 and a handle created for it");
+                    f + ": the brick strategy needs grid <= 256 and a handle created for it");
 
     if (h->table_J != J) {
         RV_HIP(h, hipStreamSynchronize(s), "sync before table upload");
@@ -490,7 +510,8 @@ RV_API rv_status rot_vote_solve(rv_handle* h, const float* x, const float* y, in
         RV_HIP(h, hipEventRecord(h->ev[2], s), "event");
     int nlists;
     if (brick) {
-        RV_HIP(h, rv::launch_brick_accum(grid, h->K, h->d_hist, h->d_partial, h->bin, s), "brick accumulate");
+        RV_HIP(h, rv::launch_brick_accum(grid, h->K, h->d_hist, h->d_partial, h->bin, s),
+               "brick accumulate");
         const int nba = rv::brick_axis(grid);
         nlists = nba * nba * nba;
     } else {
@@ -499,21 +520,52 @@ RV_API rv_status rot_vote_solve(rv_handle* h, const float* x, const float* y, in
     }
     if (tm)
         RV_HIP(h, hipEventRecord(h->ev[3], s), "event");
+    if (n == 0)
+        return RV_OK;
+    RV_HIP(h, rv::launch_topk_final(h->d_partial, nlists, h->K, grid, candidates(h), s),
+           "top-K final");
+    if (tm)
+        RV_HIP(h, hipEventRecord(h->ev[4], s), "event");
+    return RV_OK;
+}
+
+void record_empty(rv_handle* h)
+{
+    h->last_ncand = 0;
+    h->last_winner = -1;
+    h->last_count = 0;
+    h->events_recorded = false;
+}
+
+}  // namespace
+
+RV_API rv_status rot_vote_solve(rv_handle* h, const float* x, const float* y, int64_t n,
+                                int32_t grid, float eps_rad, float q_out[4],
+                                int64_t* inlier_count, uint8_t* inlier_mask)
+{
+    if (!h)
+        return RV_EINVAL;
+    h->err.clear();
+    if (!q_out || !inlier_count)
+        return fail(h, RV_EINVAL, "rot_vote_solve: q_out and inlier_count must not be NULL");
+    int32_t J = 0;
+    if (rv_status st = check_solve(h, "rot_vote_solve", x, y, n, grid, eps_rad, inlier_mask, &J))
+        return st;
+    RV_HIP(h, hipSetDevice(h->device), "hipSetDevice");
+    hipStream_t s = h->stream;
+    if (rv_status st = vote_candidates(h, x, y, n, grid, J, "rot_vote_solve"))
+        return st;
     if (n == 0) {
         RV_HIP(h, hipStreamSynchronize(s), "sync");
         q_out[0] = 1.0f;
         q_out[1] = q_out[2] = q_out[3] = 0.0f;
         *inlier_count = 0;
-        h->last_ncand = 0;
-        h->last_winner = -1;
-        h->last_count = 0;
-        h->events_recorded = false;
+        record_empty(h);
         return RV_OK;
     }
+    const bool tm = h->timing;
+    const float T2 = residual_bound(eps_rad);
     const rv::Candidates c = candidates(h);
-    RV_HIP(h, rv::launch_topk_final(h->d_partial, nlists, h->K, grid, c, s), "top-K final");
-    if (tm)
-        RV_HIP(h, hipEventRecord(h->ev[4], s), "event");
     RV_HIP(h, rv::launch_rescore(x, y, n, T2, c, s), "rescore");
     if (tm)
         RV_HIP(h, hipEventRecord(h->ev[5], s), "event");
@@ -527,6 +579,64 @@ RV_API rv_status rot_vote_solve(rv_handle* h, const float* x, const float* y, in
     const rv::Result& r = *h->h_result;
     std::memcpy(q_out, r.q, sizeof(r.q));
     *inlier_count = r.count;
+    h->last_ncand = r.n_cand;
+    h->last_winner = r.winner;
+    h->last_count = r.count;
+    return RV_OK;
+}
+
+RV_API rv_status rot_vote_solve_multi(rv_handle* h, const float* x, const float* y, int64_t n,
+                                      int32_t grid, float eps_rad, int32_t max_models,
+                                      float sep_rad, int64_t min_inliers, float* q_out,
+                                      int64_t* counts, int32_t* n_models, uint8_t* labels)
+{
+    if (!h)
+        return RV_EINVAL;
+    h->err.clear();
+    if (!q_out || !counts || !n_models)
+        return fail(h, RV_EINVAL, "rot_vote_solve_multi: q_out, counts and n_models must not be NULL");
+    if (max_models < 1 || max_models > h->K)
+        return fail(h, RV_EINVAL, "rot_vote_solve_multi: max_models outside 1..topk");
+    if (!(sep_rad >= 0.0f) || !(sep_rad <= (float)M_PI))
+        return fail(h, RV_EINVAL, "rot_vote_solve_multi: sep_rad outside [0, pi]");
+    if (min_inliers < 1)
+        return fail(h, RV_EINVAL, "rot_vote_solve_multi: min_inliers < 1");
+    int32_t J = 0;
+    if (rv_status st = check_solve(h, "rot_vote_solve_multi", x, y, n, grid, eps_rad, labels, &J))
+        return st;
+    RV_HIP(h, hipSetDevice(h->device), "hipSetDevice");
+    hipStream_t s = h->stream;
+    if (rv_status st = vote_candidates(h, x, y, n, grid, J, "rot_vote_solve_multi"))
+        return st;
+    if (n == 0) {
+        RV_HIP(h, hipStreamSynchronize(s), "sync");
+        *n_models = 0;
+        record_empty(h);
+        return RV_OK;
+    }
+    const bool tm = h->timing;
+    const float cos_half_sep = (float)std::cos(0.5 * (double)sep_rad);
+    RV_HIP(h, rv::launch_multi(x, y, n, residual_bound(eps_rad), max_models, cos_half_sep,
+                               min_inliers, candidates(h), h->d_mbits, labels, h->d_mstate, s),
+           "models");
+    if (tm) {
+        RV_HIP(h, hipEventRecord(h->ev[5], s), "event");
+        RV_HIP(h, hipEventRecord(h->ev[6], s), "event");
+    }
+    RV_HIP(h, hipMemcpyAsync(h->h_mstate, h->d_mstate, sizeof(rv::MultiState), hipMemcpyDeviceToHost,
+                             s),
+           "models readback");
+    RV_HIP(h, hipMemcpyAsync(h->h_result, h->d_result, sizeof(rv::Result), hipMemcpyDeviceToHost, s),
+           "result readback");
+    RV_HIP(h, hipStreamSynchronize(s), "sync");
+    h->events_recorded = tm;
+    const rv::MultiState& ms = *h->h_mstate;
+    *n_models = ms.n_models;
+    for (int m = 0; m < ms.n_models; ++m) {
+        std::memcpy(q_out + 4 * m, ms.m_q[m], sizeof(ms.m_q[m]));
+        counts[m] = ms.m_count[m];
+    }
+    const rv::Result& r = *h->h_result;
     h->last_ncand = r.n_cand;
     h->last_winner = r.winner;
     h->last_count = r.count;

@@ -117,6 +117,20 @@ hipError_t launch_refine(const float* x, const float* y, int64_t n, float T2, in
                          const float q_in[4], uint8_t* mask, RefineState* st, double* partial,
                          hipStream_t s);
 
+// Several rotations from one vote: device state of the greedy model choice.
+struct MultiState {
+    unsigned long long counts[64];  // unclaimed inliers per candidate (running pass)
+    uint64_t suppressed;            // candidates taken or within the separation angle
+    int32_t n_models;
+    uint32_t stop;                  // no further model
+    int32_t m_cand[64];             // per model: candidate, claimed inliers, rotation
+    int64_t m_count[64];
+    float m_q[64][4];
+};
+hipError_t launch_multi(const float* x, const float* y, int64_t n, float T2, int max_models,
+                        float cos_half_sep, int64_t min_inliers, const Candidates& c,
+                        uint64_t* bits, uint8_t* labels, MultiState* st, hipStream_t s);
+
 hipError_t launch_rescore(const float* x, const float* y, int64_t n, float T2,
                           const Candidates& c, hipStream_t s);
 hipError_t launch_mask(const float* x, const float* y, int64_t n, float T2, const Candidates& c,

@@ -35,6 +35,8 @@ __all__ = [
     "BATCH_WORKLOADS",
     "Batch",
     "make_batch",
+    "MultiInstance",
+    "make_multi_instance",
     "quat_to_matrix",
     "rotation_error_deg",
 ]
@@ -166,6 +168,51 @@ def make_batch(instances: int, n_lo: int, n_hi: int, rho_lo: float, rho_hi: floa
         y[:, offsets[b]:offsets[b + 1]] = inst.y
         q[b] = inst.q_gt
     return Batch(x, y, offsets, q, rhos)
+
+
+@dataclass
+class MultiInstance:
+    x: np.ndarray          # float32 [3, N]
+    y: np.ndarray
+    q_gt: np.ndarray       # float64 [M, 4], w >= 0
+    model: np.ndarray      # int32 [N]: the model (0..M-1) of an inlier, -1 for an outlier
+    seed: int
+
+
+def make_multi_instance(models: int, per_model: int, outliers: int, delta: float, seed: int,
+                        noise: str = "additive") -> MultiInstance:
+    """Several rotations in one scene (the paper's multiple-rotation experiment:
+    random unit vectors rotated by one of `models` uniformly random rotations,
+    per_model correspondences each, noise delta; plus uniform outliers).
+    Draw order (fixed): the rotations; per model its directions and noise;
+    the outliers; one permutation of all correspondences.  noise="additive":
+    y = normalise(R x + delta N(0, I)) (delta = 0.01 in the paper);
+    "angular": a tangent-plane rotation with std delta degrees per axis."""
+    rng = np.random.default_rng(seed)
+    qs = np.array([_random_unit_quat(rng) for _ in range(models)])
+    xs, ys, lab = [], [], []
+    for m in range(models):
+        xh = _unit_rows(rng.normal(size=(per_model, 3)))
+        z = xh @ quat_to_matrix(qs[m]).T
+        if noise == "additive":
+            y = _unit_rows(z + delta * rng.normal(size=z.shape))
+        elif noise == "angular":
+            y = _angular_noise(rng, z, math.radians(delta))
+        else:
+            raise ValueError(f"unknown noise model {noise!r}")
+        xs.append(xh)
+        ys.append(y)
+        lab.append(np.full(per_model, m, np.int32))
+    if outliers:
+        xs.append(_unit_rows(rng.normal(size=(outliers, 3))))
+        ys.append(_unit_rows(rng.normal(size=(outliers, 3))))
+        lab.append(np.full(outliers, -1, np.int32))
+    x = np.concatenate(xs) if xs else np.zeros((0, 3))
+    y = np.concatenate(ys) if ys else np.zeros((0, 3))
+    lab = np.concatenate(lab) if lab else np.zeros(0, np.int32)
+    perm = rng.permutation(len(lab))
+    return MultiInstance(np.ascontiguousarray(x[perm].T.astype(np.float32)),
+                         np.ascontiguousarray(y[perm].T.astype(np.float32)), qs, lab[perm], seed)
 
 
 def quat_to_matrix(q) -> np.ndarray:

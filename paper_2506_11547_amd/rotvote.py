@@ -37,7 +37,7 @@ EXPORTS = ("rot_vote_default_config", "rot_vote_create", "rot_vote_destroy",
            "rot_vote_last_error", "rot_vote_set_stream", "rot_vote_solve",
            "rot_vote_get_histogram", "rot_vote_get_topk", "rot_vote_get_plan",
            "rot_vote_get_timings", "rot_vote_solve_batch", "rot_vote_get_batch_histogram",
-           "rot_vote_get_batch_topk", "rot_vote_refine")
+           "rot_vote_get_batch_topk", "rot_vote_refine", "rot_vote_solve_multi")
 
 
 class RvConfig(ct.Structure):
@@ -101,6 +101,9 @@ def load_library(path: Path | str = LIB_PATH) -> ct.CDLL:
     L.rot_vote_refine.argtypes = [vp, vp, vp, i64, f32, i32, ct.POINTER(f32 * 4), ct.POINTER(i64),
                                   vp, ct.POINTER(i32)]
     L.rot_vote_refine.restype = i32
+    L.rot_vote_solve_multi.argtypes = [vp, vp, vp, i64, i32, f32, i32, f32, i64, ct.POINTER(f32),
+                                       ct.POINTER(i64), ct.POINTER(i32), vp]
+    L.rot_vote_solve_multi.restype = i32
     _lib = L
     return L
 
@@ -200,6 +203,40 @@ class Solver:
         q, cnt = self.solve_raw(x.data_ptr(), y.data_ptr(), n, grid, eps_deg_to_rad(eps_deg),
                                 mask.data_ptr() if n else 0)
         return q, cnt, mask
+
+    def solve_multi_raw(self, x_ptr: int, y_ptr: int, n: int, grid: int, eps_rad: float,
+                        max_models: int, sep_rad: float, min_inliers: int, labels_ptr: int):
+        """Direct C-ABI call; returns (q [M][4], counts [M])."""
+        q = (ct.c_float * (4 * max(1, max_models)))()
+        cnt = (ct.c_int64 * max(1, max_models))()
+        nm = ct.c_int32(-1)
+        self._check(self._lib.rot_vote_solve_multi(self._h, ct.c_void_p(x_ptr), ct.c_void_p(y_ptr), n,
+                                                   grid, ct.c_float(eps_rad), max_models,
+                                                   ct.c_float(sep_rad), min_inliers, q, cnt,
+                                                   ct.byref(nm), ct.c_void_p(labels_ptr)))
+        self._last_grid = grid
+        m = nm.value
+        return [list(q[4 * k:4 * k + 4]) for k in range(m)], [int(c) for c in cnt[:m]]
+
+    def solve_multi(self, x: torch.Tensor, y: torch.Tensor, grid: int, eps_deg: float,
+                    max_models: int, sep_deg: float, min_inliers: int,
+                    labels: torch.Tensor | None = None):
+        """Several rotations from one vote.  Returns (q [M][4], counts [M],
+        labels uint8 [N]: 0 unclaimed, m + 1 for model m)."""
+        for t, nm in ((x, "x"), (y, "y")):
+            if t.dtype != torch.float32 or t.dim() != 2 or t.shape[0] != 3 or not t.is_cuda:
+                raise ValueError(f"{nm} must be a float32 [3, N] device tensor")
+        if x.shape != y.shape:
+            raise ValueError("x and y must have the same shape")
+        x = x.contiguous()
+        y = y.contiguous()
+        n = x.shape[1]
+        if labels is None:
+            labels = torch.empty(n, dtype=torch.uint8, device=x.device)
+        q, cnt = self.solve_multi_raw(x.data_ptr(), y.data_ptr(), n, grid, eps_deg_to_rad(eps_deg),
+                                      max_models, math.radians(sep_deg), min_inliers,
+                                      labels.data_ptr() if n else 0)
+        return q, cnt, labels
 
     def refine_raw(self, x_ptr: int, y_ptr: int, n: int, eps_rad: float, max_rounds: int,
                    q_in, mask_ptr: int):
