@@ -46,7 +46,9 @@ typedef enum rv_status {
     RV_EINVAL = -1,        /* an argument is out of range, NULL, or not device memory */
     RV_ENOMEM = -2,        /* device or pinned host allocation failed */
     RV_EDEVICE = -3,       /* the HIP runtime reported an error */
-    RV_EUNSUPPORTED = -4   /* valid but beyond the library's limits (n*J > 2^31-1) */
+    RV_EUNSUPPORTED = -4,  /* valid but beyond the library's limits (n*J > 2^31-1) */
+    RV_EAGAIN = -5,        /* server: the request queue is full; submit again later */
+    RV_ETIMEDOUT = -6      /* server: the request did not finish within the wait */
 } rv_status;
 
 /* How the vote histogram is accumulated; every strategy yields the same
@@ -212,6 +214,81 @@ rv_status rot_vote_get_plan(rv_handle *h, int32_t *samples_per_circle, int32_t *
  *   4 rescore  (exact inlier count of every candidate)
  *   5 mask     (winner, inlier mask, result record) */
 rv_status rot_vote_get_timings(rv_handle *h, float *ms);
+
+/* Device bytes the handle allocated at create (its whole footprint: a solve
+ * allocates nothing). */
+rv_status rot_vote_get_footprint(const rv_handle *h, int64_t *device_bytes);
+
+/* ---------------------------------------------------------------- serving
+ * A request server: worker threads, each with its own HIP stream (default
+ * priority) and its own handle, take requests from one FIFO queue.  A worker
+ * that takes a request with grid <= RV_MAX_BATCH_GRID and n <= batch_max_n
+ * also takes the queued requests of the same grid and eps (oldest first, up to
+ * max_batch of them and max_n columns in all), gathers their columns and runs
+ * them as one rot_vote_solve_batch; any other request runs alone
+ * (rot_vote_solve, then rot_vote_refine if asked).  A request's result does
+ * not depend on what it was batched with: every path gives exactly
+ * rot_vote_solve's result.  Admission: each worker's handle holds the whole
+ * scratch of one request (or batch) in flight, so requests in flight never
+ * exceed `workers`; with hbm_budget > 0 the server starts only as many workers
+ * as fit in that many device bytes (RV_ENOMEM if not even one does); beyond
+ * max_queue waiting requests a submission returns RV_EAGAIN.  Times are
+ * seconds of the host's monotonic clock (CLOCK_MONOTONIC). */
+typedef struct rv_server rv_server;
+
+typedef struct rv_server_config {
+    int32_t device;
+    int32_t workers;             /* 1..16 */
+    int64_t max_n;               /* largest request (and largest batch, in columns) */
+    int32_t max_grid;
+    int32_t topk;                /* K of every solve */
+    int32_t samples_per_circle;  /* 0: J = 8 * grid */
+    int32_t max_batch;           /* requests fused into one batched solve; 0 or 1: never */
+    int64_t batch_max_n;         /* requests with n up to this (and grid <= 64) may be fused */
+    int64_t max_queue;           /* waiting requests before RV_EAGAIN */
+    int64_t hbm_budget;          /* device bytes for all workers' scratch; 0: no limit */
+    int32_t reserved[4];         /* must be 0 */
+} rv_server_config;
+
+typedef struct rv_request {
+    const float *x;              /* device float32 [3][n] SoA, as rot_vote_solve */
+    const float *y;
+    int64_t n;
+    int32_t grid;
+    float eps_rad;
+    uint8_t *inlier_mask;        /* device uint8[n], written by the request */
+    int32_t refine_rounds;       /* 0: none; else rot_vote_refine after the solve */
+    int32_t reserved;
+} rv_request;
+
+typedef struct rv_reply {
+    float q[4];
+    int64_t inlier_count;
+    int32_t status;              /* the solve's rv_status */
+    int32_t batched;             /* requests in its solve (1: alone) */
+    int32_t worker;
+    int32_t refine_rounds_run;
+    double t_submit, t_start, t_end;
+} rv_reply;
+
+/* Fills *cfg: device 0, 2 workers, max_n 1<<20, max_grid 256, K 16, J = 8G,
+ * max_batch 64, batch_max_n 65536, max_queue 1<<20, no budget. */
+void rot_vote_server_default_config(rv_server_config *cfg);
+rv_status rot_vote_server_create(rv_server **out, const rv_server_config *cfg);
+/* Waits for the queue to drain, stops the workers, frees everything.  NULL is
+ * a no-op.  Replies not collected are dropped. */
+rv_status rot_vote_server_destroy(rv_server *s);
+/* Validates the request (as rot_vote_solve would) and queues it; *ticket
+ * identifies it for rot_vote_server_wait.  The buffers must stay valid until
+ * the reply is collected. */
+rv_status rot_vote_server_submit(rv_server *s, const rv_request *req, uint64_t *ticket);
+/* Waits up to timeout_ms (< 0: forever) for the request and collects its reply
+ * (once).  RV_ETIMEDOUT leaves it pending. */
+rv_status rot_vote_server_wait(rv_server *s, uint64_t ticket, int32_t timeout_ms, rv_reply *out);
+/* Workers started and their device bytes; requests queued and in flight. */
+rv_status rot_vote_server_stats(rv_server *s, int32_t *workers, int64_t *device_bytes,
+                                int64_t *queued, int64_t *in_flight);
+const char *rot_vote_server_last_error(const rv_server *s);
 
 #ifdef __cplusplus
 }

@@ -114,10 +114,21 @@ struct rv_handle {
     int32_t last_B = 0;
     int32_t last_bgrid = 0;
 
+    int64_t device_bytes = 0;           // sum of the handle's device allocations
+
     std::string err;
 };
 
 namespace {
+
+template <typename T>
+hipError_t dev_alloc(rv_handle* h, T** p, size_t bytes)
+{
+    const hipError_t e = hipMalloc(p, bytes);
+    if (e == hipSuccess)
+        h->device_bytes += (int64_t)bytes;
+    return e;
+}
 
 rv_status fail(rv_handle* h, rv_status st, const std::string& msg)
 {
@@ -294,18 +305,18 @@ RV_API rv_status rot_vote_create(rv_handle** out, const rv_config* cfg)
     if ((e = hipSetDevice(h->device)) != hipSuccess)
         return bail(e, "hipSetDevice");
     const size_t ncell = (size_t)h->max_grid * h->max_grid * h->max_grid;
-    if ((e = hipMalloc(&h->d_hist, ncell * sizeof(int32_t))) != hipSuccess)
+    if ((e = dev_alloc(h, &h->d_hist, ncell * sizeof(int32_t))) != hipSuccess)
         return bail(e, "vote grid");
-    if ((e = hipMalloc(&h->d_table, (size_t)h->max_J * sizeof(float2))) != hipSuccess)
+    if ((e = dev_alloc(h, &h->d_table, (size_t)h->max_J * sizeof(float2))) != hipSuccess)
         return bail(e, "sample table");
-    if ((e = hipMalloc(&h->d_partial, (size_t)rv::kTopkMaxBlocks * 64 * sizeof(uint64_t))) !=
+    if ((e = dev_alloc(h, &h->d_partial, (size_t)rv::kTopkMaxBlocks * 64 * sizeof(uint64_t))) !=
         hipSuccess)
         return bail(e, "top-K scratch");
-    if ((e = hipMalloc(&h->d_cand_q, 64 * sizeof(float4))) != hipSuccess ||
-        (e = hipMalloc(&h->d_cand_votes, 64 * sizeof(int32_t))) != hipSuccess ||
-        (e = hipMalloc(&h->d_cand_idx, 64 * sizeof(int32_t))) != hipSuccess ||
-        (e = hipMalloc(&h->d_cand_inl, 64 * sizeof(uint32_t))) != hipSuccess ||
-        (e = hipMalloc(&h->d_result, sizeof(rv::Result))) != hipSuccess)
+    if ((e = dev_alloc(h, &h->d_cand_q, 64 * sizeof(float4))) != hipSuccess ||
+        (e = dev_alloc(h, &h->d_cand_votes, 64 * sizeof(int32_t))) != hipSuccess ||
+        (e = dev_alloc(h, &h->d_cand_idx, 64 * sizeof(int32_t))) != hipSuccess ||
+        (e = dev_alloc(h, &h->d_cand_inl, 64 * sizeof(uint32_t))) != hipSuccess ||
+        (e = dev_alloc(h, &h->d_result, sizeof(rv::Result))) != hipSuccess)
         return bail(e, "candidate buffers");
     if ((e = hipHostMalloc(&h->h_result, sizeof(rv::Result), hipHostMallocDefault)) != hipSuccess)
         return bail(e, "pinned result");
@@ -315,15 +326,15 @@ RV_API rv_status rot_vote_create(rv_handle** out, const rv_config* cfg)
     for (auto& ev : h->ev)
         if ((e = hipEventCreate(&ev)) != hipSuccess)
             return bail(e, "events");
-    if ((e = hipMalloc(&h->d_rstate, sizeof(rv::RefineState))) != hipSuccess ||
-        (e = hipMalloc(&h->d_rpartial,
+    if ((e = dev_alloc(h, &h->d_rstate, sizeof(rv::RefineState))) != hipSuccess ||
+        (e = dev_alloc(h, &h->d_rpartial,
                        (size_t)rv::kRefineMaxBlocks * rv::kRefineSums * sizeof(double))) != hipSuccess)
         return bail(e, "refinement scratch");
     if ((e = hipHostMalloc(&h->h_rstate, sizeof(rv::RefineState), hipHostMallocDefault)) != hipSuccess)
         return bail(e, "pinned refinement state");
-    if ((e = hipMalloc(&h->d_mbits, (size_t)std::max<int64_t>(1, h->max_n) * sizeof(uint64_t))) !=
+    if ((e = dev_alloc(h, &h->d_mbits, (size_t)std::max<int64_t>(1, h->max_n) * sizeof(uint64_t))) !=
             hipSuccess ||
-        (e = hipMalloc(&h->d_mstate, sizeof(rv::MultiState))) != hipSuccess)
+        (e = dev_alloc(h, &h->d_mstate, sizeof(rv::MultiState))) != hipSuccess)
         return bail(e, "model scratch");
     if ((e = hipHostMalloc(&h->h_mstate, sizeof(rv::MultiState), hipHostMallocDefault)) != hipSuccess)
         return bail(e, "pinned model state");
@@ -349,7 +360,7 @@ RV_API rv_status rot_vote_create(rv_handle** out, const rv_config* cfg)
     }
     runs = std::min<uint64_t>(runs, 0xFFFFFFFFull - 64);
     h->bin.pool_runs = runs;
-    if (runs > 0 && (e = hipMalloc(&h->bin.pool, runs * sizeof(uint32_t))) != hipSuccess)
+    if (runs > 0 && (e = dev_alloc(h, &h->bin.pool, runs * sizeof(uint32_t))) != hipSuccess)
         return bail(e, "brick run pool");
     h->bin.nsets = rv::kQueueSets;
     h->bin.qstride = rv::kMaxBricks;
@@ -357,13 +368,13 @@ RV_API rv_status rot_vote_create(rv_handle** out, const rv_config* cfg)
     h->bin.batch = 0;
     if (want_brick) {
         const size_t nq = (size_t)rv::kQueueSets * rv::kMaxBricks;
-        if ((e = hipMalloc(&h->bin.fill, nq * sizeof(uint32_t))) != hipSuccess ||
-            (e = hipMalloc(&h->bin.qbase, nq * sizeof(uint32_t))) != hipSuccess ||
-            (e = hipMalloc(&h->bin.cap, rv::kMaxBricks * sizeof(uint32_t))) != hipSuccess ||
-            (e = hipMalloc(&h->bin.est, rv::kMaxBricks * sizeof(uint32_t))) != hipSuccess ||
-            (e = hipMalloc(&h->bin.flags, rv::kMaxBricks * sizeof(uint32_t))) != hipSuccess ||
-            (e = hipMalloc(&h->bin.order, rv::kMaxBricks * sizeof(uint32_t))) != hipSuccess ||
-            (e = hipMalloc(&h->d_ovf, ncell * sizeof(int32_t))) != hipSuccess)
+        if ((e = dev_alloc(h, &h->bin.fill, nq * sizeof(uint32_t))) != hipSuccess ||
+            (e = dev_alloc(h, &h->bin.qbase, nq * sizeof(uint32_t))) != hipSuccess ||
+            (e = dev_alloc(h, &h->bin.cap, rv::kMaxBricks * sizeof(uint32_t))) != hipSuccess ||
+            (e = dev_alloc(h, &h->bin.est, rv::kMaxBricks * sizeof(uint32_t))) != hipSuccess ||
+            (e = dev_alloc(h, &h->bin.flags, rv::kMaxBricks * sizeof(uint32_t))) != hipSuccess ||
+            (e = dev_alloc(h, &h->bin.order, rv::kMaxBricks * sizeof(uint32_t))) != hipSuccess ||
+            (e = dev_alloc(h, &h->d_ovf, ncell * sizeof(int32_t))) != hipSuccess)
             return bail(e, "brick scratch");
         if ((e = hipMemset(h->bin.est, 0, rv::kMaxBricks * sizeof(uint32_t))) != hipSuccess ||
             (e = hipMemset(h->d_ovf, 0, ncell * sizeof(int32_t))) != hipSuccess ||
@@ -378,20 +389,20 @@ RV_API rv_status rot_vote_create(rv_handle** out, const rv_config* cfg)
         const int64_t bg = h->batch_grid;
         const size_t gcells = (size_t)B * (size_t)(bg * bg * bg);
         h->max_units = (h->max_n + rv::kUnitSize - 1) / rv::kUnitSize + B;
-        if ((e = hipMalloc(&h->d_units, (size_t)h->max_units * sizeof(rv::Unit))) != hipSuccess ||
-            (e = hipMalloc(&h->d_bplan, (size_t)(2 * nq) * sizeof(uint32_t))) != hipSuccess ||
-            (e = hipMalloc(&h->d_offsets, (size_t)(B + 1) * sizeof(int64_t))) != hipSuccess ||
-            (e = hipMalloc(&h->d_bfill, (size_t)nq * sizeof(uint32_t))) != hipSuccess ||
-            (e = hipMalloc(&h->d_bflags, (size_t)nq * sizeof(uint32_t))) != hipSuccess ||
-            (e = hipMalloc(&h->d_bpartial, (size_t)nq * 64 * sizeof(uint64_t))) != hipSuccess ||
-            (e = hipMalloc(&h->d_bcand_q, (size_t)B * 64 * sizeof(float4))) != hipSuccess ||
-            (e = hipMalloc(&h->d_bcand_votes, (size_t)B * 64 * sizeof(int32_t))) != hipSuccess ||
-            (e = hipMalloc(&h->d_bcand_idx, (size_t)B * 64 * sizeof(int32_t))) != hipSuccess ||
-            (e = hipMalloc(&h->d_bcand_inl, (size_t)B * 64 * sizeof(uint32_t))) != hipSuccess ||
-            (e = hipMalloc(&h->d_bresult, (size_t)B * sizeof(rv::Result))) != hipSuccess ||
-            (e = hipMalloc(&h->d_bovf, gcells * sizeof(int32_t))) != hipSuccess)
+        if ((e = dev_alloc(h, &h->d_units, (size_t)h->max_units * sizeof(rv::Unit))) != hipSuccess ||
+            (e = dev_alloc(h, &h->d_bplan, (size_t)(2 * nq) * sizeof(uint32_t))) != hipSuccess ||
+            (e = dev_alloc(h, &h->d_offsets, (size_t)(B + 1) * sizeof(int64_t))) != hipSuccess ||
+            (e = dev_alloc(h, &h->d_bfill, (size_t)nq * sizeof(uint32_t))) != hipSuccess ||
+            (e = dev_alloc(h, &h->d_bflags, (size_t)nq * sizeof(uint32_t))) != hipSuccess ||
+            (e = dev_alloc(h, &h->d_bpartial, (size_t)nq * 64 * sizeof(uint64_t))) != hipSuccess ||
+            (e = dev_alloc(h, &h->d_bcand_q, (size_t)B * 64 * sizeof(float4))) != hipSuccess ||
+            (e = dev_alloc(h, &h->d_bcand_votes, (size_t)B * 64 * sizeof(int32_t))) != hipSuccess ||
+            (e = dev_alloc(h, &h->d_bcand_idx, (size_t)B * 64 * sizeof(int32_t))) != hipSuccess ||
+            (e = dev_alloc(h, &h->d_bcand_inl, (size_t)B * 64 * sizeof(uint32_t))) != hipSuccess ||
+            (e = dev_alloc(h, &h->d_bresult, (size_t)B * sizeof(rv::Result))) != hipSuccess ||
+            (e = dev_alloc(h, &h->d_bovf, gcells * sizeof(int32_t))) != hipSuccess)
             return bail(e, "batch scratch");
-        if (h->batch_grids && (e = hipMalloc(&h->d_bgrids, gcells * sizeof(int32_t))) != hipSuccess)
+        if (h->batch_grids && (e = dev_alloc(h, &h->d_bgrids, gcells * sizeof(int32_t))) != hipSuccess)
             return bail(e, "batch grids");
         if ((e = hipHostMalloc(&h->h_units, (size_t)h->max_units * sizeof(rv::Unit),
                                hipHostMallocDefault)) != hipSuccess ||
@@ -930,6 +941,14 @@ RV_API rv_status rot_vote_get_topk(rv_handle* h, int32_t* n_cand, int32_t* votes
     }
     *n_cand = m;
     *winner = h->last_winner;
+    return RV_OK;
+}
+
+RV_API rv_status rot_vote_get_footprint(const rv_handle* h, int64_t* device_bytes)
+{
+    if (!h || !device_bytes)
+        return RV_EINVAL;
+    *device_bytes = h->device_bytes;
     return RV_OK;
 }
 

@@ -157,6 +157,56 @@ __global__ __launch_bounds__(kUnitThreads) void k_mask_batch(const float* __rest
     }
 }
 
+// Gathers separate requests' SoA columns into one batch array (and scatters
+// the batch mask back): one 512-thread block per unit of one item.
+__global__ __launch_bounds__(kUnitThreads) void k_gather(const GatherItem* __restrict__ items,
+                                                         const Unit* __restrict__ units,
+                                                         float* __restrict__ dx,
+                                                         float* __restrict__ dy, int64_t total)
+{
+    const Unit un = units[blockIdx.x];
+    const GatherItem it = items[un.inst];
+    if ((int)threadIdx.x >= un.count)
+        return;
+    const int64_t j = un.first + threadIdx.x;
+    const int64_t o = it.offset + j;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        dx[c * total + o] = it.x[c * it.n + j];
+        dy[c * total + o] = it.y[c * it.n + j];
+    }
+}
+
+__global__ __launch_bounds__(kUnitThreads) void k_scatter_mask(const GatherItem* __restrict__ items,
+                                                               const Unit* __restrict__ units,
+                                                               const uint8_t* __restrict__ dmask)
+{
+    const Unit un = units[blockIdx.x];
+    const GatherItem it = items[un.inst];
+    if ((int)threadIdx.x >= un.count)
+        return;
+    const int64_t j = un.first + threadIdx.x;
+    it.mask[j] = dmask[it.offset + j];
+}
+
+hipError_t launch_gather(const GatherItem* items, const Unit* units, int nunits, float* dx,
+                         float* dy, int64_t total, hipStream_t s)
+{
+    if (nunits <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_gather, dim3(nunits), dim3(kUnitThreads), 0, s, items, units, dx, dy, total);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter_masks(const GatherItem* items, const Unit* units, int nunits,
+                                const uint8_t* dmask, hipStream_t s)
+{
+    if (nunits <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_scatter_mask, dim3(nunits), dim3(kUnitThreads), 0, s, items, units, dmask);
+    return hipGetLastError();
+}
+
 hipError_t launch_batch_finish(const float* x, const float* y, int64_t n, float T2, int B, int nb,
                                int K, int G, const uint64_t* partial, const Unit* units, int nunits,
                                const int64_t* offsets, const Candidates& c, uint8_t* mask,

@@ -131,6 +131,21 @@ hipError_t launch_multi(const float* x, const float* y, int64_t n, float T2, int
                         float cos_half_sep, int64_t min_inliers, const Candidates& c,
                         uint64_t* bits, uint8_t* labels, MultiState* st, hipStream_t s);
 
+// Request staging of the server: separate requests' columns gathered into one
+// batch array, the batch mask scattered back (units: inst = item, first =
+// column within the item).
+struct GatherItem {
+    const float* x;
+    const float* y;
+    uint8_t* mask;
+    int64_t n;
+    int64_t offset;  // first column in the batch array
+};
+hipError_t launch_gather(const GatherItem* items, const Unit* units, int nunits, float* dx,
+                         float* dy, int64_t total, hipStream_t s);
+hipError_t launch_scatter_masks(const GatherItem* items, const Unit* units, int nunits,
+                                const uint8_t* dmask, hipStream_t s);
+
 hipError_t launch_rescore(const float* x, const float* y, int64_t n, float T2,
                           const Candidates& c, hipStream_t s);
 hipError_t launch_mask(const float* x, const float* y, int64_t n, float T2, const Candidates& c,

@@ -20,8 +20,9 @@ LIB_PATH = PKG / "librotvote.so"
 PROBE_PATH = PKG / "librotvote_probe.so"
 
 RV_OK, RV_EINVAL, RV_ENOMEM, RV_EDEVICE, RV_EUNSUPPORTED = 0, -1, -2, -3, -4
+RV_EAGAIN, RV_ETIMEDOUT = -5, -6
 STATUS_NAMES = {0: "RV_OK", -1: "RV_EINVAL", -2: "RV_ENOMEM", -3: "RV_EDEVICE",
-                -4: "RV_EUNSUPPORTED"}
+                -4: "RV_EUNSUPPORTED", -5: "RV_EAGAIN", -6: "RV_ETIMEDOUT"}
 STRATEGIES = {"auto": 0, "global": 1, "brick": 2}
 STRATEGY_NAMES = {v: k for k, v in STRATEGIES.items()}
 FLAG_TIMING = 1
@@ -37,7 +38,10 @@ EXPORTS = ("rot_vote_default_config", "rot_vote_create", "rot_vote_destroy",
            "rot_vote_last_error", "rot_vote_set_stream", "rot_vote_solve",
            "rot_vote_get_histogram", "rot_vote_get_topk", "rot_vote_get_plan",
            "rot_vote_get_timings", "rot_vote_solve_batch", "rot_vote_get_batch_histogram",
-           "rot_vote_get_batch_topk", "rot_vote_refine", "rot_vote_solve_multi")
+           "rot_vote_get_batch_topk", "rot_vote_refine", "rot_vote_solve_multi",
+           "rot_vote_get_footprint", "rot_vote_server_default_config", "rot_vote_server_create",
+           "rot_vote_server_destroy", "rot_vote_server_submit", "rot_vote_server_wait",
+           "rot_vote_server_stats", "rot_vote_server_last_error")
 
 
 class RvConfig(ct.Structure):
@@ -45,6 +49,25 @@ class RvConfig(ct.Structure):
                 ("max_grid", ct.c_int32), ("samples_per_circle", ct.c_int32),
                 ("topk", ct.c_int32), ("vote_strategy", ct.c_int32), ("flags", ct.c_uint32),
                 ("max_batch", ct.c_int32), ("reserved", ct.c_int32 * 3)]
+
+
+class ServerConfig(ct.Structure):
+    _fields_ = [("device", ct.c_int32), ("workers", ct.c_int32), ("max_n", ct.c_int64),
+                ("max_grid", ct.c_int32), ("topk", ct.c_int32), ("samples_per_circle", ct.c_int32),
+                ("max_batch", ct.c_int32), ("batch_max_n", ct.c_int64), ("max_queue", ct.c_int64),
+                ("hbm_budget", ct.c_int64), ("reserved", ct.c_int32 * 4)]
+
+
+class Request(ct.Structure):
+    _fields_ = [("x", ct.c_void_p), ("y", ct.c_void_p), ("n", ct.c_int64), ("grid", ct.c_int32),
+                ("eps_rad", ct.c_float), ("inlier_mask", ct.c_void_p),
+                ("refine_rounds", ct.c_int32), ("reserved", ct.c_int32)]
+
+
+class Reply(ct.Structure):
+    _fields_ = [("q", ct.c_float * 4), ("inlier_count", ct.c_int64), ("status", ct.c_int32),
+                ("batched", ct.c_int32), ("worker", ct.c_int32), ("refine_rounds_run", ct.c_int32),
+                ("t_submit", ct.c_double), ("t_start", ct.c_double), ("t_end", ct.c_double)]
 
 
 class RotVoteError(RuntimeError):
@@ -104,6 +127,23 @@ def load_library(path: Path | str = LIB_PATH) -> ct.CDLL:
     L.rot_vote_solve_multi.argtypes = [vp, vp, vp, i64, i32, f32, i32, f32, i64, ct.POINTER(f32),
                                        ct.POINTER(i64), ct.POINTER(i32), vp]
     L.rot_vote_solve_multi.restype = i32
+    L.rot_vote_get_footprint.argtypes = [vp, ct.POINTER(i64)]
+    L.rot_vote_get_footprint.restype = i32
+    L.rot_vote_server_default_config.argtypes = [ct.POINTER(ServerConfig)]
+    L.rot_vote_server_default_config.restype = None
+    L.rot_vote_server_create.argtypes = [ct.POINTER(vp), ct.POINTER(ServerConfig)]
+    L.rot_vote_server_create.restype = i32
+    L.rot_vote_server_destroy.argtypes = [vp]
+    L.rot_vote_server_destroy.restype = i32
+    L.rot_vote_server_submit.argtypes = [vp, ct.POINTER(Request), ct.POINTER(ct.c_uint64)]
+    L.rot_vote_server_submit.restype = i32
+    L.rot_vote_server_wait.argtypes = [vp, ct.c_uint64, i32, ct.POINTER(Reply)]
+    L.rot_vote_server_wait.restype = i32
+    L.rot_vote_server_stats.argtypes = [vp, ct.POINTER(i32), ct.POINTER(i64), ct.POINTER(i64),
+                                        ct.POINTER(i64)]
+    L.rot_vote_server_stats.restype = i32
+    L.rot_vote_server_last_error.argtypes = [vp]
+    L.rot_vote_server_last_error.restype = ct.c_char_p
     _lib = L
     return L
 
@@ -354,6 +394,93 @@ class Solver:
         ms = (ct.c_float * NUM_STAGES)()
         self._check(self._lib.rot_vote_get_timings(self._h, ct.byref(ms)))
         return dict(zip(STAGE_NAMES, list(ms)))
+
+
+class Server:
+    """Request server (worker threads, one stream and handle each, batching of
+    small requests).  Inputs and masks are device tensors the caller keeps
+    alive until the reply is collected."""
+
+    def __init__(self, device: int = 0, workers: int = 2, max_n: int = 1 << 20,
+                 max_grid: int = 256, topk: int = 16, samples_per_circle: int = 0,
+                 max_batch: int = 64, batch_max_n: int = 65536, max_queue: int = 1 << 20,
+                 hbm_budget: int = 0):
+        if not torch.cuda.is_available():
+            raise RuntimeError("rotvote needs a HIP GPU; none is visible")
+        self._lib = load_library()
+        torch.cuda.init()
+        cfg = ServerConfig()
+        self._lib.rot_vote_server_default_config(ct.byref(cfg))
+        cfg.device, cfg.workers, cfg.max_n, cfg.max_grid = device, workers, max_n, max_grid
+        cfg.topk, cfg.samples_per_circle, cfg.max_batch = topk, samples_per_circle, max_batch
+        cfg.batch_max_n, cfg.max_queue, cfg.hbm_budget = batch_max_n, max_queue, hbm_budget
+        h = ct.c_void_p()
+        st = self._lib.rot_vote_server_create(ct.byref(h), ct.byref(cfg))
+        if st != RV_OK:
+            raise RotVoteError(st, self._lib.rot_vote_server_last_error(None).decode())
+        self._h = h
+        self._keep = {}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.rot_vote_server_destroy(self._h)
+            self._h = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def submit_raw(self, x_ptr: int, y_ptr: int, n: int, grid: int, eps_rad: float, mask_ptr: int,
+                   refine_rounds: int = 0) -> int:
+        """Queues a request on raw device addresses; returns its ticket (raises
+        RotVoteError with status RV_EAGAIN when the queue is full)."""
+        r = Request(ct.c_void_p(x_ptr), ct.c_void_p(y_ptr), n, grid, eps_rad, ct.c_void_p(mask_ptr),
+                    refine_rounds, 0)
+        t = ct.c_uint64()
+        st = self._lib.rot_vote_server_submit(self._h, ct.byref(r), ct.byref(t))
+        if st != RV_OK:
+            raise RotVoteError(st, self._lib.rot_vote_server_last_error(self._h).decode())
+        return int(t.value)
+
+    def submit(self, x: torch.Tensor, y: torch.Tensor, grid: int, eps_deg: float,
+               mask: torch.Tensor, refine_rounds: int = 0) -> int:
+        for t, nm in ((x, "x"), (y, "y")):
+            if t.dtype != torch.float32 or t.dim() != 2 or t.shape[0] != 3 or not t.is_cuda \
+                    or not t.is_contiguous():
+                raise ValueError(f"{nm} must be a contiguous float32 [3, N] device tensor")
+        if x.shape != y.shape or mask.numel() != x.shape[1] or mask.element_size() != 1:
+            raise ValueError("x, y must match and mask must be a 1-byte [N] tensor")
+        n = x.shape[1]
+        t = self.submit_raw(x.data_ptr(), y.data_ptr(), n, grid, eps_deg_to_rad(eps_deg),
+                            mask.data_ptr() if n else 0, refine_rounds)
+        self._keep[t] = (x, y, mask)
+        return t
+
+    def wait(self, ticket: int, timeout_ms: int = -1) -> dict:
+        r = Reply()
+        st = self._lib.rot_vote_server_wait(self._h, ticket, timeout_ms, ct.byref(r))
+        if st != RV_OK:
+            raise RotVoteError(st, self._lib.rot_vote_server_last_error(self._h).decode())
+        self._keep.pop(ticket, None)
+        return dict(q=list(r.q), count=int(r.inlier_count), status=int(r.status),
+                    batched=int(r.batched), worker=int(r.worker),
+                    refine_rounds_run=int(r.refine_rounds_run), t_submit=r.t_submit,
+                    t_start=r.t_start, t_end=r.t_end)
+
+    def stats(self) -> dict:
+        w, q, f = ct.c_int32(), ct.c_int64(), ct.c_int64()
+        b = ct.c_int64()
+        self._lib.rot_vote_server_stats(self._h, ct.byref(w), ct.byref(b), ct.byref(q), ct.byref(f))
+        return dict(workers=w.value, device_bytes=b.value, queued=q.value, in_flight=f.value)
 
 
 class Probe:

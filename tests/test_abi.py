@@ -102,3 +102,27 @@ def test_default_config_and_create_without_gpu(lib_path):
     bad.vote_strategy = 0
     assert lib.rot_vote_create(ct.byref(h), ct.byref(bad)) == -1
     assert not h.value
+
+
+def test_server_config_checks_without_gpu(lib_path):
+    from paper_2506_11547_amd.rotvote import ServerConfig
+    lib = ct.CDLL(str(lib_path))
+    lib.rot_vote_server_create.argtypes = [ct.POINTER(ct.c_void_p), ct.POINTER(ServerConfig)]
+    lib.rot_vote_server_last_error.restype = ct.c_char_p
+    lib.rot_vote_server_last_error.argtypes = [ct.c_void_p]
+    assert ct.sizeof(ServerConfig) == 72  # 4 4 8 4 4 4 4 8 8 8 16
+    cfg = ServerConfig()
+    lib.rot_vote_server_default_config(ct.byref(cfg))
+    assert cfg.workers == 2 and cfg.max_batch == 64 and cfg.hbm_budget == 0
+    h = ct.c_void_p()
+    for field, value in (("workers", 0), ("workers", 17), ("max_queue", 0), ("max_n", 0)):
+        bad = ServerConfig()
+        lib.rot_vote_server_default_config(ct.byref(bad))
+        setattr(bad, field, value)
+        assert lib.rot_vote_server_create(ct.byref(h), ct.byref(bad)) == -1, field
+        assert lib.rot_vote_server_last_error(None)
+    bad = ServerConfig()
+    lib.rot_vote_server_default_config(ct.byref(bad))
+    bad.reserved[2] = 1
+    assert lib.rot_vote_server_create(ct.byref(h), ct.byref(bad)) == -1
+    assert not h.value
