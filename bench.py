@@ -10,6 +10,12 @@ solve (N * J / seconds per solve); solves/s, the per-stage device times (HIP
 events recorded on the solve stream inside the timed region), the roofline of
 the dominant kernel and the CPU oracle's rate on a bounded sample ride along.
 
+``--workload serve`` drives the request server with Poisson arrivals (2000
+requests/s; N log-uniform on [1e3, 1e6]; G = 64 / 128 / 256 for N below 1e4 /
+below 1e5 / above; J = 8G; outliers U[0.8, 0.99]; sigma 1 deg) and reports
+throughput and latency percentiles; the requests are drawn from a resident
+pool of seeded instances.
+
 ``--workload batch`` times the batched solve instead: a step is one
 rot_vote_solve_batch over 4096 instances (N log-uniform on [100, 20000], G =
 64, J = 512), reported with the same fields plus the one-solve-per-call loop
@@ -56,6 +62,10 @@ def parse():
                     help="correspondences of the workload the CPU oracle times")
     ap.add_argument("--cpu-instances", type=int, default=1000,
                     help="batch workload: instances the CPU oracle times")
+    ap.add_argument("--duration", type=float, default=10.0,
+                    help="serve workload: seconds of arrivals")
+    ap.add_argument("--rate", type=float, default=2000.0, help="serve workload: requests/s")
+    ap.add_argument("--workers", type=int, default=4, help="serve workload: server workers")
     ap.add_argument("--no-loop", action="store_true",
                     help="batch workload: skip the one-solve-per-call comparison")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -168,6 +178,114 @@ def loop_baseline(args, w, bt, x, y, mask, stream, q, cnt) -> dict:
             "vote_strategy": plan["strategy"], "identical_results": same}
 
 
+def serve_pool(per_tier: int, seed: int):
+    """Resident request pool: per tier, per_tier seeded instances whose N are
+    the midpoint quantiles of the log-uniform law over the tier's decade (so
+    the pool's mean load is the law's)."""
+    import numpy as np
+
+    from paper_2506_11547_amd import datagen
+    rng = np.random.default_rng(seed)
+    pool = []
+    for lo, hi, G in ((1_000, 10_000, 64), (10_000, 100_000, 128), (100_000, 1_000_000, 256)):
+        for k in range(per_tier):
+            n = int(round(np.exp(np.log(lo) + (k + 0.5) / per_tier * np.log(hi / lo))))
+            inst = datagen.make_instance(n, float(rng.uniform(0.8, 0.99)), 1.0,
+                                         int(rng.integers(0, 2**62)))
+            pool.append((G, inst))
+    return pool
+
+
+def run_serve(args):
+    import threading
+
+    import numpy as np
+    import torch
+
+    from paper_2506_11547_amd import rotvote
+    seed = 4
+    eps_deg = 1.5
+    pool = serve_pool(24, seed)
+    dev = torch.device("cuda", 0)
+    res = []
+    for G, inst in pool:
+        x = torch.from_numpy(inst.x).to(dev)
+        y = torch.from_numpy(inst.y).to(dev)
+        masks = [torch.empty(inst.n, dtype=torch.uint8, device=dev) for _ in range(4)]
+        res.append((G, inst.n, x, y, masks))
+    rng = np.random.default_rng(seed + 1)
+    n_req = int(rng.poisson(args.rate * args.duration))
+    arrivals = np.sort(rng.uniform(0.0, args.duration, n_req))
+    picks = rng.integers(0, len(res), n_req)
+    srv = rotvote.Server(workers=args.workers, max_n=1_000_000, max_grid=256, topk=16,
+                         max_batch=64, batch_max_n=65536, max_queue=1 << 22)
+    # warm-up: one request of every pool entry
+    for k, (G, n, x, y, masks) in enumerate(res):
+        srv.wait(srv.submit(x, y, G, eps_deg, masks[0]))
+    torch.cuda.synchronize()
+    tickets = [None] * n_req
+    use = [0] * len(res)
+    t0 = time.monotonic() + 0.05
+    for i in range(n_req):
+        k = int(picks[i])
+        G, n, x, y, masks = res[k]
+        m = masks[use[k] % len(masks)]
+        use[k] += 1
+        ta = t0 + arrivals[i]
+        while True:
+            d = ta - time.monotonic()
+            if d <= 0:
+                break
+            if d > 2e-4:
+                time.sleep(d - 1e-4)
+        tickets[i] = srv.submit(x, y, G, eps_deg, m)
+    replies = [srv.wait(t) for t in tickets]
+    torch.cuda.synchronize()
+    st = srv.stats()
+    srv.close()
+    lat = np.array([r["t_end"] - (t0 + a) for r, a in zip(replies, arrivals)])
+    wait = np.array([r["t_start"] - r["t_submit"] for r in replies])
+    end = max(r["t_end"] for r in replies)
+    span = end - t0
+    samples = np.array([res[int(k)][1] * 8 * res[int(k)][0] for k in picks], np.float64)
+    offered = samples.sum() / args.duration
+    achieved = samples.sum() / span
+    tier = np.array([res[int(k)][0] for k in picks])
+    out = {
+        "metric": METRIC,
+        "value": achieved,
+        "unit": "votes/s",
+        "n_gpus": 1,
+        "steps": n_req,
+        "warmup": len(res),
+        "ms_per_step": span / n_req * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "serve", "rate_rps": args.rate, "duration_s": args.duration,
+                   "n_range": [1_000, 1_000_000], "grids": [64, 128, 256], "outlier_ratio": [0.8, 0.99],
+                   "sigma_deg": 1.0, "eps_deg": eps_deg, "topk": 16, "seed": seed,
+                   "pool_per_tier": 24, "workers": st["workers"], "max_batch": 64},
+        "serving": {
+            "requests": n_req, "offered_rps": n_req / args.duration, "achieved_rps": n_req / span,
+            "offered_votes_per_s": offered, "achieved_votes_per_s": achieved,
+            "saturated": bool(achieved < 0.97 * offered),
+            "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3),
+                           "p90": float(np.percentile(lat, 90) * 1e3),
+                           "p99": float(np.percentile(lat, 99) * 1e3)},
+            "latency_p99_ms_by_grid": {int(g): float(np.percentile(lat[tier == g], 99) * 1e3)
+                                       for g in (64, 128, 256) if (tier == g).any()},
+            "queue_wait_ms_p50": float(np.percentile(wait, 50) * 1e3),
+            "batched_fraction": float(np.mean([r["batched"] > 1 for r in replies])),
+            "mean_batch": float(np.mean([r["batched"] for r in replies])),
+            "server_device_bytes": st["device_bytes"],
+        },
+    }
+    print(json.dumps(out), flush=True)
+
+
 def run_batch(args):
     import numpy as np
     import torch
@@ -274,6 +392,9 @@ def main():
     from paper_2506_11547_amd import datagen
     if args.workload in datagen.BATCH_WORKLOADS:
         run_batch(args)
+        return
+    if args.workload == "serve":
+        run_serve(args)
         return
     import numpy as np
     import torch
