@@ -37,8 +37,8 @@ constexpr int kSplit = 240;      // runs are cut every 240 samples: counts fit 8
 // flush before a step could overflow a wave's staging: one step adds at most
 // kWave * kStep runs and a run-block boundary at most kWave more.
 constexpr int kFlushAt = kStageCap - kWave * kStep - kWave;
-// Marks a dropped zero-length staged run.  A rewritten entry never equals it:
-// its length field (bits 15..22) is at most 240, never 0xFF.
+// Marks a dropped zero-length staged run.  A staged run never equals it: its
+// length (bits 24..31) is at most 240, never 0xFF.
 constexpr uint32_t kDropped = 0xFFFFFFFFu;
 constexpr int kAccumThreads = 1024;
 constexpr int kAccumWaves = kAccumThreads / kWave;
@@ -46,22 +46,13 @@ constexpr int kAccumWaves = kAccumThreads / kWave;
 __device__ __forceinline__ uint32_t brick_of(uint32_t pc, int nba)
 {
     const uint32_t ix = pc & 255u, iy = (pc >> 8) & 255u, iz = (pc >> 16) & 255u;
-    return ((iz >> 5) * (uint32_t)nba + (iy >> 5)) * (uint32_t)nba + (ix >> 5);
+    return __umul24(__umul24(iz >> 5, (uint32_t)nba) + (iy >> 5), (uint32_t)nba) + (ix >> 5);
 }
 
 __device__ __forceinline__ uint32_t local_of(uint32_t pc)
 {
     const uint32_t ix = pc & 255u, iy = (pc >> 8) & 255u, iz = (pc >> 16) & 255u;
     return ((iz & 31u) << 10) | ((iy & 31u) << 5) | (ix & 31u);
-}
-
-__device__ __forceinline__ int64_t global_of(uint32_t b, uint32_t loc, int nba, int G)
-{
-    const uint32_t bx = b % nba, by = (b / nba) % nba, bz = b / (nba * nba);
-    const int64_t gx = bx * kEdge + (loc & 31u);
-    const int64_t gy = by * kEdge + ((loc >> 5) & 31u);
-    const int64_t gz = bz * kEdge + (loc >> 10);
-    return (gz * G + gy) * G + gx;
 }
 
 }  // namespace
@@ -194,42 +185,49 @@ __global__ __launch_bounds__(kMaxBricks) void k_bin_plan(BinArgs a, int nb)
 // counted per brick, one reservation atomic per brick, then written to its
 // queue slot (or, past the queue's capacity, added to the overflow grid).
 __device__ __forceinline__ void bin_flush(uint32_t (*stage)[kStageCap], const uint32_t* s_fillw,
-                                          uint32_t* s_cnt, uint32_t* s_gbase,
-                                          const uint32_t* s_cap, const uint32_t* s_qbase,
-                                          int wave, int lane, int nb, int nba, int G, int xs,
-                                          int qoff, int64_t ovf_off, const BinArgs& a)
+                                          uint32_t* s_cnt, uint2* s_dst, const uint32_t* s_cap,
+                                          const uint32_t* s_qbase, int wave, int lane, int nb,
+                                          int nba, int G, int xs, int qoff, int64_t ovf_off,
+                                          const BinArgs& a)
 {
     const uint32_t my = s_fillw[wave];
+    // 1: runs per brick (zero-length entries are marked dropped)
     for (uint32_t k = lane; k < my; k += kWave) {
         const uint32_t e = stage[wave][k];
         if ((e >> 24) == 0u) {
             stage[wave][k] = kDropped;
             continue;
         }
-        const uint32_t pc = e & 0xFFFFFFu;
-        const uint32_t b = brick_of(pc, nba);
-        stage[wave][k] = (b << 23) | ((e >> 24) << 15) | local_of(pc);
-        atomicAdd(&s_cnt[b], 1u);
+        atomicAdd(&s_cnt[brick_of(e & 0xFFFFFFu, nba)], 1u);
     }
     __syncthreads();
+    // 2: one reservation per brick in its queue; the first pool slot of this
+    //    flush's runs and the room left before the queue's capacity
     for (int b = threadIdx.x; b < nb; b += kBinThreads) {
         const uint32_t c = s_cnt[b];
-        if (c)
-            s_gbase[b] = atomicAdd(a.fill + (int64_t)xs * a.qstride + qoff + b, c);
+        if (c) {
+            const uint32_t g = atomicAdd(a.fill + (int64_t)xs * a.qstride + qoff + b, c);
+            const uint32_t cap = s_cap[b];
+            s_dst[b] = make_uint2(s_qbase[b] + g, cap > g ? cap - g : 0u);
+        }
         s_cnt[b] = 0;
     }
     __syncthreads();
+    // 3: each run to its slot (brick and cell recomputed from the staged entry)
     for (uint32_t k = lane; k < my; k += kWave) {
         const uint32_t e = stage[wave][k];
         if (e == kDropped)
             continue;
-        const uint32_t b = e >> 23;
-        const uint32_t q = e & 0x7FFFFFu;
-        const uint32_t slot = s_gbase[b] + atomicAdd(&s_cnt[b], 1u);
-        if (slot < s_cap[b]) {
-            a.pool[(uint64_t)s_qbase[b] + slot] = q;
+        const uint32_t pc = e & 0xFFFFFFu;
+        const uint32_t b = brick_of(pc, nba);
+        const uint32_t rank = atomicAdd(&s_cnt[b], 1u);
+        const uint2 d = s_dst[b];
+        if (rank < d.y) {
+            a.pool[(uint64_t)(d.x + rank)] = local_of(pc) | ((e >> 24) << 15);
         } else {
-            atomicAdd(a.ovf + ovf_off + global_of(b, q & 0x7FFFu, nba, G), (int32_t)(q >> 15));
+            const int64_t cell = ((int64_t)((pc >> 16) & 255u) * G + ((pc >> 8) & 255u)) * G +
+                                 (pc & 255u);
+            atomicAdd(a.ovf + ovf_off + cell, (int32_t)(e >> 24));
             a.flags[qoff + b] = 1u;
         }
     }
@@ -250,7 +248,7 @@ __global__ __launch_bounds__(kBinThreads, 2) void k_vote_bin(const float* __rest
 {
     __shared__ uint32_t stage[kBinWaves][kStageCap];
     __shared__ uint32_t s_cnt[kMaxBricks];
-    __shared__ uint32_t s_gbase[kMaxBricks];
+    __shared__ uint2 s_dst[kMaxBricks];
     __shared__ uint32_t s_cap[kMaxBricks];
     __shared__ uint32_t s_qbase[kMaxBricks];
     // double-buffered by check parity: a wave that runs ahead writes the other
@@ -330,7 +328,7 @@ __global__ __launch_bounds__(kBinThreads, 2) void k_vote_bin(const float* __rest
             for (int w = 0; w < kBinWaves; ++w)
                 need |= s_fill[parity][w] > (uint32_t)kFlushAt;
             if (need) {
-                bin_flush(stage, s_fill[parity], s_cnt, s_gbase, s_cap, s_qbase, wave, lane, nb, nba,
+                bin_flush(stage, s_fill[parity], s_cnt, s_dst, s_cap, s_qbase, wave, lane, nb, nba,
                           G, xs, qoff, ovf_off, a);
                 fill = 0;
             }
@@ -347,7 +345,7 @@ __global__ __launch_bounds__(kBinThreads, 2) void k_vote_bin(const float* __rest
     for (int w = 0; w < kBinWaves; ++w)
         any |= s_fill[parity][w] > 0;
     if (any)
-        bin_flush(stage, s_fill[parity], s_cnt, s_gbase, s_cap, s_qbase, wave, lane, nb, nba, G, xs,
+        bin_flush(stage, s_fill[parity], s_cnt, s_dst, s_cap, s_qbase, wave, lane, nb, nba, G, xs,
                   qoff, ovf_off, a);
 }
 
