@@ -304,6 +304,7 @@ def run_batch(args):
     solver = rotvote.Solver(device=0, max_n=n, max_grid=w.grid, topk=w.topk,
                             samples_per_circle=w.samples, timing=True, stream=stream,
                             max_batch=bt.B)
+    edge, edge_ms = solver.tune_batch(x, y, offs, w.grid, w.eps_deg, reps=2)
     for _ in range(args.warmup):
         solver.solve_batch(x, y, offs, w.grid, w.eps_deg, mask=mask)
     stage = {k: 0.0 for k in rotvote.STAGE_NAMES}
@@ -344,7 +345,8 @@ def run_batch(args):
                    "n_hi": w.n_hi, "outlier_ratio": [w.rho_lo, w.rho_hi],
                    "sigma_deg": w.sigma_deg, "grid": w.grid, "samples_per_circle": w.samples,
                    "eps_deg": w.eps_deg, "topk": w.topk, "seed": w.seed,
-                   "vote_strategy": "brick (batched)"},
+                   "vote_strategy": "brick (batched)", "brick_edge": edge},
+        "brick_edge_tuning": {"chosen": edge, "ms_edge32": edge_ms[32], "ms_edge16": edge_ms[16]},
         "solves_per_s": bt.B * steps / dt,
         "stage_ms": stage_ms,
         "loop": loop if loop is None else dict(loop, speedup_of_batch=(bt.B * steps / dt) /
@@ -410,6 +412,10 @@ def main():
     solver = rotvote.Solver(device=0, max_n=inst.n, max_grid=w.grid, topk=w.topk,
                             samples_per_circle=w.samples, strategy=args.strategy, timing=True,
                             stream=stream)
+    tuned = None
+    if args.strategy == "auto":
+        best, ms = solver.tune(x, y, w.grid, w.eps_deg, reps=3)
+        tuned = {"chosen": best, "ms_global": ms["global"], "ms_brick": ms["brick"]}
     for _ in range(args.warmup):
         solver.solve(x, y, w.grid, w.eps_deg, mask=mask)
     stage = {k: 0.0 for k in rotvote.STAGE_NAMES}
@@ -451,6 +457,7 @@ def main():
                    "vote_strategy": plan["strategy"]},
         "solves_per_s": steps / dt,
         "stage_ms": stage_ms,
+        "strategy_tuning": tuned,
         "roofline": {"bound": "alu", "kernel": "vote", "achieved": achieved / 1e3,
                      "peak": ALU_PEAK_GOPS / 1e3, "unit": "TOP/s", "frac": achieved / ALU_PEAK_GOPS,
                      "traffic": measured_traffic(w.name) if plan["strategy"] == "brick" else None,

@@ -82,7 +82,9 @@ typedef struct rv_config {
     int32_t vote_strategy;       /* rv_vote_strategy */
     uint32_t flags;              /* RV_FLAG_* */
     int32_t max_batch;           /* largest B of rot_vote_solve_batch (0: no batches) */
-    int32_t reserved[3];         /* must be 0 */
+    int32_t batch_brick_edge;    /* batches' LDS bricks: 16 or 32 cells a side; 0: measured
+                                    by rot_vote_tune_batch, else 32 */
+    int32_t reserved[2];         /* must be 0 */
 } rv_config;
 
 /* Fills *cfg with: device 0, null stream, max_n 1<<20, max_grid 256, J = 8G,
@@ -121,6 +123,20 @@ rv_status rot_vote_set_stream(rv_handle *h, void *stream);
 rv_status rot_vote_solve(rv_handle *h, const float *x, const float *y, int64_t n, int32_t grid,
                          float eps_rad, float q_out[4], int64_t *inlier_count,
                          uint8_t *inlier_mask);
+
+/* Vote strategy chosen by measurement: times `reps` solves of this input
+ * (after one untimed solve) with each strategy the handle supports at this
+ * grid and remembers the faster one for the grid; later solves at that grid
+ * with vote_strategy AUTO use it.  Both strategies give the same histogram
+ * and results bit for bit, so tuning changes speed only.
+ *   mask_scratch   device uint8[n] written by the timed solves.
+ *   strategy_out   host (may be NULL): RV_VOTE_GLOBAL or RV_VOTE_BRICK.
+ *   ms_out         host float[2] (may be NULL): mean wall time per solve of
+ *                  {global, brick} in ms; -1 for a strategy not available.
+ * Needs n >= 1; reps in 1..1000. */
+rv_status rot_vote_tune(rv_handle *h, const float *x, const float *y, int64_t n, int32_t grid,
+                        float eps_rad, int32_t reps, uint8_t *mask_scratch, int32_t *strategy_out,
+                        float ms_out[2]);
 
 /* Several rotations from one vote (Alg. 1 returning several high peaks; one
  * cluster point per rotation motion in the scene).  The vote, top-K and decode
@@ -180,6 +196,16 @@ rv_status rot_vote_refine(rv_handle *h, const float *x, const float *y, int64_t 
 rv_status rot_vote_solve_batch(rv_handle *h, const float *x, const float *y, const int64_t *offsets,
                                int32_t B, int32_t grid, float eps_rad, float *q_out,
                                int64_t *inlier_count, uint8_t *inlier_mask);
+
+/* Brick size chosen by measurement for batches: times `reps` batched solves
+ * of this batch (after one untimed) with 32^3 and with 16^3 bricks and keeps
+ * the faster for this grid (results are the same either way).  Arguments as
+ * rot_vote_solve_batch; mask_scratch is its inlier_mask.  edge_out (host, may
+ * be NULL): 16 or 32; ms_out (host float[2], may be NULL): mean wall time per
+ * batch of {32, 16}.  RV_EINVAL when the config fixes batch_brick_edge. */
+rv_status rot_vote_tune_batch(rv_handle *h, const float *x, const float *y, const int64_t *offsets,
+                              int32_t B, int32_t grid, float eps_rad, int32_t reps,
+                              uint8_t *mask_scratch, int32_t *edge_out, float ms_out[2]);
 
 /* Test hook (RV_FLAG_BATCH_GRIDS): copies instance b's vote grid of the last
  * batch to the device buffer dst (grid^3 int32). */

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -112,9 +113,13 @@ struct rv_handle {
     // last batch
     bool batched = false;
     int32_t last_B = 0;
+    int32_t last_batch_edge = 0;
     int32_t last_bgrid = 0;
 
     int64_t device_bytes = 0;           // sum of the handle's device allocations
+    int8_t tuned[RV_MAX_GRID + 1] = {};  // per grid: strategy chosen by rot_vote_tune (0: none)
+    int8_t batch_edge_log2[RV_MAX_BATCH_GRID + 1] = {};  // per grid: by rot_vote_tune_batch (0: none)
+    int32_t forced_strategy = 0;         // while tuning
 
     std::string err;
 };
@@ -253,6 +258,7 @@ RV_API void rot_vote_default_config(rv_config* cfg)
     cfg->vote_strategy = RV_VOTE_AUTO;
     cfg->flags = 0;
     cfg->max_batch = 0;
+    cfg->batch_brick_edge = 0;
 }
 
 RV_API rv_status rot_vote_create(rv_handle** out, const rv_config* cfg)
@@ -273,6 +279,8 @@ RV_API rv_status rot_vote_create(rv_handle** out, const rv_config* cfg)
         return fail(nullptr, RV_EINVAL, "rot_vote_create: unknown flags");
     if (cfg->max_batch < 0)
         return fail(nullptr, RV_EINVAL, "rot_vote_create: max_batch < 0");
+    if (cfg->batch_brick_edge != 0 && cfg->batch_brick_edge != 16 && cfg->batch_brick_edge != 32)
+        return fail(nullptr, RV_EINVAL, "rot_vote_create: batch_brick_edge must be 0, 16 or 32");
     if (cfg->max_batch > 0 && cfg->vote_strategy == RV_VOTE_GLOBAL)
         return fail(nullptr, RV_EUNSUPPORTED,
                     "rot_vote_create: batches use the brick strategy (vote_strategy global)");
@@ -482,7 +490,9 @@ rv_status vote_candidates(rv_handle* h, const float* x, const float* y, int64_t 
     const std::string f(fn);
     hipStream_t s = h->stream;
     const int64_t ncell = (int64_t)grid * grid * grid;
-    int strategy = h->cfg.vote_strategy;
+    int strategy = h->forced_strategy ? h->forced_strategy : h->cfg.vote_strategy;
+    if (strategy == RV_VOTE_AUTO && h->tuned[grid] != 0)
+        strategy = h->tuned[grid];  // measured by rot_vote_tune
     if (strategy == RV_VOTE_AUTO)
         strategy = (h->brick_ok && grid >= kBrickMinGrid && grid <= rv::kMaxBrickGrid)
                        ? RV_VOTE_BRICK : RV_VOTE_GLOBAL;
@@ -521,9 +531,9 @@ rv_status vote_candidates(rv_handle* h, const float* x, const float* y, int64_t 
         RV_HIP(h, hipEventRecord(h->ev[2], s), "event");
     int nlists;
     if (brick) {
-        RV_HIP(h, rv::launch_brick_accum(grid, h->K, h->d_hist, h->d_partial, h->bin, s),
+        RV_HIP(h, rv::launch_brick_accum(grid, h->K, 5, h->d_hist, h->d_partial, h->bin, s),
                "brick accumulate");
-        const int nba = rv::brick_axis(grid);
+        const int nba = rv::brick_axis(grid, 5);
         nlists = nba * nba * nba;
     } else {
         nlists = rv::topk_blocks(ncell);
@@ -593,6 +603,50 @@ RV_API rv_status rot_vote_solve(rv_handle* h, const float* x, const float* y, in
     h->last_ncand = r.n_cand;
     h->last_winner = r.winner;
     h->last_count = r.count;
+    return RV_OK;
+}
+
+RV_API rv_status rot_vote_tune(rv_handle* h, const float* x, const float* y, int64_t n,
+                               int32_t grid, float eps_rad, int32_t reps, uint8_t* mask_scratch,
+                               int32_t* strategy_out, float ms_out[2])
+{
+    if (!h)
+        return RV_EINVAL;
+    h->err.clear();
+    if (reps < 1 || reps > 1000)
+        return fail(h, RV_EINVAL, "rot_vote_tune: reps outside 1..1000");
+    if (n < 1)
+        return fail(h, RV_EINVAL, "rot_vote_tune: needs n >= 1");
+    int32_t J = 0;
+    if (rv_status st = check_solve(h, "rot_vote_tune", x, y, n, grid, eps_rad, mask_scratch, &J))
+        return st;
+    const bool brick_ok = h->brick_ok && grid <= rv::kMaxBrickGrid;
+    const int cand[2] = {RV_VOTE_GLOBAL, RV_VOTE_BRICK};
+    float ms[2] = {-1.0f, -1.0f};
+    float q[4];
+    int64_t cnt = 0;
+    for (int c = 0; c < 2; ++c) {
+        if (cand[c] == RV_VOTE_BRICK && !brick_ok)
+            continue;
+        h->forced_strategy = cand[c];
+        rv_status st = rot_vote_solve(h, x, y, n, grid, eps_rad, q, &cnt, mask_scratch);  // warm-up
+        const auto t0 = std::chrono::steady_clock::now();
+        for (int r = 0; st == RV_OK && r < reps; ++r)
+            st = rot_vote_solve(h, x, y, n, grid, eps_rad, q, &cnt, mask_scratch);
+        const auto t1 = std::chrono::steady_clock::now();
+        h->forced_strategy = 0;
+        if (st != RV_OK)
+            return st;
+        ms[c] = (float)(std::chrono::duration<double, std::milli>(t1 - t0).count() / reps);
+    }
+    const int best = (ms[1] >= 0.0f && ms[1] < ms[0]) ? RV_VOTE_BRICK : RV_VOTE_GLOBAL;
+    h->tuned[grid] = (int8_t)best;
+    if (strategy_out)
+        *strategy_out = best;
+    if (ms_out) {
+        ms_out[0] = ms[0];
+        ms_out[1] = ms[1];
+    }
     return RV_OK;
 }
 
@@ -742,9 +796,16 @@ RV_API rv_status rot_vote_solve_batch(rv_handle* h, const float* x, const float*
     RV_HIP(h, hipSetDevice(h->device), "hipSetDevice");
     hipStream_t s = h->stream;
     const float T2 = residual_bound(eps_rad);
-    const int nba = rv::brick_axis(grid);
+    // brick edge: fixed by the config, else measured by rot_vote_tune_batch, else 32
+    const int edge_log2 = h->cfg.batch_brick_edge == 16   ? 4
+                          : h->cfg.batch_brick_edge == 32 ? 5
+                          : h->batch_edge_log2[grid]      ? h->batch_edge_log2[grid]
+                                                          : 5;
+    const int nba = rv::brick_axis(grid, edge_log2);
     const int nb = nba * nba * nba;
     const int64_t nq = (int64_t)B * nb;
+    // slack per queue: smaller bricks, more queues per instance, less slack each
+    const uint64_t slack = (uint64_t)std::min(256, std::max(64, 2048 / nb));
 
     // The staging buffers are reused: nothing of an earlier call may still read them.
     RV_HIP(h, hipStreamSynchronize(s), "sync before batch plan");
@@ -767,7 +828,7 @@ RV_API rv_status rot_vote_solve_batch(rv_handle* h, const float* x, const float*
         const int64_t lo = offsets[b], hi = offsets[b + 1];
         for (int64_t f = lo; f < hi; f += rv::kUnitSize)
             h->h_units[nunits++] = rv::Unit{b, (int32_t)std::min<int64_t>(rv::kUnitSize, hi - f), f};
-        const uint64_t c = hi > lo ? (((uint64_t)std::ceil(share * (double)(hi - lo)) + kBatchCapSlack + 63u) & ~63ull)
+        const uint64_t c = hi > lo ? (((uint64_t)std::ceil(share * (double)(hi - lo)) + slack + 63u) & ~63ull)
                                    : 0u;
         for (int k = 0; k < nb; ++k)
             cap[(int64_t)b * nb + k] = (uint32_t)std::min<uint64_t>(c, 0x7FFFFFC0u);
@@ -788,6 +849,7 @@ RV_API rv_status rot_vote_solve_batch(rv_handle* h, const float* x, const float*
 
     const bool tm = h->timing;
     h->batched = true;
+    h->last_batch_edge = 1 << edge_log2;
     h->last_B = B;
     h->last_bgrid = grid;
     h->last_J = J;
@@ -819,10 +881,12 @@ RV_API rv_status rot_vote_solve_batch(rv_handle* h, const float* x, const float*
     a.nsets = 1;
     a.qstride = (int32_t)nq;
     a.batch = B;
-    RV_HIP(h, rv::launch_bin_vote_batch(x, y, n, grid, J, h->d_table, a, (int)nunits, s), "batch vote");
+    RV_HIP(h, rv::launch_bin_vote_batch(x, y, n, grid, J, edge_log2, h->d_table, a, (int)nunits, s),
+           "batch vote");
     if (tm)
         RV_HIP(h, hipEventRecord(h->ev[2], s), "event");
-    RV_HIP(h, rv::launch_brick_accum(grid, h->K, h->batch_grids ? h->d_bgrids : nullptr, h->d_bpartial, a, s),
+    RV_HIP(h, rv::launch_brick_accum(grid, h->K, edge_log2, h->batch_grids ? h->d_bgrids : nullptr,
+                                     h->d_bpartial, a, s),
            "batch brick accumulate");
     if (tm)
         RV_HIP(h, hipEventRecord(h->ev[3], s), "event");
@@ -842,6 +906,53 @@ RV_API rv_status rot_vote_solve_batch(rv_handle* h, const float* x, const float*
         const rv::Result& r = h->h_bresult[b];
         std::memcpy(q_out + 4 * (int64_t)b, r.q, sizeof(r.q));
         inlier_count[b] = r.count;
+    }
+    return RV_OK;
+}
+
+RV_API rv_status rot_vote_tune_batch(rv_handle* h, const float* x, const float* y,
+                                     const int64_t* offsets, int32_t B, int32_t grid, float eps_rad,
+                                     int32_t reps, uint8_t* mask_scratch, int32_t* edge_out,
+                                     float ms_out[2])
+{
+    if (!h)
+        return RV_EINVAL;
+    h->err.clear();
+    if (reps < 1 || reps > 1000)
+        return fail(h, RV_EINVAL, "rot_vote_tune_batch: reps outside 1..1000");
+    if (B < 1 || B > h->max_batch)
+        return fail(h, RV_EINVAL, "rot_vote_tune_batch: B outside 1..max_batch");
+    if (h->cfg.batch_brick_edge != 0)
+        return fail(h, RV_EINVAL, "rot_vote_tune_batch: the config fixes batch_brick_edge");
+    if (grid < 1 || grid > h->batch_grid)
+        return fail(h, RV_EINVAL, "rot_vote_tune_batch: grid outside 1..min(max_grid, 64)");
+    std::vector<float> q(4 * (size_t)B);
+    std::vector<int64_t> cnt(B);
+    const int edges[2] = {5, 4};
+    float ms[2] = {-1.0f, -1.0f};
+    const int8_t saved = h->batch_edge_log2[grid];
+    for (int c = 0; c < 2; ++c) {
+        h->batch_edge_log2[grid] = (int8_t)edges[c];
+        rv_status st = rot_vote_solve_batch(h, x, y, offsets, B, grid, eps_rad, q.data(), cnt.data(),
+                                            mask_scratch);  // warm-up (and argument checks)
+        const auto t0 = std::chrono::steady_clock::now();
+        for (int r = 0; st == RV_OK && r < reps; ++r)
+            st = rot_vote_solve_batch(h, x, y, offsets, B, grid, eps_rad, q.data(), cnt.data(),
+                                      mask_scratch);
+        const auto t1 = std::chrono::steady_clock::now();
+        if (st != RV_OK) {
+            h->batch_edge_log2[grid] = saved;
+            return st;
+        }
+        ms[c] = (float)(std::chrono::duration<double, std::milli>(t1 - t0).count() / reps);
+    }
+    const int best = ms[1] < ms[0] ? 4 : 5;
+    h->batch_edge_log2[grid] = (int8_t)best;
+    if (edge_out)
+        *edge_out = 1 << best;
+    if (ms_out) {
+        ms_out[0] = ms[0];
+        ms_out[1] = ms[1];
     }
     return RV_OK;
 }

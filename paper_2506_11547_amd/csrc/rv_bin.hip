@@ -25,8 +25,16 @@ namespace rv {
 
 namespace {
 
-constexpr int kEdge = 32;
-constexpr int kBrickCells = kEdge * kEdge * kEdge;
+// Bricks are 2^kLog cells on a side: 32 (kLog 5, 128 KiB of LDS, one solve and
+// batches) or 16 (kLog 4, 16 KiB, batches: many workgroups per CU).
+template <int kLog>
+struct Brick {
+    static constexpr int kEdge = 1 << kLog;
+    static constexpr int kCells = kEdge * kEdge * kEdge;
+    static constexpr uint32_t kMask = (uint32_t)kEdge - 1u;
+    static constexpr int kThreads = kLog == 5 ? 1024 : 256;  // accumulation workgroup
+    static constexpr int kWaves = kThreads / kWave;
+};
 constexpr int kSets = kQueueSets;
 constexpr int kBinWaves = 8;
 constexpr int kBinThreads = kBinWaves * kWave;
@@ -40,19 +48,20 @@ constexpr int kFlushAt = kStageCap - kWave * kStep - kWave;
 // Marks a dropped zero-length staged run.  A staged run never equals it: its
 // length (bits 24..31) is at most 240, never 0xFF.
 constexpr uint32_t kDropped = 0xFFFFFFFFu;
-constexpr int kAccumThreads = 1024;
-constexpr int kAccumWaves = kAccumThreads / kWave;
-
+template <int kLog>
 __device__ __forceinline__ uint32_t brick_of(uint32_t pc, int nba)
 {
     const uint32_t ix = pc & 255u, iy = (pc >> 8) & 255u, iz = (pc >> 16) & 255u;
-    return __umul24(__umul24(iz >> 5, (uint32_t)nba) + (iy >> 5), (uint32_t)nba) + (ix >> 5);
+    return __umul24(__umul24(iz >> kLog, (uint32_t)nba) + (iy >> kLog), (uint32_t)nba) +
+           (ix >> kLog);
 }
 
+template <int kLog>
 __device__ __forceinline__ uint32_t local_of(uint32_t pc)
 {
+    constexpr uint32_t m = Brick<kLog>::kMask;
     const uint32_t ix = pc & 255u, iy = (pc >> 8) & 255u, iz = (pc >> 16) & 255u;
-    return ((iz & 31u) << 10) | ((iy & 31u) << 5) | (ix & 31u);
+    return ((iz & m) << (2 * kLog)) | ((iy & m) << kLog) | (ix & m);
 }
 
 }  // namespace
@@ -88,7 +97,7 @@ __global__ __launch_bounds__(256) void k_bin_estimate(const float* __restrict__ 
                           [&](const Cell& cell, int) {
                               const uint32_t pc = packed_coords(cell);
                               if (ok && pc != cur)
-                                  atomicAdd(&s_est[brick_of(pc, nba)], 1u);
+                                  atomicAdd(&s_est[brick_of<5>(pc, nba)], 1u);
                               cur = pc;
                           });
     }
@@ -184,6 +193,7 @@ __global__ __launch_bounds__(kMaxBricks) void k_bin_plan(BinArgs a, int nb)
 // Flush: each run is rewritten as brick << 23 | length << 15 | local cell,
 // counted per brick, one reservation atomic per brick, then written to its
 // queue slot (or, past the queue's capacity, added to the overflow grid).
+template <int kLog>
 __device__ __forceinline__ void bin_flush(uint32_t (*stage)[kStageCap], const uint32_t* s_fillw,
                                           uint32_t* s_cnt, uint2* s_dst, const uint32_t* s_cap,
                                           const uint32_t* s_qbase, int wave, int lane, int nb,
@@ -198,7 +208,7 @@ __device__ __forceinline__ void bin_flush(uint32_t (*stage)[kStageCap], const ui
             stage[wave][k] = kDropped;
             continue;
         }
-        atomicAdd(&s_cnt[brick_of(e & 0xFFFFFFu, nba)], 1u);
+        atomicAdd(&s_cnt[brick_of<kLog>(e & 0xFFFFFFu, nba)], 1u);
     }
     __syncthreads();
     // 2: one reservation per brick in its queue; the first pool slot of this
@@ -219,11 +229,11 @@ __device__ __forceinline__ void bin_flush(uint32_t (*stage)[kStageCap], const ui
         if (e == kDropped)
             continue;
         const uint32_t pc = e & 0xFFFFFFu;
-        const uint32_t b = brick_of(pc, nba);
+        const uint32_t b = brick_of<kLog>(pc, nba);
         const uint32_t rank = atomicAdd(&s_cnt[b], 1u);
         const uint2 d = s_dst[b];
         if (rank < d.y) {
-            a.pool[(uint64_t)(d.x + rank)] = local_of(pc) | ((e >> 24) << 15);
+            a.pool[(uint64_t)(d.x + rank)] = local_of<kLog>(pc) | ((e >> 24) << 15);
         } else {
             const int64_t cell = ((int64_t)((pc >> 16) & 255u) * G + ((pc >> 8) & 255u)) * G +
                                  (pc & 255u);
@@ -239,6 +249,7 @@ __device__ __forceinline__ void bin_flush(uint32_t (*stage)[kStageCap], const ui
 
 // One block per (512 correspondences, chunk of samples); chunks are whole run
 // blocks, so splitting J across blocks only adds run boundaries.
+template <int kLog>
 __global__ __launch_bounds__(kBinThreads, 2) void k_vote_bin(const float* __restrict__ x,
                                                               const float* __restrict__ y,
                                                               int64_t n, int G, float H, float gm,
@@ -328,7 +339,7 @@ __global__ __launch_bounds__(kBinThreads, 2) void k_vote_bin(const float* __rest
             for (int w = 0; w < kBinWaves; ++w)
                 need |= s_fill[parity][w] > (uint32_t)kFlushAt;
             if (need) {
-                bin_flush(stage, s_fill[parity], s_cnt, s_dst, s_cap, s_qbase, wave, lane, nb, nba,
+                bin_flush<kLog>(stage, s_fill[parity], s_cnt, s_dst, s_cap, s_qbase, wave, lane, nb, nba,
                           G, xs, qoff, ovf_off, a);
                 fill = 0;
             }
@@ -345,16 +356,22 @@ __global__ __launch_bounds__(kBinThreads, 2) void k_vote_bin(const float* __rest
     for (int w = 0; w < kBinWaves; ++w)
         any |= s_fill[parity][w] > 0;
     if (any)
-        bin_flush(stage, s_fill[parity], s_cnt, s_dst, s_cap, s_qbase, wave, lane, nb, nba, G, xs,
+        bin_flush<kLog>(stage, s_fill[parity], s_cnt, s_dst, s_cap, s_qbase, wave, lane, nb, nba, G, xs,
                   qoff, ovf_off, a);
 }
 
 // ----------------------------------------------------------- accumulate
 
-__global__ __launch_bounds__(kAccumThreads, 1) void k_brick_accum(BinArgs a, int G, int nba, int K,
+template <int kLog>
+__global__ __launch_bounds__(Brick<kLog>::kThreads) void k_brick_accum(BinArgs a, int G, int nba, int K,
                                                                    int32_t* __restrict__ grid,
                                                                    uint64_t* __restrict__ partial)
 {
+    using Br = Brick<kLog>;
+    constexpr int kEdge = Br::kEdge;
+    constexpr int kBrickCells = Br::kCells;
+    constexpr int kAccumThreads = Br::kThreads;
+    constexpr int kAccumWaves = Br::kWaves;
     __shared__ uint32_t acc[kBrickCells];
     __shared__ uint64_t lists[kAccumWaves][kWave];
     __shared__ uint32_t s_floor;
@@ -429,7 +446,7 @@ __global__ __launch_bounds__(kAccumThreads, 1) void k_brick_accum(BinArgs a, int
     const bool vec = (G % 4) == 0;
     uint32_t lmax = 0;
     for (int c = threadIdx.x * 4; c < kBrickCells; c += kAccumThreads * 4) {
-        const int lx = c & 31, ly = (c >> 5) & 31, lz = c >> 10;
+        const int lx = c & (kEdge - 1), ly = (c >> kLog) & (kEdge - 1), lz = c >> (2 * kLog);
         const int gx = bx * kEdge + lx, gy = by * kEdge + ly, gz = bz * kEdge + lz;
         uint32_t val[4] = {0u, 0u, 0u, 0u};
         const bool row = gy < G && gz < G;
@@ -475,7 +492,7 @@ __global__ __launch_bounds__(kAccumThreads, 1) void k_brick_accum(BinArgs a, int
     // Pass 2: the sorted list of the brick's best cells at or above the floor.
     uint64_t list = 0;
     for (int c = threadIdx.x * 4; c < kBrickCells; c += kAccumThreads * 4) {
-        const int lx = c & 31, ly = (c >> 5) & 31, lz = c >> 10;
+        const int lx = c & (kEdge - 1), ly = (c >> kLog) & (kEdge - 1), lz = c >> (2 * kLog);
         const int gx = bx * kEdge + lx, gy = by * kEdge + ly, gz = bz * kEdge + lz;
         const bool row = gy < G && gz < G;
         const uint4 v4 = acc4[c >> 2];
@@ -497,12 +514,12 @@ __global__ __launch_bounds__(kAccumThreads, 1) void k_brick_accum(BinArgs a, int
 
 // ------------------------------------------------------------- launchers
 
-int brick_axis(int G) { return (G + kEdge - 1) / kEdge; }
+int brick_axis(int G, int edge_log2) { return (G + (1 << edge_log2) - 1) >> edge_log2; }
 
 hipError_t launch_bin_prepare(const float* x, const float* y, int64_t n, int G, int J,
                               const float2* table, const BinArgs& a, hipStream_t s)
 {
-    const int nba = brick_axis(G);
+    const int nba = brick_axis(G, 5);
     const int nb = nba * nba * nba;
     if (G > kMaxBrickGrid || nb > kMaxBricks)
         return hipErrorInvalidValue;
@@ -540,36 +557,50 @@ hipError_t launch_bin_vote(const float* x, const float* y, int64_t n, int G, int
     const int64_t blocks = ngroups * nchunks;
     if (blocks > INT32_MAX || G > kMaxBrickGrid)
         return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_vote_bin, dim3((unsigned)blocks), dim3(kBinThreads), 0, s, x, y, n, G,
+    hipLaunchKernelGGL(k_vote_bin<5>, dim3((unsigned)blocks), dim3(kBinThreads), 0, s, x, y, n, G,
                        (float)G * 0.5f, (float)G - 0.5f, J, chunk, (int)ngroups, table,
-                       brick_axis(G), a);
+                       brick_axis(G, 5), a);
     return hipGetLastError();
 }
 
-hipError_t launch_brick_accum(int G, int K, int32_t* grid, uint64_t* partial, const BinArgs& a,
-                              hipStream_t s)
+hipError_t launch_brick_accum(int G, int K, int edge_log2, int32_t* grid, uint64_t* partial,
+                              const BinArgs& a, hipStream_t s)
 {
-    const int nba = brick_axis(G);
+    if (edge_log2 != 4 && edge_log2 != 5)
+        return hipErrorInvalidValue;
+    const int nba = brick_axis(G, edge_log2);
     const int nb = nba * nba * nba;
     if (G > kMaxBrickGrid || nb > kMaxBricks)
         return hipErrorInvalidValue;
     const int blocks = a.batch ? a.batch * nb : nb;
     if (K < 1 || K > kWave)
         return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_brick_accum, dim3(blocks), dim3(kAccumThreads), 0, s, a, G, nba, K, grid,
-                       partial);
+    if (edge_log2 == 5)
+        hipLaunchKernelGGL(k_brick_accum<5>, dim3(blocks), dim3(Brick<5>::kThreads), 0, s, a, G, nba,
+                           K, grid, partial);
+    else
+        hipLaunchKernelGGL(k_brick_accum<4>, dim3(blocks), dim3(Brick<4>::kThreads), 0, s, a, G, nba,
+                           K, grid, partial);
     return hipGetLastError();
 }
 
 hipError_t launch_bin_vote_batch(const float* x, const float* y, int64_t n, int G, int J,
-                                 const float2* table, const BinArgs& a, int nunits, hipStream_t s)
+                                 int edge_log2, const float2* table, const BinArgs& a, int nunits,
+                                 hipStream_t s)
 {
     if (nunits <= 0)
         return hipSuccess;
-    if (G > kMaxBrickGrid || !a.units)
+    if (G > kMaxBrickGrid || !a.units || (edge_log2 != 4 && edge_log2 != 5))
         return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_vote_bin, dim3((unsigned)nunits), dim3(kBinThreads), 0, s, x, y, n, G,
-                       (float)G * 0.5f, (float)G - 0.5f, J, J, 1, table, brick_axis(G), a);
+    const int nba = brick_axis(G, edge_log2);
+    if (nba * nba * nba > kMaxBricks)
+        return hipErrorInvalidValue;
+    if (edge_log2 == 5)
+        hipLaunchKernelGGL(k_vote_bin<5>, dim3((unsigned)nunits), dim3(kBinThreads), 0, s, x, y, n,
+                           G, (float)G * 0.5f, (float)G - 0.5f, J, J, 1, table, nba, a);
+    else
+        hipLaunchKernelGGL(k_vote_bin<4>, dim3((unsigned)nunits), dim3(kBinThreads), 0, s, x, y, n,
+                           G, (float)G * 0.5f, (float)G - 0.5f, J, J, 1, table, nba, a);
     return hipGetLastError();
 }
 

@@ -72,7 +72,8 @@ struct BinArgs {
     int32_t batch;       // number of instances (0 for one solve)
 };
 
-int brick_axis(int G);
+// bricks per axis for bricks of 2^edge_log2 cells (5: 32, one solve; 4 or 5 in batches)
+int brick_axis(int G, int edge_log2);
 // estimate + plan (queue capacities); then the binned vote; then per-brick
 // accumulation, which writes every cell of the grid and one sorted list per
 // brick that holds the brick's K best cells
@@ -80,16 +81,17 @@ hipError_t launch_bin_prepare(const float* x, const float* y, int64_t n, int G, 
                               const float2* table, const BinArgs& a, hipStream_t s);
 hipError_t launch_bin_vote(const float* x, const float* y, int64_t n, int G, int J,
                            const float2* table, const BinArgs& a, hipStream_t s);
-hipError_t launch_brick_accum(int G, int K, int32_t* grid, uint64_t* partial, const BinArgs& a,
-                              hipStream_t s);
+hipError_t launch_brick_accum(int G, int K, int edge_log2, int32_t* grid, uint64_t* partial,
+                              const BinArgs& a, hipStream_t s);
 
 // Batches (G <= kMaxBatchGrid): the binned vote over work units, then the
 // per-instance top-K merge, rescore and mask.
 constexpr int kMaxBatchGrid = 64;
-constexpr int kMaxBatchBricks = 8;   // (64 / 32)^3
+constexpr int kMaxBatchBricks = 64;  // (64 / 16)^3
 constexpr int kUnitSize = 512;       // correspondences per work unit
 hipError_t launch_bin_vote_batch(const float* x, const float* y, int64_t n, int G, int J,
-                                 const float2* table, const BinArgs& a, int nunits, hipStream_t s);
+                                 int edge_log2, const float2* table, const BinArgs& a, int nunits,
+                                 hipStream_t s);
 hipError_t launch_batch_finish(const float* x, const float* y, int64_t n, float T2, int B, int nb,
                                int K, int G, const uint64_t* partial, const Unit* units, int nunits,
                                const int64_t* offsets, const Candidates& c, uint8_t* mask,

@@ -39,7 +39,9 @@ EXPORTS = ("rot_vote_default_config", "rot_vote_create", "rot_vote_destroy",
            "rot_vote_get_histogram", "rot_vote_get_topk", "rot_vote_get_plan",
            "rot_vote_get_timings", "rot_vote_solve_batch", "rot_vote_get_batch_histogram",
            "rot_vote_get_batch_topk", "rot_vote_refine", "rot_vote_solve_multi",
-           "rot_vote_get_footprint", "rot_vote_server_default_config", "rot_vote_server_create",
+           "rot_vote_get_footprint", "rot_vote_tune", "rot_vote_tune_batch",
+           "rot_vote_server_default_config",
+           "rot_vote_server_create",
            "rot_vote_server_destroy", "rot_vote_server_submit", "rot_vote_server_wait",
            "rot_vote_server_stats", "rot_vote_server_last_error")
 
@@ -48,7 +50,8 @@ class RvConfig(ct.Structure):
     _fields_ = [("device", ct.c_int32), ("stream", ct.c_void_p), ("max_n", ct.c_int64),
                 ("max_grid", ct.c_int32), ("samples_per_circle", ct.c_int32),
                 ("topk", ct.c_int32), ("vote_strategy", ct.c_int32), ("flags", ct.c_uint32),
-                ("max_batch", ct.c_int32), ("reserved", ct.c_int32 * 3)]
+                ("max_batch", ct.c_int32), ("batch_brick_edge", ct.c_int32),
+                ("reserved", ct.c_int32 * 2)]
 
 
 class ServerConfig(ct.Structure):
@@ -127,6 +130,12 @@ def load_library(path: Path | str = LIB_PATH) -> ct.CDLL:
     L.rot_vote_solve_multi.argtypes = [vp, vp, vp, i64, i32, f32, i32, f32, i64, ct.POINTER(f32),
                                        ct.POINTER(i64), ct.POINTER(i32), vp]
     L.rot_vote_solve_multi.restype = i32
+    L.rot_vote_tune.argtypes = [vp, vp, vp, i64, i32, f32, i32, vp, ct.POINTER(i32),
+                                ct.POINTER(f32 * 2)]
+    L.rot_vote_tune.restype = i32
+    L.rot_vote_tune_batch.argtypes = [vp, vp, vp, ct.POINTER(i64), i32, i32, f32, i32, vp,
+                                      ct.POINTER(i32), ct.POINTER(f32 * 2)]
+    L.rot_vote_tune_batch.restype = i32
     L.rot_vote_get_footprint.argtypes = [vp, ct.POINTER(i64)]
     L.rot_vote_get_footprint.restype = i32
     L.rot_vote_server_default_config.argtypes = [ct.POINTER(ServerConfig)]
@@ -159,7 +168,7 @@ class Solver:
     def __init__(self, device: int = 0, max_n: int = 1 << 20, max_grid: int = 256,
                  topk: int = 16, samples_per_circle: int = 0, strategy: str = "auto",
                  timing: bool = False, stream: torch.cuda.Stream | None = None,
-                 max_batch: int = 0, batch_grids: bool = False):
+                 max_batch: int = 0, batch_grids: bool = False, batch_brick_edge: int = 0):
         if not torch.cuda.is_available():
             raise RuntimeError("rotvote needs a HIP GPU; none is visible")
         self._lib = load_library()
@@ -176,6 +185,7 @@ class Solver:
         cfg.vote_strategy = STRATEGIES[strategy]
         cfg.flags = (FLAG_TIMING if timing else 0) | (FLAG_BATCH_GRIDS if batch_grids else 0)
         cfg.max_batch = max_batch
+        cfg.batch_brick_edge = batch_brick_edge
         h = ct.c_void_p()
         st = self._lib.rot_vote_create(ct.byref(h), ct.byref(cfg))
         if st != RV_OK:
@@ -244,6 +254,22 @@ class Solver:
                                 mask.data_ptr() if n else 0)
         return q, cnt, mask
 
+    def tune(self, x: torch.Tensor, y: torch.Tensor, grid: int, eps_deg: float, reps: int = 3):
+        """Measures both vote strategies on this input and fixes the faster one
+        for `grid` (AUTO solves).  Returns (strategy name, {name: ms})."""
+        x = x.contiguous()
+        y = y.contiguous()
+        n = x.shape[1]
+        scratch = torch.empty(n, dtype=torch.uint8, device=x.device)
+        st = ct.c_int32()
+        ms = (ct.c_float * 2)()
+        self._check(self._lib.rot_vote_tune(self._h, ct.c_void_p(x.data_ptr()),
+                                            ct.c_void_p(y.data_ptr()), n, grid,
+                                            ct.c_float(eps_deg_to_rad(eps_deg)), reps,
+                                            ct.c_void_p(scratch.data_ptr()), ct.byref(st),
+                                            ct.byref(ms)))
+        return STRATEGY_NAMES[st.value], {"global": ms[0], "brick": ms[1]}
+
     def solve_multi_raw(self, x_ptr: int, y_ptr: int, n: int, grid: int, eps_rad: float,
                         max_models: int, sep_rad: float, min_inliers: int, labels_ptr: int):
         """Direct C-ABI call; returns (q [M][4], counts [M])."""
@@ -308,6 +334,24 @@ class Solver:
         n = x.shape[1]
         return self.refine_raw(x.data_ptr(), y.data_ptr(), n, eps_deg_to_rad(eps_deg), max_rounds,
                                q, mask.data_ptr() if n else 0)
+
+    def tune_batch(self, x: torch.Tensor, y: torch.Tensor, offsets, grid: int, eps_deg: float,
+                   reps: int = 2):
+        """Measures 32^3 and 16^3 bricks on this batch and keeps the faster for
+        `grid`.  Returns (edge, {32: ms, 16: ms})."""
+        x = x.contiguous()
+        y = y.contiguous()
+        B = len(offsets) - 1
+        offs = (ct.c_int64 * (B + 1))(*[int(o) for o in offsets])
+        scratch = torch.empty(max(1, x.shape[1]), dtype=torch.uint8, device=x.device)
+        edge = ct.c_int32()
+        ms = (ct.c_float * 2)()
+        self._check(self._lib.rot_vote_tune_batch(self._h, ct.c_void_p(x.data_ptr()),
+                                                  ct.c_void_p(y.data_ptr()), offs, B, grid,
+                                                  ct.c_float(eps_deg_to_rad(eps_deg)), reps,
+                                                  ct.c_void_p(scratch.data_ptr()), ct.byref(edge),
+                                                  ct.byref(ms)))
+        return edge.value, {32: ms[0], 16: ms[1]}
 
     def solve_batch_raw(self, x_ptr: int, y_ptr: int, offsets, grid: int, eps_rad: float,
                         mask_ptr: int):

@@ -68,14 +68,15 @@ def mixed_instances(seed):
     return out
 
 
+@pytest.mark.parametrize("edge", [32, 16])
 @pytest.mark.parametrize("G,J,K", [(1, 5, 4), (8, 64, 16), (33, 241, 8), (64, 512, 16),
                                    (64, 300, 64)])
-def test_mixed_batch_matches_oracle(rv, orc, G, J, K):
+def test_mixed_batch_matches_oracle(rv, orc, G, J, K, edge):
     inst = mixed_instances(G)
     x, y, offs = concat(inst)
     eps = 1.5
     with rv.Solver(max_n=int(offs[-1]), max_grid=G, topk=K, samples_per_circle=J,
-                   max_batch=len(inst), batch_grids=True) as s:
+                   max_batch=len(inst), batch_grids=True, batch_brick_edge=edge) as s:
         q, cnt, mask = s.solve_batch(dev(x), dev(y), offs, G, eps)
         m = mask.cpu().numpy()
         for b, (xb, yb) in enumerate(inst):
@@ -100,7 +101,8 @@ def test_handle_reuse_and_smaller_second_batch(rv, orc):
                                16, orc)
 
 
-def test_batch_queue_overflow_is_exact(rv, orc):
+@pytest.mark.parametrize("edge", [32, 16])
+def test_batch_queue_overflow_is_exact(rv, orc, edge):
     """One instance repeats a single correspondence, so its heaviest bricks get
     several times the planned share of runs and the excess takes the
     per-instance overflow grid; neighbours in the batch must be unaffected."""
@@ -111,7 +113,8 @@ def test_batch_queue_overflow_is_exact(rv, orc):
     c = datagen.make_instance(2500, 0.5, 0.5, 22)
     inst = [(a.x, a.y), (xr, yr), (c.x, c.y), (xr[:, :1500], yr[:, :1500])]
     x, y, offs = concat(inst)
-    with rv.Solver(max_n=int(offs[-1]), max_grid=64, topk=16, max_batch=4, batch_grids=True) as s:
+    with rv.Solver(max_n=int(offs[-1]), max_grid=64, topk=16, max_batch=4, batch_grids=True,
+                   batch_brick_edge=edge) as s:
         for _ in range(2):  # overflow grids must be left zeroed
             q, cnt, mask = s.solve_batch(dev(x), dev(y), offs, 64, 1.0)
             m = mask.cpu().numpy()
@@ -170,6 +173,27 @@ def test_full_batch_workload_sampled(rv, orc):
         # few instances with about 50 inliers lose to an outlier peak.
         assert np.mean(err[enough] < 3 * bound) > 0.99, np.sort(err[enough])[-5:]
         assert np.mean(err < bound) > 0.95, np.mean(err < bound)
+
+
+def test_tuned_brick_edge_changes_speed_only(rv):
+    """rot_vote_tune_batch times 32^3 and 16^3 bricks on the batch and keeps
+    the faster; results are identical either way."""
+    bt = datagen.make_batch(300, 100, 8000, 0.5, 0.99, 0.5, 17)
+    x, y = dev(bt.x), dev(bt.y)
+    with rv.Solver(max_n=int(bt.offsets[-1]), max_grid=64, topk=16, samples_per_circle=512,
+                   max_batch=bt.B) as s:
+        q0, c0, m0 = s.solve_batch(x, y, bt.offsets, 64, 1.0)
+        m0 = m0.clone()
+        edge, ms = s.tune_batch(x, y, bt.offsets, 64, 1.0, reps=1)
+        assert edge in (16, 32) and ms[16] > 0 and ms[32] > 0
+        assert edge == (16 if ms[16] < ms[32] else 32)
+        q1, c1, m1 = s.solve_batch(x, y, bt.offsets, 64, 1.0)
+        assert q0 == q1 and c0 == c1 and torch.equal(m0, m1)
+    with rv.Solver(max_n=1000, max_grid=64, max_batch=4, batch_brick_edge=16) as s:
+        with pytest.raises(rv.RotVoteError):
+            s.tune_batch(x, y, [0, 10], 64, 1.0)
+    with pytest.raises(rv.RotVoteError):
+        rv.Solver(max_n=1000, max_grid=64, max_batch=4, batch_brick_edge=8)
 
 
 def test_batch_error_conventions(rv):

@@ -255,3 +255,28 @@ def test_error_conventions(rv):
                                    1 << 21, 256, ct.c_float(0.01), ct.byref(q), ct.byref(cnt),
                                    ct.c_void_p(m.data_ptr()))
         assert st == rv.RV_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("G", [48, 96, 200])
+def test_tuned_strategy_changes_speed_only(rv, orc, G):
+    """rot_vote_tune measures both strategies on the caller's input and fixes
+    the faster for that grid; the solve's results are unchanged."""
+    inst = datagen.make_instance(30000, 0.9, 1.0, 31 + G)
+    with rv.Solver(max_n=inst.n, max_grid=256, topk=16) as s:
+        x, y = dev(inst.x), dev(inst.y)
+        q0, c0, m0 = s.solve(x, y, G, 1.0)
+        m0 = m0.clone()
+        best, ms = s.tune(x, y, G, 1.0, reps=2)
+        assert best in ("global", "brick") and ms["global"] > 0 and ms["brick"] > 0
+        assert best == ("brick" if ms["brick"] < ms["global"] else "global")
+        q1, c1, m1 = s.solve(x, y, G, 1.0)
+        assert s.plan()["strategy"] == best
+        assert q0 == q1 and c0 == c1 and torch.equal(m0, m1)
+        import ctypes as ct
+        st = s._lib.rot_vote_tune(s._h, ct.c_void_p(x.data_ptr()), ct.c_void_p(y.data_ptr()),
+                                  inst.n, G, ct.c_float(0.01), 0, ct.c_void_p(m1.data_ptr()),
+                                  None, None)
+        assert st == rv.RV_EINVAL
+    o = orc.solve(inst.x, inst.y, G, 8 * G, eps_rad(rv, 1.0), 16)
+    assert np.array_equal(np.float32(q1).view(np.uint32), o["q"].view(np.uint32))
+    assert c1 == o["count"]
