@@ -56,7 +56,7 @@ typedef enum rv_status {
 typedef enum rv_vote_strategy {
     RV_VOTE_AUTO = 0,      /* chosen per (G, n) from measurements */
     RV_VOTE_GLOBAL = 1,    /* run-coalesced atomics straight into the grid */
-    RV_VOTE_BRICK = 2      /* runs binned by brick, bricks accumulated in LDS */
+    RV_VOTE_BRICK = 2      /* runs binned by brick, bricks accumulated in LDS (grid <= 384) */
 } rv_vote_strategy;
 
 enum {

@@ -349,13 +349,17 @@ RV_API rv_status rot_vote_create(rv_handle** out, const rv_config* cfg)
     h->max_batch = cfg->max_batch;
     h->batch_grid = std::min(h->max_grid, rv::kMaxBatchGrid);
     h->batch_grids = (cfg->flags & RV_FLAG_BATCH_GRIDS) != 0;
-    const bool want_brick = cfg->vote_strategy != RV_VOTE_GLOBAL && h->max_grid <= rv::kMaxBrickGrid;
+    // the brick strategy serves grids up to kMaxBrickGrid (its scratch is sized for
+    // min(max_grid, kMaxBrickGrid)); larger grids use global atomics
+    const bool want_brick = cfg->vote_strategy != RV_VOTE_GLOBAL && h->max_grid >= 1;
+    const int64_t brick_grid = std::min<int64_t>(h->max_grid, rv::kMaxBrickGrid);
+    const size_t brick_cells = (size_t)(brick_grid * brick_grid * brick_grid);
     uint64_t runs = 0;
     if (want_brick) {
         // One solve: about 1.7 G runs per circle are expected at J = 8 G (at
         // most J); room for 3 G per circle plus the per-queue slack.
         const uint64_t per_circle = (uint64_t)std::min<int64_t>(h->max_J, 3 * (int64_t)h->max_grid);
-        runs = (uint64_t)h->max_n * per_circle + (uint64_t)rv::kQueueSets * rv::kMaxBricks * 320u;
+        runs = (uint64_t)h->max_n * per_circle + (uint64_t)rv::kQueueSets * rv::kMaxBricksAll * 320u;
     }
     if (h->max_batch > 0) {
         // A batch reserves kBatchCapFactor expected runs per circle plus the
@@ -371,21 +375,21 @@ RV_API rv_status rot_vote_create(rv_handle** out, const rv_config* cfg)
     if (runs > 0 && (e = dev_alloc(h, &h->bin.pool, runs * sizeof(uint32_t))) != hipSuccess)
         return bail(e, "brick run pool");
     h->bin.nsets = rv::kQueueSets;
-    h->bin.qstride = rv::kMaxBricks;
+    h->bin.qstride = rv::kMaxBricksAll;
     h->bin.units = nullptr;
     h->bin.batch = 0;
     if (want_brick) {
-        const size_t nq = (size_t)rv::kQueueSets * rv::kMaxBricks;
+        const size_t nq = (size_t)rv::kQueueSets * rv::kMaxBricksAll;
         if ((e = dev_alloc(h, &h->bin.fill, nq * sizeof(uint32_t))) != hipSuccess ||
             (e = dev_alloc(h, &h->bin.qbase, nq * sizeof(uint32_t))) != hipSuccess ||
-            (e = dev_alloc(h, &h->bin.cap, rv::kMaxBricks * sizeof(uint32_t))) != hipSuccess ||
-            (e = dev_alloc(h, &h->bin.est, rv::kMaxBricks * sizeof(uint32_t))) != hipSuccess ||
-            (e = dev_alloc(h, &h->bin.flags, rv::kMaxBricks * sizeof(uint32_t))) != hipSuccess ||
-            (e = dev_alloc(h, &h->bin.order, rv::kMaxBricks * sizeof(uint32_t))) != hipSuccess ||
-            (e = dev_alloc(h, &h->d_ovf, ncell * sizeof(int32_t))) != hipSuccess)
+            (e = dev_alloc(h, &h->bin.cap, rv::kMaxBricksAll * sizeof(uint32_t))) != hipSuccess ||
+            (e = dev_alloc(h, &h->bin.est, rv::kMaxBricksAll * sizeof(uint32_t))) != hipSuccess ||
+            (e = dev_alloc(h, &h->bin.flags, rv::kMaxBricksAll * sizeof(uint32_t))) != hipSuccess ||
+            (e = dev_alloc(h, &h->bin.order, rv::kMaxBricksAll * sizeof(uint32_t))) != hipSuccess ||
+            (e = dev_alloc(h, &h->d_ovf, brick_cells * sizeof(int32_t))) != hipSuccess)
             return bail(e, "brick scratch");
-        if ((e = hipMemset(h->bin.est, 0, rv::kMaxBricks * sizeof(uint32_t))) != hipSuccess ||
-            (e = hipMemset(h->d_ovf, 0, ncell * sizeof(int32_t))) != hipSuccess ||
+        if ((e = hipMemset(h->bin.est, 0, rv::kMaxBricksAll * sizeof(uint32_t))) != hipSuccess ||
+            (e = hipMemset(h->d_ovf, 0, brick_cells * sizeof(int32_t))) != hipSuccess ||
             (e = hipDeviceSynchronize()) != hipSuccess)
             return bail(e, "brick scratch init");
         h->bin.ovf = h->d_ovf;
@@ -498,7 +502,7 @@ rv_status vote_candidates(rv_handle* h, const float* x, const float* y, int64_t 
                        ? RV_VOTE_BRICK : RV_VOTE_GLOBAL;
     if (strategy == RV_VOTE_BRICK && !(h->brick_ok && grid <= rv::kMaxBrickGrid))
         return fail(h, RV_EUNSUPPORTED,
-                    f + ": the brick strategy needs grid <= 256 and a handle created for it");
+                    f + ": the brick strategy needs grid <= 384 and a handle created for it");
 
     if (h->table_J != J) {
         RV_HIP(h, hipStreamSynchronize(s), "sync before table upload");

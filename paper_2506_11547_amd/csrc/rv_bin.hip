@@ -41,26 +41,43 @@ constexpr int kBinThreads = kBinWaves * kWave;
 static_assert(kBinThreads == kUnitSize, "a batch work unit is one vote block");
 constexpr int kStageCap = 2048;  // runs staged per wave between flushes
 constexpr int kStep = 16;        // samples per lane between flush checks
-constexpr int kSplit = 240;      // runs are cut every 240 samples: counts fit 8 bits
+// A staged run is its packed cell with the run length above it: 8-bit axes
+// and an 8-bit length (runs cut every 240 samples) for G <= 256, 9-bit axes
+// and a 5-bit length (cut every 24 samples) for G <= 384.  Cuts are multiples
+// of 8 samples: the sample loop reads the table eight entries at a time.
+template <bool kWide>
+struct Pack {
+    static constexpr int kBits = kWide ? 9 : 8;
+    static constexpr uint32_t kAxis = (1u << kBits) - 1u;
+    static constexpr int kLenShift = 3 * kBits;
+    static constexpr uint32_t kCellMask = (1u << kLenShift) - 1u;
+    static constexpr int kSplit = kWide ? 24 : 240;
+    static_assert(kSplit % 8 == 0 && kSplit < (1 << (32 - kLenShift)), "cut and length field");
+    static constexpr int kMaxBricksHere = kWide ? kMaxBricksAll : kMaxBricks;
+};
 // flush before a step could overflow a wave's staging: one step adds at most
 // kWave * kStep runs and a run-block boundary at most kWave more.
 constexpr int kFlushAt = kStageCap - kWave * kStep - kWave;
 // Marks a dropped zero-length staged run.  A staged run never equals it: its
-// length (bits 24..31) is at most 240, never 0xFF.
+// length field is at most 240 (of 8 bits) or 24 (of 5 bits).
 constexpr uint32_t kDropped = 0xFFFFFFFFu;
-template <int kLog>
+template <int kLog, bool kWide>
 __device__ __forceinline__ uint32_t brick_of(uint32_t pc, int nba)
 {
-    const uint32_t ix = pc & 255u, iy = (pc >> 8) & 255u, iz = (pc >> 16) & 255u;
+    using P = Pack<kWide>;
+    const uint32_t ix = pc & P::kAxis, iy = (pc >> P::kBits) & P::kAxis,
+                   iz = (pc >> (2 * P::kBits)) & P::kAxis;
     return __umul24(__umul24(iz >> kLog, (uint32_t)nba) + (iy >> kLog), (uint32_t)nba) +
            (ix >> kLog);
 }
 
-template <int kLog>
+template <int kLog, bool kWide>
 __device__ __forceinline__ uint32_t local_of(uint32_t pc)
 {
+    using P = Pack<kWide>;
     constexpr uint32_t m = Brick<kLog>::kMask;
-    const uint32_t ix = pc & 255u, iy = (pc >> 8) & 255u, iz = (pc >> 16) & 255u;
+    const uint32_t ix = pc & P::kAxis, iy = (pc >> P::kBits) & P::kAxis,
+                   iz = (pc >> (2 * P::kBits)) & P::kAxis;
     return ((iz & m) << (2 * kLog)) | ((iy & m) << kLog) | (ix & m);
 }
 
@@ -73,6 +90,7 @@ __device__ __forceinline__ uint32_t local_of(uint32_t pc)
 // index stays wave-uniform and the work spreads over the whole GPU.
 constexpr int kEstChunk = 256;
 
+template <bool kWide>
 __global__ __launch_bounds__(256) void k_bin_estimate(const float* __restrict__ x,
                                                       const float* __restrict__ y, int64_t n,
                                                       float H, float gm, int J,
@@ -80,7 +98,7 @@ __global__ __launch_bounds__(256) void k_bin_estimate(const float* __restrict__ 
                                                       int ngroups, int nwaves,
                                                       uint32_t* __restrict__ est)
 {
-    __shared__ uint32_t s_est[kMaxBricks];
+    __shared__ uint32_t s_est[Pack<kWide>::kMaxBricksHere];
     const int nb = nba * nba * nba;
     for (int b = threadIdx.x; b < nb; b += 256)
         s_est[b] = 0;
@@ -95,9 +113,9 @@ __global__ __launch_bounds__(256) void k_bin_estimate(const float* __restrict__ 
         uint32_t cur = 0xFFFFFFFFu;
         for_samples<true>(u, v, table, c * kEstChunk, min(J, (c + 1) * kEstChunk), H, gm,
                           [&](const Cell& cell, int) {
-                              const uint32_t pc = packed_coords(cell);
+                              const uint32_t pc = packed_coords<kWide>(cell);
                               if (ok && pc != cur)
-                                  atomicAdd(&s_est[brick_of<5>(pc, nba)], 1u);
+                                  atomicAdd(&s_est[brick_of<5, kWide>(pc, nba)], 1u);
                               cur = pc;
                           });
     }
@@ -113,74 +131,79 @@ __global__ __launch_bounds__(256) void k_bin_estimate(const float* __restrict__ 
 // queue sets, plus slack, in multiples of 64 runs (queues start 256-byte
 // aligned); scaled down if the pool cannot hold them all.  Resets the fill
 // counters, the overflow flags and the estimate for the next solve.
-__global__ __launch_bounds__(kMaxBricks) void k_bin_plan(BinArgs a, int nb)
+constexpr int kPlanThreads = kMaxBricksAll / 2;  // two bricks per thread
+
+__global__ __launch_bounds__(kPlanThreads) void k_bin_plan(BinArgs a, int nb)
 {
-    __shared__ uint64_t s_scan[kMaxBricks];
+    __shared__ uint64_t s_scan[kPlanThreads];
     __shared__ uint64_t s_total;
-    __shared__ uint64_t s_sort[kMaxBricks];
-    const int b = threadIdx.x;
-    uint64_t capq = 0;
-    if (b < nb) {
-        const uint64_t e = (uint64_t)a.est[b] * kEstimateStride;
-        capq = (e * 115 / 100) / kSets + 256;
-        capq = (capq + 63) & ~63ull;
+    __shared__ uint64_t s_sort[kMaxBricksAll];
+    const int t = threadIdx.x;
+    const int b0 = 2 * t, b1 = 2 * t + 1;
+    uint64_t cap[2] = {0, 0};
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int b = b0 + h;
+        if (b < nb) {
+            const uint64_t e = (uint64_t)a.est[b] * kEstimateStride;
+            cap[h] = ((e * 115 / 100) / kSets + 256 + 63) & ~63ull;
+        }
     }
-    s_scan[b] = capq;
-    __syncthreads();
-    // inclusive scan (Hillis-Steele)
-    for (int off = 1; off < kMaxBricks; off <<= 1) {
-        const uint64_t t = b >= off ? s_scan[b - off] : 0;
+    // exclusive offsets of the bricks within one queue set: a scan over pairs
+    auto scan = [&](uint64_t& excl0, uint64_t& excl1) {
+        s_scan[t] = cap[0] + cap[1];
         __syncthreads();
-        s_scan[b] += t;
+        for (int off = 1; off < kPlanThreads; off <<= 1) {  // inclusive (Hillis-Steele)
+            const uint64_t v = t >= off ? s_scan[t - off] : 0;
+            __syncthreads();
+            s_scan[t] += v;
+            __syncthreads();
+        }
+        if (t == kPlanThreads - 1)
+            s_total = s_scan[t];
         __syncthreads();
-    }
-    if (b == kMaxBricks - 1)
-        s_total = s_scan[b];
-    __syncthreads();
+        excl0 = s_scan[t] - cap[0] - cap[1];
+        excl1 = excl0 + cap[0];
+    };
+    uint64_t excl0, excl1;
+    scan(excl0, excl1);
     uint64_t total = s_total * kSets;
-    uint64_t excl = s_scan[b] - capq;
     if (total > a.pool_runs) {
         // proportional shrink, still in multiples of 64 runs
         const double f = (double)a.pool_runs / (double)total;
-        capq = (uint64_t)((double)capq * f) & ~63ull;
-        s_scan[b] = capq;
+        cap[0] = (uint64_t)((double)cap[0] * f) & ~63ull;
+        cap[1] = (uint64_t)((double)cap[1] * f) & ~63ull;
         __syncthreads();
-        for (int off = 1; off < kMaxBricks; off <<= 1) {
-            const uint64_t t = b >= off ? s_scan[b - off] : 0;
-            __syncthreads();
-            s_scan[b] += t;
-            __syncthreads();
-        }
-        if (b == kMaxBricks - 1)
-            s_total = s_scan[b];
-        __syncthreads();
-        excl = s_scan[b] - capq;
-        total = s_total * kSets;
+        scan(excl0, excl1);
     }
-    // accumulation order: heaviest bricks first (bitonic sort of cap << 16 | b)
-    s_sort[b] = b < nb ? ((capq << 16) | (uint64_t)b) : 0ull;
+    // accumulation order: heaviest bricks first (bitonic sort of cap << 16 | b,
+    // descending, two elements per thread)
+    s_sort[b0] = b0 < nb ? ((cap[0] << 16) | (uint64_t)b0) : 0ull;
+    s_sort[b1] = b1 < nb ? ((cap[1] << 16) | (uint64_t)b1) : 0ull;
     __syncthreads();
-    for (int k = 2; k <= kMaxBricks; k <<= 1) {
+    for (int k = 2; k <= kMaxBricksAll; k <<= 1) {
         for (int j = k >> 1; j > 0; j >>= 1) {
-            const int o = b ^ j;
-            if (o > b) {
-                const uint64_t p = s_sort[b], q = s_sort[o];
-                const bool desc = (b & k) == 0;
-                if (desc ? (p < q) : (p > q)) {
-                    s_sort[b] = q;
-                    s_sort[o] = p;
-                }
+            const int i = 2 * t - (t & (j - 1));  // the lower index of this thread's pair
+            const uint64_t p = s_sort[i], q = s_sort[i + j];
+            const bool desc = (i & k) == 0;
+            if (desc ? (p < q) : (p > q)) {
+                s_sort[i] = q;
+                s_sort[i + j] = p;
             }
             __syncthreads();
         }
     }
-    if (b < nb)
+    const uint64_t excl[2] = {excl0, excl1};
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int b = b0 + h;
+        if (b >= nb)
+            continue;
         a.order[b] = (uint32_t)(s_sort[b] & 0xFFFFu);
-    if (b < nb) {
-        a.cap[b] = (uint32_t)capq;
+        a.cap[b] = (uint32_t)cap[h];
         for (int xs = 0; xs < kSets; ++xs) {
-            a.qbase[xs * kMaxBricks + b] = (uint32_t)(xs * s_total + excl);
-            a.fill[xs * kMaxBricks + b] = 0u;
+            a.qbase[xs * a.qstride + b] = (uint32_t)(xs * s_total + excl[h]);
+            a.fill[xs * a.qstride + b] = 0u;
         }
         a.flags[b] = 0u;
         a.est[b] = 0u;
@@ -193,7 +216,7 @@ __global__ __launch_bounds__(kMaxBricks) void k_bin_plan(BinArgs a, int nb)
 // Flush: each run is rewritten as brick << 23 | length << 15 | local cell,
 // counted per brick, one reservation atomic per brick, then written to its
 // queue slot (or, past the queue's capacity, added to the overflow grid).
-template <int kLog>
+template <int kLog, bool kWide>
 __device__ __forceinline__ void bin_flush(uint32_t (*stage)[kStageCap], const uint32_t* s_fillw,
                                           uint32_t* s_cnt, uint2* s_dst, const uint32_t* s_cap,
                                           const uint32_t* s_qbase, int wave, int lane, int nb,
@@ -204,11 +227,11 @@ __device__ __forceinline__ void bin_flush(uint32_t (*stage)[kStageCap], const ui
     // 1: runs per brick (zero-length entries are marked dropped)
     for (uint32_t k = lane; k < my; k += kWave) {
         const uint32_t e = stage[wave][k];
-        if ((e >> 24) == 0u) {
+        if ((e >> Pack<kWide>::kLenShift) == 0u) {
             stage[wave][k] = kDropped;
             continue;
         }
-        atomicAdd(&s_cnt[brick_of<kLog>(e & 0xFFFFFFu, nba)], 1u);
+        atomicAdd(&s_cnt[brick_of<kLog, kWide>(e & Pack<kWide>::kCellMask, nba)], 1u);
     }
     __syncthreads();
     // 2: one reservation per brick in its queue; the first pool slot of this
@@ -228,16 +251,18 @@ __device__ __forceinline__ void bin_flush(uint32_t (*stage)[kStageCap], const ui
         const uint32_t e = stage[wave][k];
         if (e == kDropped)
             continue;
-        const uint32_t pc = e & 0xFFFFFFu;
-        const uint32_t b = brick_of<kLog>(pc, nba);
+        const uint32_t pc = e & Pack<kWide>::kCellMask;
+        const uint32_t len = e >> Pack<kWide>::kLenShift;
+        const uint32_t b = brick_of<kLog, kWide>(pc, nba);
         const uint32_t rank = atomicAdd(&s_cnt[b], 1u);
         const uint2 d = s_dst[b];
         if (rank < d.y) {
-            a.pool[(uint64_t)(d.x + rank)] = local_of<kLog>(pc) | ((e >> 24) << 15);
+            a.pool[(uint64_t)(d.x + rank)] = local_of<kLog, kWide>(pc) | (len << 15);
         } else {
-            const int64_t cell = ((int64_t)((pc >> 16) & 255u) * G + ((pc >> 8) & 255u)) * G +
-                                 (pc & 255u);
-            atomicAdd(a.ovf + ovf_off + cell, (int32_t)(e >> 24));
+            using P = Pack<kWide>;
+            const int64_t cell = ((int64_t)((pc >> (2 * P::kBits)) & P::kAxis) * G +
+                                  ((pc >> P::kBits) & P::kAxis)) * G + (pc & P::kAxis);
+            atomicAdd(a.ovf + ovf_off + cell, (int32_t)len);
             a.flags[qoff + b] = 1u;
         }
     }
@@ -249,19 +274,21 @@ __device__ __forceinline__ void bin_flush(uint32_t (*stage)[kStageCap], const ui
 
 // One block per (512 correspondences, chunk of samples); chunks are whole run
 // blocks, so splitting J across blocks only adds run boundaries.
-template <int kLog>
-__global__ __launch_bounds__(kBinThreads, 2) void k_vote_bin(const float* __restrict__ x,
+template <int kLog, bool kWide>
+__global__ __launch_bounds__(kBinThreads, kWide ? 1 : 2) void k_vote_bin(const float* __restrict__ x,
                                                               const float* __restrict__ y,
                                                               int64_t n, int G, float H, float gm,
                                                               int J, int chunk, int ngroups,
                                                               const float2* __restrict__ table,
                                                               int nba, BinArgs a)
 {
+    using P = Pack<kWide>;
+    constexpr int kSplit = P::kSplit;
     __shared__ uint32_t stage[kBinWaves][kStageCap];
-    __shared__ uint32_t s_cnt[kMaxBricks];
-    __shared__ uint2 s_dst[kMaxBricks];
-    __shared__ uint32_t s_cap[kMaxBricks];
-    __shared__ uint32_t s_qbase[kMaxBricks];
+    __shared__ uint32_t s_cnt[P::kMaxBricksHere];
+    __shared__ uint2 s_dst[P::kMaxBricksHere];
+    __shared__ uint32_t s_cap[P::kMaxBricksHere];
+    __shared__ uint32_t s_qbase[P::kMaxBricksHere];
     // double-buffered by check parity: a wave that runs ahead writes the other
     // half, so every wave reads the same counts and takes the same decision
     __shared__ uint32_t s_fill[2][kBinWaves];
@@ -317,7 +344,7 @@ __global__ __launch_bounds__(kBinThreads, 2) void k_vote_bin(const float* __rest
         const uint32_t r = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
                                                      __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
         const bool mine = change && ok;
-        *(mine ? (my_stage + fill + r) : my_dummy) = cur | (cnt << 24);
+        *(mine ? (my_stage + fill + r) : my_dummy) = cur | (cnt << P::kLenShift);
         fill += (uint32_t)__popcll(m);
     };
 
@@ -325,7 +352,7 @@ __global__ __launch_bounds__(kBinThreads, 2) void k_vote_bin(const float* __rest
         const int je = min(j1, jb + kSplit);
         for (int js = jb; js < je; js += kStep) {
             for_samples<true>(u, v, table, js, min(je, js + kStep), H, gm, [&](const Cell& c, int) {
-                const uint32_t pc = packed_coords(c);
+                const uint32_t pc = packed_coords<kWide>(c);
                 const bool change = pc != cur;
                 emit(change);
                 cnt = change ? 1u : cnt + 1u;
@@ -339,7 +366,7 @@ __global__ __launch_bounds__(kBinThreads, 2) void k_vote_bin(const float* __rest
             for (int w = 0; w < kBinWaves; ++w)
                 need |= s_fill[parity][w] > (uint32_t)kFlushAt;
             if (need) {
-                bin_flush<kLog>(stage, s_fill[parity], s_cnt, s_dst, s_cap, s_qbase, wave, lane, nb, nba,
+                bin_flush<kLog, kWide>(stage, s_fill[parity], s_cnt, s_dst, s_cap, s_qbase, wave, lane, nb, nba,
                           G, xs, qoff, ovf_off, a);
                 fill = 0;
             }
@@ -356,7 +383,7 @@ __global__ __launch_bounds__(kBinThreads, 2) void k_vote_bin(const float* __rest
     for (int w = 0; w < kBinWaves; ++w)
         any |= s_fill[parity][w] > 0;
     if (any)
-        bin_flush<kLog>(stage, s_fill[parity], s_cnt, s_dst, s_cap, s_qbase, wave, lane, nb, nba, G, xs,
+        bin_flush<kLog, kWide>(stage, s_fill[parity], s_cnt, s_dst, s_cap, s_qbase, wave, lane, nb, nba, G, xs,
                   qoff, ovf_off, a);
 }
 
@@ -521,8 +548,9 @@ hipError_t launch_bin_prepare(const float* x, const float* y, int64_t n, int G, 
 {
     const int nba = brick_axis(G, 5);
     const int nb = nba * nba * nba;
-    if (G > kMaxBrickGrid || nb > kMaxBricks)
+    if (G > kMaxBrickGrid || nb > kMaxBricksAll)
         return hipErrorInvalidValue;
+    const bool wide = G > kNarrowGrid;
     const float H = (float)G * 0.5f;
     const float gm = (float)G - 0.5f;
     if (n > 0) {
@@ -532,12 +560,16 @@ hipError_t launch_bin_prepare(const float* x, const float* y, int64_t n, int G, 
         const int64_t nwaves = ngroups * nchunks;
         if (nwaves > (int64_t)INT32_MAX - 4)
             return hipErrorInvalidValue;
-        hipLaunchKernelGGL(k_bin_estimate, dim3((unsigned)((nwaves + 3) / 4)), dim3(256), 0, s, x,
-                           y, n, H, gm, J, table, nba, (int)ngroups, (int)nwaves, a.est);
+        if (wide)
+            hipLaunchKernelGGL(k_bin_estimate<true>, dim3((unsigned)((nwaves + 3) / 4)), dim3(256),
+                               0, s, x, y, n, H, gm, J, table, nba, (int)ngroups, (int)nwaves, a.est);
+        else
+            hipLaunchKernelGGL(k_bin_estimate<false>, dim3((unsigned)((nwaves + 3) / 4)), dim3(256),
+                               0, s, x, y, n, H, gm, J, table, nba, (int)ngroups, (int)nwaves, a.est);
         if (hipError_t e = hipGetLastError(); e != hipSuccess)
             return e;
     }
-    hipLaunchKernelGGL(k_bin_plan, dim3(1), dim3(kMaxBricks), 0, s, a, nb);
+    hipLaunchKernelGGL(k_bin_plan, dim3(1), dim3(kPlanThreads), 0, s, a, nb);
     return hipGetLastError();
 }
 
@@ -546,20 +578,27 @@ hipError_t launch_bin_vote(const float* x, const float* y, int64_t n, int G, int
 {
     if (n <= 0)
         return hipSuccess;
+    const bool wide = G > kNarrowGrid;
     const int64_t ngroups = (n + kBinThreads - 1) / kBinThreads;
     // at least ~4 rounds of blocks over the GPU (2 resident per CU), by
     // splitting J into whole run blocks when there are few correspondences
+    const int split_len = wide ? Pack<true>::kSplit : Pack<false>::kSplit;
     const int64_t want = 4 * 2 * 256;
-    const int64_t nblk = (J + kSplit - 1) / kSplit;
+    const int64_t nblk = (J + split_len - 1) / split_len;
     const int64_t split = std::max<int64_t>(1, std::min<int64_t>(nblk, want / ngroups));
-    const int chunk = (int)(((nblk + split - 1) / split) * kSplit);
+    const int chunk = (int)(((nblk + split - 1) / split) * split_len);
     const int64_t nchunks = (J + chunk - 1) / chunk;
     const int64_t blocks = ngroups * nchunks;
     if (blocks > INT32_MAX || G > kMaxBrickGrid)
         return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_vote_bin<5>, dim3((unsigned)blocks), dim3(kBinThreads), 0, s, x, y, n, G,
-                       (float)G * 0.5f, (float)G - 0.5f, J, chunk, (int)ngroups, table,
-                       brick_axis(G, 5), a);
+    if (wide)
+        hipLaunchKernelGGL((k_vote_bin<5, true>), dim3((unsigned)blocks), dim3(kBinThreads), 0, s, x,
+                           y, n, G, (float)G * 0.5f, (float)G - 0.5f, J, chunk, (int)ngroups, table,
+                           brick_axis(G, 5), a);
+    else
+        hipLaunchKernelGGL((k_vote_bin<5, false>), dim3((unsigned)blocks), dim3(kBinThreads), 0, s, x,
+                           y, n, G, (float)G * 0.5f, (float)G - 0.5f, J, chunk, (int)ngroups, table,
+                           brick_axis(G, 5), a);
     return hipGetLastError();
 }
 
@@ -570,7 +609,7 @@ hipError_t launch_brick_accum(int G, int K, int edge_log2, int32_t* grid, uint64
         return hipErrorInvalidValue;
     const int nba = brick_axis(G, edge_log2);
     const int nb = nba * nba * nba;
-    if (G > kMaxBrickGrid || nb > kMaxBricks)
+    if (G > kMaxBrickGrid || nb > kMaxBricksAll)
         return hipErrorInvalidValue;
     const int blocks = a.batch ? a.batch * nb : nb;
     if (K < 1 || K > kWave)
@@ -596,11 +635,11 @@ hipError_t launch_bin_vote_batch(const float* x, const float* y, int64_t n, int 
     if (nba * nba * nba > kMaxBricks)
         return hipErrorInvalidValue;
     if (edge_log2 == 5)
-        hipLaunchKernelGGL(k_vote_bin<5>, dim3((unsigned)nunits), dim3(kBinThreads), 0, s, x, y, n,
-                           G, (float)G * 0.5f, (float)G - 0.5f, J, J, 1, table, nba, a);
+        hipLaunchKernelGGL((k_vote_bin<5, false>), dim3((unsigned)nunits), dim3(kBinThreads), 0, s, x,
+                           y, n, G, (float)G * 0.5f, (float)G - 0.5f, J, J, 1, table, nba, a);
     else
-        hipLaunchKernelGGL(k_vote_bin<4>, dim3((unsigned)nunits), dim3(kBinThreads), 0, s, x, y, n,
-                           G, (float)G * 0.5f, (float)G - 0.5f, J, J, 1, table, nba, a);
+        hipLaunchKernelGGL((k_vote_bin<4, false>), dim3((unsigned)nunits), dim3(kBinThreads), 0, s, x,
+                           y, n, G, (float)G * 0.5f, (float)G - 0.5f, J, J, 1, table, nba, a);
     return hipGetLastError();
 }
 

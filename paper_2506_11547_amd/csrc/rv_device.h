@@ -140,11 +140,13 @@ __device__ __forceinline__ unsigned linear_index(const Cell& c, unsigned G)
     return __umul24(__umul24(c.z, G) + c.y, G) + c.x;
 }
 
-// Cell coordinates packed one byte each (G <= 256): a key that is unique per
-// cell and cheap to build and to take apart.
+// Cell coordinates packed 8 bits each (G <= 256) or 9 bits each (G <= 512):
+// a key that is unique per cell and cheap to build and to take apart.
+template <bool kWide = false>
 __device__ __forceinline__ unsigned packed_coords(const Cell& c)
 {
-    return c.x | (c.y << 8) | (c.z << 16);
+    constexpr int kBits = kWide ? 9 : 8;
+    return c.x | (c.y << kBits) | (c.z << (2 * kBits));
 }
 
 template <bool kFastRecip>

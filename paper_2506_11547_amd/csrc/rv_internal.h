@@ -24,7 +24,7 @@ struct Candidates {
 };
 
 constexpr int kMaxTopK = 64;
-constexpr int kTopkMaxBlocks = 512;   // also the largest brick count
+constexpr int kTopkMaxBlocks = 2048;  // also the largest brick count
 
 hipError_t launch_fill(int32_t* p, int64_t count, int32_t value, hipStream_t s);
 
@@ -42,8 +42,10 @@ hipError_t launch_topk_final(const uint64_t* partial, int nblocks, int K, int G,
 
 // Brick-binned vote (G <= 256): estimate, plan, binned vote, brick accumulation.
 constexpr int kQueueSets = 8;        // one queue per brick per XCD
-constexpr int kMaxBricks = 512;      // (256 / 32)^3
-constexpr int kMaxBrickGrid = 256;   // cell coordinates packed in one byte each
+constexpr int kMaxBricks = 512;      // (256 / 32)^3: bricks of a solve with 8-bit packed cells
+constexpr int kNarrowGrid = 256;     // up to here cells pack 8 bits per axis, beyond 9
+constexpr int kMaxBrickGrid = 384;   // (384 / 32)^3 = 1728 bricks
+constexpr int kMaxBricksAll = 2048;  // brick tables of one solve (queue metadata, plan)
 constexpr int kEstimateStride = 64;  // the estimate samples every 64th correspondence
 
 // A batch work unit: up to 512 consecutive correspondences of one instance.
@@ -54,16 +56,16 @@ struct Unit {
 };
 
 // Queues are indexed [set][instance * nb + brick]: one solve uses kQueueSets
-// sets (one per XCD) and qstride = kMaxBricks; a batch uses one set and
+// sets (one per XCD) and qstride = kMaxBricksAll; a batch uses one set and
 // qstride = B * nb.
 struct BinArgs {
     uint32_t* pool;      // run queues; entry = local cell | run length << 15
     uint32_t* fill;      // [nsets][qstride] runs appended per queue
     uint32_t* qbase;     // [nsets][qstride] first pool slot of each queue
     uint32_t* cap;       // [qstride] capacity of each queue of the brick
-    uint32_t* est;       // [kMaxBricks] estimated runs (sampled), zero between solves
+    uint32_t* est;       // [kMaxBricksAll] estimated runs (sampled), zero between solves
     uint32_t* flags;     // [qstride] set when a brick's queue overflowed
-    uint32_t* order;     // [kMaxBricks] one solve: bricks by decreasing capacity
+    uint32_t* order;     // [kMaxBricksAll] one solve: bricks by decreasing capacity
     int32_t* ovf;        // [instances][G^3] overflow grids, zero between solves
     uint64_t pool_runs;  // pool capacity in runs (< 2^32)
     const Unit* units;   // batch: work units of the binned vote (null for one solve)

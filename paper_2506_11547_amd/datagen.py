@@ -226,10 +226,14 @@ def quat_to_matrix(q) -> np.ndarray:
 
 
 def rotation_error_deg(q_a, q_b) -> float:
-    """Geodesic angle between two rotations, in degrees (Sec. 5.2's e_R)."""
+    """Geodesic angle between two rotations, in degrees (Sec. 5.2's e_R).
+    From the relative rotation's axis-angle form, 2 atan2(|sin|, |cos|), which
+    stays accurate for small angles (an arccos of the trace does not)."""
     ra, rb = quat_to_matrix(q_a), quat_to_matrix(q_b)
-    c = (np.trace(ra.T @ rb) - 1.0) * 0.5
-    return math.degrees(math.acos(min(1.0, max(-1.0, c))))
+    d = ra.T @ rb
+    c = (np.trace(d) - 1.0) * 0.5
+    s = 0.5 * math.sqrt((d[2, 1] - d[1, 2]) ** 2 + (d[0, 2] - d[2, 0]) ** 2 + (d[1, 0] - d[0, 1]) ** 2)
+    return math.degrees(math.atan2(s, c))
 
 
 def _unit_rows(v: np.ndarray) -> np.ndarray:

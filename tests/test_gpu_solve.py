@@ -88,7 +88,9 @@ STRATEGIES = ["global", "brick"]
                                      (31, 250, 4097, 16), (33, 241, 1500, 8),
                                      (64, 512, 3000, 16), (100, 801, 2000, 33),
                                      (128, 1024, 5000, 64), (250, 300, 3001, 64),
-                                     (256, 2048, 1000, 64)])
+                                     (256, 2048, 1000, 64), (257, 240, 2000, 16),
+                                     (300, 180, 3000, 16), (360, 180, 5000, 16),
+                                     (384, 512, 2500, 64)])
 def test_random_shapes(rv, orc, G, J, n, K, strategy):
     inst = datagen.make_instance(n, 0.7, 1.0, 1000 + G, radii=(0.3, 3.0))
     eps = 2.0
@@ -120,14 +122,27 @@ def test_large_workload_full_parity(rv, orc):
     assert datagen.rotation_error_deg(g["q"], inst.q_gt) < 1.5
 
 
+def test_paper_default_workload_full_parity(rv, orc):
+    """The paper's default resolution (G = 360, J = 180; N = 1e6, 99 % outliers)
+    on the brick path with 9-bit packed cells, against the oracle in full."""
+    w, inst = datagen.make_workload("paper_default")
+    g = run_gpu(rv, inst.x, inst.y, w.grid, w.samples, w.eps_deg, w.topk)
+    assert g["plan"]["strategy"] == "brick"
+    o = orc.solve(inst.x, inst.y, w.grid, w.samples, eps_rad(rv, w.eps_deg), w.topk,
+                  nthreads=oracle.threads())
+    check_parity(g, o, w.grid)
+
+
 def test_auto_strategy_choice(rv):
     inst = datagen.make_instance(2000, 0.5, 1.0, 11)
-    for G, want in ((8, "global"), (64, "global"), (72, "brick"), (128, "brick"), (256, "brick")):
+    for G, want in ((8, "global"), (64, "global"), (72, "brick"), (128, "brick"), (256, "brick"),
+                    (360, "brick"), (400, "global")):
         g = run_gpu(rv, inst.x, inst.y, G, 8 * G, 1.0, 8)
         assert g["plan"]["strategy"] == want, G
 
 
-def test_brick_queue_overflow_is_exact(rv, orc):
+@pytest.mark.parametrize("G,J", [(128, 1024), (300, 600)])
+def test_brick_queue_overflow_is_exact(rv, orc, G, J):
     """Queue capacities come from every 32nd correspondence; here all the
     others are one repeated correspondence, so its bricks overflow and their
     excess runs take the atomic overflow path.  The histogram must not change."""
@@ -138,7 +153,6 @@ def test_brick_queue_overflow_is_exact(rv, orc):
     rep = np.arange(n) % 32 != 0
     x[:, rep] = np.float32([[0.3], [-0.5], [0.8]])
     y[:, rep] = np.float32([[0.9], [0.1], [-0.2]])
-    G, J = 128, 1024
     o = orc.solve(x, y, G, J, eps_rad(rv, 1.0), 16, nthreads=oracle.threads())
     with rv.Solver(max_n=n, max_grid=G, topk=16, samples_per_circle=J, strategy="brick") as s:
         for _ in range(2):  # the overflow grid must be left zeroed for the next solve
