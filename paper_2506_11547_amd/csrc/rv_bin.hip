@@ -39,8 +39,12 @@ constexpr int kSets = kQueueSets;
 constexpr int kBinWaves = 8;
 constexpr int kBinThreads = kBinWaves * kWave;
 static_assert(kBinThreads == kUnitSize, "a batch work unit is one vote block");
-constexpr int kStageCap = 2048;  // runs staged per wave between flushes
-constexpr int kStep = 16;        // samples per lane between flush checks
+// 1280 runs staged per wave between flushes and a flush check every 8 samples
+// keep a workgroup's LDS at 48 KiB, so three vote workgroups share a CU (two
+// with the wide layout's larger brick tables): measured 7-10 % faster than
+// two workgroups with twice the staging.
+constexpr int kStageCap = 1280;
+constexpr int kStep = 8;
 // A staged run is its packed cell with the run length above it: 8-bit axes
 // and an 8-bit length (runs cut every 240 samples) for G <= 256, 9-bit axes
 // and a 5-bit length (cut every 24 samples) for G <= 384.  Cuts are multiples
@@ -218,8 +222,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_bin_plan(BinArgs a, int nb)
 // queue slot (or, past the queue's capacity, added to the overflow grid).
 template <int kLog, bool kWide>
 __device__ __forceinline__ void bin_flush(uint32_t (*stage)[kStageCap], const uint32_t* s_fillw,
-                                          uint32_t* s_cnt, uint2* s_dst, const uint32_t* s_cap,
-                                          const uint32_t* s_qbase, int wave, int lane, int nb,
+                                          uint32_t* s_cnt, uint2* s_dst, int wave, int lane, int nb,
                                           int nba, int G, int xs, int qoff, int64_t ovf_off,
                                           const BinArgs& a)
 {
@@ -239,9 +242,10 @@ __device__ __forceinline__ void bin_flush(uint32_t (*stage)[kStageCap], const ui
     for (int b = threadIdx.x; b < nb; b += kBinThreads) {
         const uint32_t c = s_cnt[b];
         if (c) {
-            const uint32_t g = atomicAdd(a.fill + (int64_t)xs * a.qstride + qoff + b, c);
-            const uint32_t cap = s_cap[b];
-            s_dst[b] = make_uint2(s_qbase[b] + g, cap > g ? cap - g : 0u);
+            const int64_t q = (int64_t)xs * a.qstride + qoff + b;
+            const uint32_t g = atomicAdd(a.fill + q, c);
+            const uint32_t cap = a.cap[qoff + b];
+            s_dst[b] = make_uint2(a.qbase[q] + g, cap > g ? cap - g : 0u);
         }
         s_cnt[b] = 0;
     }
@@ -275,7 +279,7 @@ __device__ __forceinline__ void bin_flush(uint32_t (*stage)[kStageCap], const ui
 // One block per (512 correspondences, chunk of samples); chunks are whole run
 // blocks, so splitting J across blocks only adds run boundaries.
 template <int kLog, bool kWide>
-__global__ __launch_bounds__(kBinThreads, kWide ? 1 : 2) void k_vote_bin(const float* __restrict__ x,
+__global__ __launch_bounds__(kBinThreads, kWide ? 2 : 3) void k_vote_bin(const float* __restrict__ x,
                                                               const float* __restrict__ y,
                                                               int64_t n, int G, float H, float gm,
                                                               int J, int chunk, int ngroups,
@@ -287,8 +291,6 @@ __global__ __launch_bounds__(kBinThreads, kWide ? 1 : 2) void k_vote_bin(const f
     __shared__ uint32_t stage[kBinWaves][kStageCap];
     __shared__ uint32_t s_cnt[P::kMaxBricksHere];
     __shared__ uint2 s_dst[P::kMaxBricksHere];
-    __shared__ uint32_t s_cap[P::kMaxBricksHere];
-    __shared__ uint32_t s_qbase[P::kMaxBricksHere];
     // double-buffered by check parity: a wave that runs ahead writes the other
     // half, so every wave reads the same counts and takes the same decision
     __shared__ uint32_t s_fill[2][kBinWaves];
@@ -318,8 +320,6 @@ __global__ __launch_bounds__(kBinThreads, kWide ? 1 : 2) void k_vote_bin(const f
     const int64_t ovf_off = (int64_t)inst * G * G * G;
     for (int b = threadIdx.x; b < nb; b += kBinThreads) {
         s_cnt[b] = 0;
-        s_cap[b] = a.cap[qoff + b];
-        s_qbase[b] = a.qbase[(int64_t)xs * a.qstride + qoff + b];
     }
     Quat u, v;
     const bool ok = load_circle(x, y, n, i0 + threadIdx.x, u, v) && (i0 + threadIdx.x < iend);
@@ -366,7 +366,7 @@ __global__ __launch_bounds__(kBinThreads, kWide ? 1 : 2) void k_vote_bin(const f
             for (int w = 0; w < kBinWaves; ++w)
                 need |= s_fill[parity][w] > (uint32_t)kFlushAt;
             if (need) {
-                bin_flush<kLog, kWide>(stage, s_fill[parity], s_cnt, s_dst, s_cap, s_qbase, wave, lane, nb, nba,
+                bin_flush<kLog, kWide>(stage, s_fill[parity], s_cnt, s_dst, wave, lane, nb, nba,
                           G, xs, qoff, ovf_off, a);
                 fill = 0;
             }
@@ -383,7 +383,7 @@ __global__ __launch_bounds__(kBinThreads, kWide ? 1 : 2) void k_vote_bin(const f
     for (int w = 0; w < kBinWaves; ++w)
         any |= s_fill[parity][w] > 0;
     if (any)
-        bin_flush<kLog, kWide>(stage, s_fill[parity], s_cnt, s_dst, s_cap, s_qbase, wave, lane, nb, nba, G, xs,
+        bin_flush<kLog, kWide>(stage, s_fill[parity], s_cnt, s_dst, wave, lane, nb, nba, G, xs,
                   qoff, ovf_off, a);
 }
 
@@ -580,10 +580,10 @@ hipError_t launch_bin_vote(const float* x, const float* y, int64_t n, int G, int
         return hipSuccess;
     const bool wide = G > kNarrowGrid;
     const int64_t ngroups = (n + kBinThreads - 1) / kBinThreads;
-    // at least ~4 rounds of blocks over the GPU (2 resident per CU), by
-    // splitting J into whole run blocks when there are few correspondences
+    // at least ~4 rounds of workgroups over the GPU (3 resident per CU, 2 wide),
+    // by splitting J into whole run blocks when there are few correspondences
     const int split_len = wide ? Pack<true>::kSplit : Pack<false>::kSplit;
-    const int64_t want = 4 * 2 * 256;
+    const int64_t want = 4 * (wide ? 2 : 3) * 256;
     const int64_t nblk = (J + split_len - 1) / split_len;
     const int64_t split = std::max<int64_t>(1, std::min<int64_t>(nblk, want / ngroups));
     const int chunk = (int)(((nblk + split - 1) / split) * split_len);
