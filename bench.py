@@ -16,6 +16,8 @@ below 1e5 / above; J = 8G; outliers U[0.8, 0.99]; sigma 1 deg) and reports
 throughput and latency percentiles; the requests are drawn from a resident
 pool of seeded instances.
 
+``--workload multi`` times a several-rotations solve (9 rotations in one scene).
+
 ``--workload batch`` times the batched solve instead: a step is one
 rot_vote_solve_batch over 4096 instances (N log-uniform on [100, 20000], G =
 64, J = 512), reported with the same fields plus the one-solve-per-call loop
@@ -88,7 +90,8 @@ def copy_calibration(mib: int):
 
 
 TRAFFIC_RECORDS = {"large": ROOT / "profiles" / "vote_bin__large_traffic.json",
-                   "batch": ROOT / "profiles" / "vote_bin__batch_traffic.json"}
+                   "batch": ROOT / "profiles" / "vote_bin__batch_traffic.json",
+                   "paper_default": ROOT / "profiles" / "vote_bin__paper_default_traffic.json"}
 
 
 def measured_traffic(workload: str):
@@ -286,6 +289,47 @@ def run_serve(args):
     print(json.dumps(out), flush=True)
 
 
+def run_multi(args):
+    """Several rotations in one scene (the paper's multiple-rotation setting:
+    9 rotations x 3000 correspondences, delta 0.01, J = 540) plus 27 000
+    uniform outliers; G = 128, K = 64, eps 2 deg, at most 12 models."""
+    import numpy as np
+    import torch
+
+    from paper_2506_11547_amd import datagen, rotvote
+    models, per_model, G, J, K, eps_deg = 9, 3000, 128, 540, 64, 2.0
+    inst = datagen.make_multi_instance(models, per_model, models * per_model, 0.01, 6)
+    dev = torch.device("cuda", 0)
+    x = torch.from_numpy(inst.x).to(dev)
+    y = torch.from_numpy(inst.y).to(dev)
+    n = x.shape[1]
+    labels = torch.empty(n, dtype=torch.uint8, device=dev)
+    solver = rotvote.Solver(device=0, max_n=n, max_grid=G, topk=K, samples_per_circle=J)
+    for _ in range(args.warmup):
+        solver.solve_multi(x, y, G, eps_deg, models + 3, 10.0, 50, labels=labels)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        q, cnt, _ = solver.solve_multi(x, y, G, eps_deg, models + 3, 10.0, 50, labels=labels)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    solver.close()
+    errs = [min(datagen.rotation_error_deg(np.array(qm), qg) for qm in q) for qg in inst.q_gt]
+    lab = labels.cpu().numpy()
+    out = {"metric": METRIC, "value": n * J / dt, "unit": "votes/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": "multi", "models": models, "per_model": per_model,
+                      "outliers": models * per_model, "delta": 0.01, "grid": G,
+                      "samples_per_circle": J, "topk": K, "eps_deg": eps_deg, "sep_deg": 10.0,
+                      "min_inliers": 50, "seed": 6},
+           "result": {"models_found": len(q), "counts": cnt, "max_err_deg": max(errs),
+                      "mean_err_deg": float(np.mean(errs)),
+                      "labelled_fraction": float((lab > 0).mean())}}
+    print(json.dumps(out), flush=True)
+
+
 def run_batch(args):
     import numpy as np
     import torch
@@ -397,6 +441,9 @@ def main():
         return
     if args.workload == "serve":
         run_serve(args)
+        return
+    if args.workload == "multi":
+        run_multi(args)
         return
     import numpy as np
     import torch
