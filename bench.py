@@ -94,16 +94,23 @@ TRAFFIC_RECORDS = {"large": ROOT / "profiles" / "vote_bin__large_traffic.json",
                    "paper_default": ROOT / "profiles" / "vote_bin__paper_default_traffic.json"}
 
 
-def measured_traffic(workload: str):
+def vote_kernel_name(grid: int, edge: int = 32) -> str:
+    """The vote kernel instance a brick solve launches: brick edge 2^5 or 2^4,
+    wide run layout above grid 256."""
+    return f"rv::k_vote_bin<{5 if edge == 32 else 4}, {'true' if grid > 256 else 'false'}>"
+
+
+def measured_traffic(workload: str, kernel: str):
     """HBM bytes per launch of the vote kernel from the committed FETCH_SIZE /
     WRITE_SIZE profile (scaled by the copy calibration), or None when the
-    profile is of another workload or the kernel's sources changed since."""
+    profile is of another workload or kernel instance, or the kernel's sources
+    changed since."""
     import hashlib
     try:
         rec = json.loads(TRAFFIC_RECORDS[workload].read_text())
     except (KeyError, OSError, ValueError):
         return None
-    if rec.get("workload") != workload:
+    if rec.get("workload") != workload or rec.get("kernel") != kernel:
         return None
     for path, digest in rec["sources_sha256"].items():
         try:
@@ -397,7 +404,7 @@ def run_batch(args):
                                                   loop["solves_per_s"]),
         "roofline": {"bound": "alu", "kernel": "vote (batched)", "achieved": achieved / 1e3,
                      "peak": ALU_PEAK_GOPS / 1e3, "unit": "TOP/s", "frac": achieved / ALU_PEAK_GOPS,
-                     "traffic": measured_traffic(w.name), "ops_per_sample": OPS_PER_SAMPLE,
+                     "traffic": measured_traffic(w.name, vote_kernel_name(w.grid, edge)), "ops_per_sample": OPS_PER_SAMPLE,
                      "samples_per_launch": samples, "vote_ms": stage_ms["vote"]},
         "result": {"median_e_R_deg": float(np.median(err)), "p99_e_R_deg": float(np.percentile(err, 99)),
                    "inliers_total": int(sum(cnt))},
@@ -507,7 +514,8 @@ def main():
         "strategy_tuning": tuned,
         "roofline": {"bound": "alu", "kernel": "vote", "achieved": achieved / 1e3,
                      "peak": ALU_PEAK_GOPS / 1e3, "unit": "TOP/s", "frac": achieved / ALU_PEAK_GOPS,
-                     "traffic": measured_traffic(w.name) if plan["strategy"] == "brick" else None,
+                     "traffic": (measured_traffic(w.name, vote_kernel_name(w.grid))
+                                 if plan["strategy"] == "brick" else None),
                      "ops_per_sample": OPS_PER_SAMPLE, "samples_per_launch": samples,
                      "vote_ms": stage_ms["vote"]},
         "result": {"q": q, "inliers": cnt, "e_R_deg": datagen.rotation_error_deg(q, inst.q_gt),
