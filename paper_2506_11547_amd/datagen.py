@@ -37,6 +37,8 @@ __all__ = [
     "make_batch",
     "MultiInstance",
     "make_multi_instance",
+    "RigidInstance",
+    "make_rigid_instance",
     "quat_to_matrix",
     "rotation_error_deg",
 ]
@@ -213,6 +215,46 @@ def make_multi_instance(models: int, per_model: int, outliers: int, delta: float
     perm = rng.permutation(len(lab))
     return MultiInstance(np.ascontiguousarray(x[perm].T.astype(np.float32)),
                          np.ascontiguousarray(y[perm].T.astype(np.float32)), qs, lab[perm], seed)
+
+
+@dataclass
+class RigidInstance:
+    x: np.ndarray          # float32 [3, N] points (not directions)
+    y: np.ndarray          # float32 [3, N]
+    q_gt: np.ndarray       # float64 [4], w >= 0
+    t_gt: np.ndarray       # float64 [3]
+    inlier: np.ndarray     # bool [N]
+    seed: int
+
+    @property
+    def n(self) -> int:
+        return int(self.x.shape[1])
+
+
+def make_rigid_instance(n: int, outlier_ratio: float, delta: float, seed: int,
+                        box: float = 1.0) -> RigidInstance:
+    """Point correspondences under one rigid motion with outliers (the paper's
+    6-DoF synthetic experiment, Sec. 5.4.1): R uniform, t uniform in
+    [-1, 1]^3; x uniform in [-box, box]^3; inliers y = R x + t + delta N(0, I);
+    outliers x and y independent and uniform in [-box, box]^3.
+    Draw order (fixed): q, t, all x, a permutation whose first
+    round((1 - outlier_ratio) n) entries are inliers, inlier noise, outlier y."""
+    if n < 0:
+        raise ValueError("n must be >= 0")
+    rng = np.random.default_rng(seed)
+    q = _random_unit_quat(rng)
+    t = rng.uniform(-1.0, 1.0, size=3)
+    x = rng.uniform(-box, box, size=(n, 3))
+    perm = rng.permutation(n)
+    n_in = int(round((1.0 - outlier_ratio) * n))
+    inl = np.zeros(n, bool)
+    inl[perm[:n_in]] = True
+    y = np.empty_like(x)
+    R = quat_to_matrix(q)
+    y[inl] = x[inl] @ R.T + t + delta * rng.normal(size=(n_in, 3))
+    y[~inl] = rng.uniform(-box, box, size=(n - n_in, 3))
+    return RigidInstance(np.ascontiguousarray(x.T.astype(np.float32)),
+                         np.ascontiguousarray(y.T.astype(np.float32)), q, t, inl, seed)
 
 
 def quat_to_matrix(q) -> np.ndarray:
