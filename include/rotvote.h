@@ -69,7 +69,8 @@ enum {
     RV_MAX_GRID = 1024,
     RV_NUM_STAGES = 6,
     RV_MAX_BATCH_GRID = 64,
-    RV_MAX_REFINE_ROUNDS = 64
+    RV_MAX_REFINE_ROUNDS = 64,
+    RV_MAX_T_CELLS = 1024
 };
 
 typedef struct rv_config {
@@ -84,11 +85,13 @@ typedef struct rv_config {
     int32_t max_batch;           /* largest B of rot_vote_solve_batch (0: no batches) */
     int32_t batch_brick_edge;    /* batches' LDS bricks: 16 or 32 cells a side; 0: measured
                                     by rot_vote_tune_batch, else 32 */
-    int32_t reserved[2];         /* must be 0 */
+    int32_t reserved;            /* must be 0 */
+    int64_t max_pairs;           /* pair buffers of rot_vote_solve_rigid, 0..max_n pairs
+                                    (0: no rigid solves); 25 bytes each */
 } rv_config;
 
 /* Fills *cfg with: device 0, null stream, max_n 1<<20, max_grid 256, J = 8G,
- * K = 16, automatic vote strategy, no flags, no batches. */
+ * K = 16, automatic vote strategy, no flags, no batches, no pair buffers. */
 void rot_vote_default_config(rv_config *cfg);
 
 /* Creates a handle on cfg->device and allocates all device scratch for the
@@ -179,6 +182,81 @@ rv_status rot_vote_solve_multi(rv_handle *h, const float *x, const float *y, int
 rv_status rot_vote_refine(rv_handle *h, const float *x, const float *y, int64_t n, float eps_rad,
                           int32_t max_rounds, float q_io[4], int64_t *inlier_count,
                           uint8_t *inlier_mask, int32_t *rounds_run);
+
+/* Rigid pose from point correspondences, step 1 (Sec. 4.5, the pairwise
+ * constraint and the length check of Sec. 4.5.1): for i < j the differences
+ * m = x_i - x_j, n = y_i - y_j satisfy R m = n under the rigid motion
+ * y = R x + t, and a rotation keeps lengths, so a pair is kept iff
+ * | |m| - |n| | <= mu and both lengths are nonzero (binary32 lengths
+ * sqrt((c0*c0 + c1*c1) + c2*c2); a pair with a non-finite value is dropped).
+ * Kept pairs are written in row order (i ascending, then j ascending).
+ *   x, y          device float32 SoA [3][n] points (not directions).
+ *   n             0..max_n correspondences; the work is n(n-1)/2 pair tests.
+ *   mu            length tolerance >= 0, in the points' units.
+ *   capacity      room of the outputs, in pairs.
+ *   m_out, n_out  device float32 SoA [3][P] for the P kept pairs (component c
+ *                 of pair k at c*P + k).
+ *   idx_out       device int32 [2][P] (i then j), or NULL.
+ *   pairs         host: P.
+ * When P > capacity nothing is written but *pairs, and the call returns
+ * RV_ENOMEM.  Synchronous on the handle's stream. */
+rv_status rot_vote_pairs(rv_handle *h, const float *x, const float *y, int64_t n, float mu,
+                         int64_t capacity, float *m_out, float *n_out, int32_t *idx_out,
+                         int64_t *pairs);
+
+/* Rigid pose, the translation vote (Sec. 4.5.2): with the rotation q fixed,
+ * every correspondence gives a candidate t_i = y_i - R(q) x_i; the candidates
+ * vote in cubic cells of edge t_step over [t_min, t_min + t_cells * t_step)^3
+ * (cell floor((t_r - t_min) / t_step) per axis, index (c_z*T + c_y)*T + c_x; a
+ * candidate outside the domain or not finite does not vote), and t is the
+ * centre t_min + (c + 0.5) * t_step of the cell with the most candidates
+ * (ties to the lowest index).  A correspondence is an inlier iff
+ * |t_i - t| <= t_inlier.  R(q) is the homogeneous rotation matrix of the unit
+ * quaternion, all in binary32.  With no vote, t = 0 and there is no inlier.
+ *   q             host float[4] (w, x, y, z), unit.
+ *   t_step > 0, t_cells 1..RV_MAX_T_CELLS, t_inlier >= 0.
+ *   t_out         host float[3];  t_votes, inliers: host.
+ *   inlier_mask   device uint8[n].
+ * The vote costs O(n^2) comparisons (the mode of n cell indices), like the
+ * pair stage it follows.  Synchronous on the handle's stream. */
+rv_status rot_vote_translation(rv_handle *h, const float *x, const float *y, int64_t n,
+                               const float q[4], float t_min, float t_step, int32_t t_cells,
+                               float t_inlier, float t_out[3], int64_t *t_votes, int64_t *inliers,
+                               uint8_t *inlier_mask);
+
+typedef struct rv_rigid_params {
+    float mu;                 /* length tolerance of the pair check */
+    float eps_rad;            /* rotation inlier angle of the pairs' rescoring, (0, pi] */
+    int32_t grid;             /* rotation vote grid G, 1..max_grid */
+    int32_t refine_rounds;    /* least-squares rounds on the pairs' inliers, 0..64 */
+    float t_min;              /* translation domain [t_min, t_min + t_cells * t_step)^3 */
+    float t_step;             /* translation cell edge, > 0 */
+    int32_t t_cells;          /* cells per axis, 1..RV_MAX_T_CELLS */
+    float t_inlier;           /* inlier distance of the final pose, >= 0 */
+} rv_rigid_params;
+
+typedef struct rv_rigid_result {
+    float q[4];               /* rotation, w >= 0 */
+    float t[3];               /* translation */
+    int32_t refine_rounds_run;
+    int64_t pairs;            /* pairs kept by the length check */
+    int64_t rot_inliers;      /* pairs within eps_rad of q */
+    int64_t t_votes;          /* candidates in the translation cell */
+    int64_t inliers;          /* correspondences within t_inlier of (q, t) */
+} rv_rigid_result;
+
+/* Rigid pose (R, t) from point correspondences by pairwise decoupling
+ * (Sec. 4.5): rot_vote_pairs into the handle's pair buffers, the rotation
+ * solve (rot_vote_solve) on the kept pairs, refine_rounds of rot_vote_refine
+ * on the pairs' inliers when refine_rounds > 0, then rot_vote_translation.
+ * Each stage gives exactly what the separate calls give.
+ *   inlier_mask   device uint8[n] (the translation stage's mask).
+ * RV_EUNSUPPORTED if the handle has no pair buffers (max_pairs = 0); RV_ENOMEM
+ * (with res->pairs set) if more than max_pairs pairs pass the length check.
+ * Synchronous on the handle's stream. */
+rv_status rot_vote_solve_rigid(rv_handle *h, const float *x, const float *y, int64_t n,
+                               const rv_rigid_params *p, rv_rigid_result *res,
+                               uint8_t *inlier_mask);
 
 /* Many independent solves in one pass (Alg. 1 and the rescoring for each
  * instance; the instances share grid, J, K and eps).  Instance b is the

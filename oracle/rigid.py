@@ -36,7 +36,8 @@ per axis (correctly rounded binary32 division), a candidate outside the domain
 (or not finite) does not vote; cell index (c_z * cells + c_y) * cells + c_x;
 ties between cells go to the lowest index; the centre is
 t_min + ((float)c + 0.5) * step; the inlier test is
-(e0*e0 + e1*e1) + e2*e2 <= f32(tau^2) with e = t_i - t*; with no vote at all,
+(e0*e0 + e1*e1) + e2*e2 <= f32(tau^2) with e = t_i - t* (tau the binary32
+parameter, squared in binary64 and rounded once); with no vote at all,
 t* = 0 and no correspondence is an inlier.
 """
 from __future__ import annotations
@@ -55,6 +56,17 @@ def pairs(x, y, mu: float):
     mu = F(mu)
     N = x.shape[1]
     ms, ns, ii, jj = [], [], [], []
+    with np.errstate(over="ignore", invalid="ignore"):
+        _pair_rows(x, y, mu, N, ms, ns, ii, jj)
+    if not ms:
+        z = np.zeros((3, 0), F)
+        return z, z.copy(), np.zeros(0, np.int32), np.zeros(0, np.int32)
+    return (np.ascontiguousarray(np.concatenate(ms, axis=1)),
+            np.ascontiguousarray(np.concatenate(ns, axis=1)),
+            np.concatenate(ii), np.concatenate(jj))
+
+
+def _pair_rows(x, y, mu, N, ms, ns, ii, jj):
     for i in range(N - 1):
         m = x[:, i:i + 1] - x[:, i + 1:]
         d = y[:, i:i + 1] - y[:, i + 1:]
@@ -67,12 +79,6 @@ def pairs(x, y, mu: float):
             ns.append(d[:, k])
             ii.append(np.full(len(k), i, np.int32))
             jj.append((k + i + 1).astype(np.int32))
-    if not ms:
-        z = np.zeros((3, 0), F)
-        return z, z.copy(), np.zeros(0, np.int32), np.zeros(0, np.int32)
-    return (np.ascontiguousarray(np.concatenate(ms, axis=1)),
-            np.ascontiguousarray(np.concatenate(ns, axis=1)),
-            np.concatenate(ii), np.concatenate(jj))
 
 
 def rotation_matrix(q):
@@ -95,9 +101,10 @@ def candidates(x, y, R):
     y = np.ascontiguousarray(y, F)
     R = np.asarray(R, F)
     t = np.empty_like(y)
-    for r in range(3):
-        rx = (R[r, 0] * x[0] + R[r, 1] * x[1]) + R[r, 2] * x[2]
-        t[r] = y[r] - rx
+    with np.errstate(over="ignore", invalid="ignore"):
+        for r in range(3):
+            rx = (R[r, 0] * x[0] + R[r, 1] * x[1]) + R[r, 2] * x[2]
+            t[r] = y[r] - rx
     return t
 
 
@@ -128,7 +135,8 @@ def translation(x, y, q, t_min: float, step: float, ncell: int, tau: float) -> d
     ks, cnt = np.unique(valid, return_counts=True)
     best = int(np.argmax(cnt))           # first maximum: the lowest key among ties
     ts = centre(int(ks[best]), t_min, step, ncell)
-    T2 = F(float(tau) * float(tau))
+    tf = float(F(tau))                   # the binary32 parameter, squared in binary64
+    T2 = F(tf * tf)
     e = t - ts[:, None]
     with np.errstate(invalid="ignore", over="ignore"):
         d2 = (e[0] * e[0] + e[1] * e[1]) + e[2] * e[2]

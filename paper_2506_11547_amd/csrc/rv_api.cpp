@@ -93,6 +93,14 @@ struct rv_handle {
     rv::MultiState* d_mstate = nullptr;
     rv::MultiState* h_mstate = nullptr;   // pinned
 
+    // rigid pose: pair buffers of rot_vote_solve_rigid (max_pairs) and the stage state
+    int64_t max_pairs = 0;
+    float* d_pm = nullptr;                // [3][max_pairs]
+    float* d_pn = nullptr;                // [3][max_pairs]
+    uint8_t* d_pmask = nullptr;           // max_pairs
+    rv::RigidState* d_rigid = nullptr;
+    rv::RigidState* h_rigid = nullptr;    // pinned
+
     // refinement
     rv::RefineState* d_rstate = nullptr;
     rv::RefineState* h_rstate = nullptr;  // pinned
@@ -202,6 +210,11 @@ void release(rv_handle* h)
     (void)hipFree(h->d_bresult);
     (void)hipFree(h->d_bovf);
     (void)hipFree(h->d_bgrids);
+    (void)hipFree(h->d_pm);
+    (void)hipFree(h->d_pn);
+    (void)hipFree(h->d_pmask);
+    (void)hipFree(h->d_rigid);
+    (void)hipHostFree(h->h_rigid);
     (void)hipFree(h->d_mbits);
     (void)hipFree(h->d_mstate);
     (void)hipHostFree(h->h_mstate);
@@ -284,9 +297,10 @@ RV_API rv_status rot_vote_create(rv_handle** out, const rv_config* cfg)
     if (cfg->max_batch > 0 && cfg->vote_strategy == RV_VOTE_GLOBAL)
         return fail(nullptr, RV_EUNSUPPORTED,
                     "rot_vote_create: batches use the brick strategy (vote_strategy global)");
-    for (int r : cfg->reserved)
-        if (r != 0)
-            return fail(nullptr, RV_EINVAL, "rot_vote_create: reserved fields must be 0");
+    if (cfg->reserved != 0)
+        return fail(nullptr, RV_EINVAL, "rot_vote_create: reserved fields must be 0");
+    if (cfg->max_pairs < 0 || cfg->max_pairs > cfg->max_n)
+        return fail(nullptr, RV_EINVAL, "rot_vote_create: max_pairs outside 0..max_n");
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || cfg->device < 0 || cfg->device >= ndev)
         return fail(nullptr, RV_EINVAL, "rot_vote_create: no such HIP device");
@@ -346,6 +360,18 @@ RV_API rv_status rot_vote_create(rv_handle** out, const rv_config* cfg)
         return bail(e, "model scratch");
     if ((e = hipHostMalloc(&h->h_mstate, sizeof(rv::MultiState), hipHostMallocDefault)) != hipSuccess)
         return bail(e, "pinned model state");
+    if ((e = dev_alloc(h, &h->d_rigid, sizeof(rv::RigidState))) != hipSuccess)
+        return bail(e, "rigid state");
+    if ((e = hipHostMalloc(&h->h_rigid, sizeof(rv::RigidState), hipHostMallocDefault)) != hipSuccess)
+        return bail(e, "pinned rigid state");
+    h->max_pairs = cfg->max_pairs;
+    if (h->max_pairs > 0) {
+        const size_t P = (size_t)h->max_pairs;
+        if ((e = dev_alloc(h, &h->d_pm, 3 * P * sizeof(float))) != hipSuccess ||
+            (e = dev_alloc(h, &h->d_pn, 3 * P * sizeof(float))) != hipSuccess ||
+            (e = dev_alloc(h, &h->d_pmask, P)) != hipSuccess)
+            return bail(e, "pair buffers");
+    }
     h->max_batch = cfg->max_batch;
     h->batch_grid = std::min(h->max_grid, rv::kMaxBatchGrid);
     h->batch_grids = (cfg->flags & RV_FLAG_BATCH_GRIDS) != 0;
@@ -754,6 +780,143 @@ RV_API rv_status rot_vote_refine(rv_handle* h, const float* x, const float* y, i
     *inlier_count = (int64_t)st.count;
     if (rounds_run)
         *rounds_run = st.rounds;
+    return RV_OK;
+}
+
+RV_API rv_status rot_vote_pairs(rv_handle* h, const float* x, const float* y, int64_t n, float mu,
+                                int64_t capacity, float* m_out, float* n_out, int32_t* idx_out,
+                                int64_t* pairs)
+{
+    if (!h)
+        return RV_EINVAL;
+    h->err.clear();
+    if (!pairs)
+        return fail(h, RV_EINVAL, "rot_vote_pairs: pairs must not be NULL");
+    if (n < 0 || n > h->max_n)
+        return fail(h, RV_EINVAL, "rot_vote_pairs: n outside 0..max_n");
+    if (n > (int64_t)INT32_MAX)
+        return fail(h, RV_EUNSUPPORTED, "rot_vote_pairs: n exceeds int32 pair indices");
+    if (!(mu >= 0.0f))
+        return fail(h, RV_EINVAL, "rot_vote_pairs: mu must be >= 0");
+    if (capacity < 0)
+        return fail(h, RV_EINVAL, "rot_vote_pairs: capacity < 0");
+    if (n < 2) {
+        *pairs = 0;
+        return RV_OK;
+    }
+    if (!x || !y || !is_device_memory(x) || !is_device_memory(y))
+        return fail(h, RV_EINVAL, "rot_vote_pairs: x and y must be device memory");
+    RV_HIP(h, hipSetDevice(h->device), "hipSetDevice");
+    hipStream_t s = h->stream;
+    RV_HIP(h, rv::launch_pairs_count(x, y, n, mu, h->d_mbits, h->d_rigid, s), "pair count");
+    RV_HIP(h, hipMemcpyAsync(h->h_rigid, h->d_rigid, sizeof(rv::RigidState), hipMemcpyDeviceToHost, s),
+           "pair count readback");
+    RV_HIP(h, hipStreamSynchronize(s), "sync");
+    const int64_t P = (int64_t)h->h_rigid->pairs;
+    *pairs = P;
+    if (P > capacity)
+        return fail(h, RV_ENOMEM, "rot_vote_pairs: " + std::to_string(P) +
+                                      " pairs pass the length check, more than the capacity " +
+                                      std::to_string(capacity));
+    if (P == 0)
+        return RV_OK;
+    if (!m_out || !n_out || !is_device_memory(m_out) || !is_device_memory(n_out) ||
+        (idx_out && !is_device_memory(idx_out)))
+        return fail(h, RV_EINVAL, "rot_vote_pairs: m_out, n_out (and idx_out) must be device memory");
+    RV_HIP(h, rv::launch_pairs_emit(x, y, n, mu, h->d_mbits, P, m_out, n_out, idx_out, s),
+           "pair emit");
+    RV_HIP(h, hipStreamSynchronize(s), "sync");
+    return RV_OK;
+}
+
+RV_API rv_status rot_vote_translation(rv_handle* h, const float* x, const float* y, int64_t n,
+                                      const float q[4], float t_min, float t_step, int32_t t_cells,
+                                      float t_inlier, float t_out[3], int64_t* t_votes,
+                                      int64_t* inliers, uint8_t* inlier_mask)
+{
+    if (!h)
+        return RV_EINVAL;
+    h->err.clear();
+    if (!q || !t_out || !t_votes || !inliers)
+        return fail(h, RV_EINVAL, "rot_vote_translation: q, t_out, t_votes and inliers must not be NULL");
+    if (n < 0 || n > h->max_n)
+        return fail(h, RV_EINVAL, "rot_vote_translation: n outside 0..max_n");
+    for (int k = 0; k < 4; ++k)
+        if (!std::isfinite(q[k]))
+            return fail(h, RV_EINVAL, "rot_vote_translation: q must be finite");
+    if (!std::isfinite(t_min) || !(t_step > 0.0f) || !std::isfinite(t_step))
+        return fail(h, RV_EINVAL, "rot_vote_translation: t_min must be finite and t_step > 0");
+    if (t_cells < 1 || t_cells > RV_MAX_T_CELLS)
+        return fail(h, RV_EINVAL, "rot_vote_translation: t_cells outside 1..1024");
+    if (!(t_inlier >= 0.0f) || !std::isfinite(t_inlier))
+        return fail(h, RV_EINVAL, "rot_vote_translation: t_inlier must be finite and >= 0");
+    if (n > 0 && (!x || !y || !inlier_mask || !is_device_memory(x) || !is_device_memory(y) ||
+                  !is_device_memory(inlier_mask)))
+        return fail(h, RV_EINVAL, "rot_vote_translation: x, y and inlier_mask must be device memory");
+    RV_HIP(h, hipSetDevice(h->device), "hipSetDevice");
+    hipStream_t s = h->stream;
+    const float T2 = (float)((double)t_inlier * (double)t_inlier);
+    RV_HIP(h, rv::launch_translation(x, y, n, q, t_min, t_step, t_cells, T2,
+                                     reinterpret_cast<uint32_t*>(h->d_mbits), inlier_mask,
+                                     h->d_rigid, s),
+           "translation vote");
+    RV_HIP(h, hipMemcpyAsync(h->h_rigid, h->d_rigid, sizeof(rv::RigidState), hipMemcpyDeviceToHost, s),
+           "translation readback");
+    RV_HIP(h, hipStreamSynchronize(s), "sync");
+    const rv::RigidState& r = *h->h_rigid;
+    std::memcpy(t_out, r.t, sizeof(r.t));
+    *t_votes = (int64_t)r.votes;
+    *inliers = (int64_t)r.inliers;
+    return RV_OK;
+}
+
+RV_API rv_status rot_vote_solve_rigid(rv_handle* h, const float* x, const float* y, int64_t n,
+                                      const rv_rigid_params* p, rv_rigid_result* res,
+                                      uint8_t* inlier_mask)
+{
+    if (!h)
+        return RV_EINVAL;
+    h->err.clear();
+    if (!p || !res)
+        return fail(h, RV_EINVAL, "rot_vote_solve_rigid: p and res must not be NULL");
+    if (h->max_pairs == 0)
+        return fail(h, RV_EUNSUPPORTED, "rot_vote_solve_rigid: the handle has no pair buffers (max_pairs 0)");
+    if (p->grid < 1 || p->grid > h->max_grid)
+        return fail(h, RV_EINVAL, "rot_vote_solve_rigid: grid outside 1..max_grid");
+    if (!(p->eps_rad > 0.0f) || !(p->eps_rad <= (float)M_PI))
+        return fail(h, RV_EINVAL, "rot_vote_solve_rigid: eps_rad outside (0, pi]");
+    if (p->refine_rounds < 0 || p->refine_rounds > RV_MAX_REFINE_ROUNDS)
+        return fail(h, RV_EINVAL, "rot_vote_solve_rigid: refine_rounds outside 0..64");
+    if (!(p->mu >= 0.0f))
+        return fail(h, RV_EINVAL, "rot_vote_solve_rigid: mu must be >= 0");
+    if (!std::isfinite(p->t_min) || !(p->t_step > 0.0f) || !std::isfinite(p->t_step) ||
+        p->t_cells < 1 || p->t_cells > RV_MAX_T_CELLS || !(p->t_inlier >= 0.0f) ||
+        !std::isfinite(p->t_inlier))
+        return fail(h, RV_EINVAL, "rot_vote_solve_rigid: translation domain or t_inlier invalid");
+    if (n > 0 && (!inlier_mask || !is_device_memory(inlier_mask)))
+        return fail(h, RV_EINVAL, "rot_vote_solve_rigid: inlier_mask must be device memory");
+    rv_rigid_result r{};
+    r.q[0] = 1.0f;
+    if (rv_status st = rot_vote_pairs(h, x, y, n, p->mu, h->max_pairs, h->d_pm, h->d_pn, nullptr,
+                                      &r.pairs)) {
+        res->pairs = r.pairs;
+        return st;
+    }
+    const int64_t P = r.pairs;
+    if (P > 0) {
+        // the pair buffers hold [3][P] with stride P
+        if (rv_status st = rot_vote_solve(h, h->d_pm, h->d_pn, P, p->grid, p->eps_rad, r.q,
+                                          &r.rot_inliers, h->d_pmask))
+            return st;
+        if (p->refine_rounds > 0)
+            if (rv_status st = rot_vote_refine(h, h->d_pm, h->d_pn, P, p->eps_rad, p->refine_rounds,
+                                               r.q, &r.rot_inliers, h->d_pmask, &r.refine_rounds_run))
+                return st;
+    }
+    if (rv_status st = rot_vote_translation(h, x, y, n, r.q, p->t_min, p->t_step, p->t_cells,
+                                            p->t_inlier, r.t, &r.t_votes, &r.inliers, inlier_mask))
+        return st;
+    *res = r;
     return RV_OK;
 }
 

@@ -150,6 +150,29 @@ hipError_t launch_gather(const GatherItem* items, const Unit* units, int nunits,
 hipError_t launch_scatter_masks(const GatherItem* items, const Unit* units, int nunits,
                                 const uint8_t* dmask, hipStream_t s);
 
+// Rigid pose (Sec. 4.5): device state of the pair stage and the translation vote.
+struct RigidState {
+    uint64_t pairs;     // kept pairs (the row-count scan's total)
+    uint64_t best;      // (votes << 32) | ~key of the fullest translation cell; 0: no vote
+    float t[3];         // the cell's centre (0 without a vote)
+    uint32_t reserved;
+    uint64_t votes;
+    uint64_t inliers;
+};
+// Pair stage: per-row counts of kept pairs into rows[0..n), their exclusive
+// scan in place (total into st->pairs).
+hipError_t launch_pairs_count(const float* x, const float* y, int64_t n, float mu, uint64_t* rows,
+                              RigidState* st, hipStream_t s);
+// Writes the P kept pairs at the scanned row offsets (row order).
+hipError_t launch_pairs_emit(const float* x, const float* y, int64_t n, float mu,
+                             const uint64_t* rows, int64_t P, float* m_out, float* n_out,
+                             int32_t* idx_out, hipStream_t s);
+// Translation vote, centre, inlier mask and count (keys: 2n uint32 scratch,
+// the cells and their votes).
+hipError_t launch_translation(const float* x, const float* y, int64_t n, const float q[4],
+                              float t_min, float t_step, int t_cells, float T2, uint32_t* keys,
+                              uint8_t* mask, RigidState* st, hipStream_t s);
+
 hipError_t launch_rescore(const float* x, const float* y, int64_t n, float T2,
                           const Candidates& c, hipStream_t s);
 hipError_t launch_mask(const float* x, const float* y, int64_t n, float T2, const Candidates& c,

@@ -40,6 +40,7 @@ EXPORTS = ("rot_vote_default_config", "rot_vote_create", "rot_vote_destroy",
            "rot_vote_get_timings", "rot_vote_solve_batch", "rot_vote_get_batch_histogram",
            "rot_vote_get_batch_topk", "rot_vote_refine", "rot_vote_solve_multi",
            "rot_vote_get_footprint", "rot_vote_tune", "rot_vote_tune_batch",
+           "rot_vote_pairs", "rot_vote_translation", "rot_vote_solve_rigid",
            "rot_vote_server_default_config",
            "rot_vote_server_create",
            "rot_vote_server_destroy", "rot_vote_server_submit", "rot_vote_server_wait",
@@ -51,7 +52,19 @@ class RvConfig(ct.Structure):
                 ("max_grid", ct.c_int32), ("samples_per_circle", ct.c_int32),
                 ("topk", ct.c_int32), ("vote_strategy", ct.c_int32), ("flags", ct.c_uint32),
                 ("max_batch", ct.c_int32), ("batch_brick_edge", ct.c_int32),
-                ("reserved", ct.c_int32 * 2)]
+                ("reserved", ct.c_int32), ("max_pairs", ct.c_int64)]
+
+
+class RigidParams(ct.Structure):
+    _fields_ = [("mu", ct.c_float), ("eps_rad", ct.c_float), ("grid", ct.c_int32),
+                ("refine_rounds", ct.c_int32), ("t_min", ct.c_float), ("t_step", ct.c_float),
+                ("t_cells", ct.c_int32), ("t_inlier", ct.c_float)]
+
+
+class RigidResult(ct.Structure):
+    _fields_ = [("q", ct.c_float * 4), ("t", ct.c_float * 3), ("refine_rounds_run", ct.c_int32),
+                ("pairs", ct.c_int64), ("rot_inliers", ct.c_int64), ("t_votes", ct.c_int64),
+                ("inliers", ct.c_int64)]
 
 
 class ServerConfig(ct.Structure):
@@ -127,6 +140,14 @@ def load_library(path: Path | str = LIB_PATH) -> ct.CDLL:
     L.rot_vote_refine.argtypes = [vp, vp, vp, i64, f32, i32, ct.POINTER(f32 * 4), ct.POINTER(i64),
                                   vp, ct.POINTER(i32)]
     L.rot_vote_refine.restype = i32
+    L.rot_vote_pairs.argtypes = [vp, vp, vp, i64, f32, i64, vp, vp, vp, ct.POINTER(i64)]
+    L.rot_vote_pairs.restype = i32
+    L.rot_vote_translation.argtypes = [vp, vp, vp, i64, ct.POINTER(f32 * 4), f32, f32, i32, f32,
+                                       ct.POINTER(f32 * 3), ct.POINTER(i64), ct.POINTER(i64), vp]
+    L.rot_vote_translation.restype = i32
+    L.rot_vote_solve_rigid.argtypes = [vp, vp, vp, i64, ct.POINTER(RigidParams),
+                                       ct.POINTER(RigidResult), vp]
+    L.rot_vote_solve_rigid.restype = i32
     L.rot_vote_solve_multi.argtypes = [vp, vp, vp, i64, i32, f32, i32, f32, i64, ct.POINTER(f32),
                                        ct.POINTER(i64), ct.POINTER(i32), vp]
     L.rot_vote_solve_multi.restype = i32
@@ -157,6 +178,15 @@ def load_library(path: Path | str = LIB_PATH) -> ct.CDLL:
     return L
 
 
+def _points(x: torch.Tensor, y: torch.Tensor):
+    for t, nm in ((x, "x"), (y, "y")):
+        if t.dtype != torch.float32 or t.dim() != 2 or t.shape[0] != 3 or not t.is_cuda:
+            raise ValueError(f"{nm} must be a float32 [3, N] device tensor")
+    if x.shape != y.shape:
+        raise ValueError("x and y must have the same shape")
+    return x.contiguous(), y.contiguous()
+
+
 def eps_deg_to_rad(eps_deg: float) -> float:
     """Degrees to the float32 radians the C-ABI takes (converted in float64)."""
     return float(ct.c_float(eps_deg * math.pi / 180.0).value)
@@ -168,7 +198,8 @@ class Solver:
     def __init__(self, device: int = 0, max_n: int = 1 << 20, max_grid: int = 256,
                  topk: int = 16, samples_per_circle: int = 0, strategy: str = "auto",
                  timing: bool = False, stream: torch.cuda.Stream | None = None,
-                 max_batch: int = 0, batch_grids: bool = False, batch_brick_edge: int = 0):
+                 max_batch: int = 0, batch_grids: bool = False, batch_brick_edge: int = 0,
+                 max_pairs: int = 0):
         if not torch.cuda.is_available():
             raise RuntimeError("rotvote needs a HIP GPU; none is visible")
         self._lib = load_library()
@@ -186,6 +217,7 @@ class Solver:
         cfg.flags = (FLAG_TIMING if timing else 0) | (FLAG_BATCH_GRIDS if batch_grids else 0)
         cfg.max_batch = max_batch
         cfg.batch_brick_edge = batch_brick_edge
+        cfg.max_pairs = max_pairs
         h = ct.c_void_p()
         st = self._lib.rot_vote_create(ct.byref(h), ct.byref(cfg))
         if st != RV_OK:
@@ -334,6 +366,86 @@ class Solver:
         n = x.shape[1]
         return self.refine_raw(x.data_ptr(), y.data_ptr(), n, eps_deg_to_rad(eps_deg), max_rounds,
                                q, mask.data_ptr() if n else 0)
+
+    # ---- rigid pose (Sec. 4.5)
+    def pairs_raw(self, x_ptr: int, y_ptr: int, n: int, mu: float, capacity: int, m_ptr: int,
+                  n_ptr: int, idx_ptr: int):
+        """Direct C-ABI call; returns (status, P) without raising on RV_ENOMEM."""
+        P = ct.c_int64()
+        st = self._lib.rot_vote_pairs(self._h, ct.c_void_p(x_ptr), ct.c_void_p(y_ptr), n,
+                                      ct.c_float(mu), capacity, ct.c_void_p(m_ptr),
+                                      ct.c_void_p(n_ptr), ct.c_void_p(idx_ptr), ct.byref(P))
+        if st not in (RV_OK, RV_ENOMEM):
+            self._check(st)
+        return st, int(P.value)
+
+    def pairs(self, x: torch.Tensor, y: torch.Tensor, mu: float, capacity: int = 1 << 20):
+        """Pairwise differences that pass the length check (Sec. 4.5.1), in
+        row order.  Returns (m [3, P], n [3, P], idx int32 [2, P]); the
+        buffers are grown to P and the call repeated if P > capacity."""
+        x, y = _points(x, y)
+        n = x.shape[1]
+        while True:
+            cap = max(1, int(capacity))
+            mo = torch.empty(3 * cap, dtype=torch.float32, device=x.device)
+            no = torch.empty(3 * cap, dtype=torch.float32, device=x.device)
+            idx = torch.empty(2 * cap, dtype=torch.int32, device=x.device)
+            st, P = self.pairs_raw(x.data_ptr(), y.data_ptr(), n, mu, cap, mo.data_ptr(),
+                                   no.data_ptr(), idx.data_ptr())
+            if st == RV_OK:
+                return mo[:3 * P].view(3, P), no[:3 * P].view(3, P), idx[:2 * P].view(2, P)
+            capacity = P
+
+    def translation_raw(self, x_ptr: int, y_ptr: int, n: int, q, t_min: float, t_step: float,
+                        t_cells: int, t_inlier: float, mask_ptr: int):
+        """Direct C-ABI call; returns (t, votes, inliers)."""
+        qq = (ct.c_float * 4)(*[float(v) for v in q])
+        t = (ct.c_float * 3)()
+        votes = ct.c_int64()
+        inl = ct.c_int64()
+        self._check(self._lib.rot_vote_translation(
+            self._h, ct.c_void_p(x_ptr), ct.c_void_p(y_ptr), n, ct.byref(qq), ct.c_float(t_min),
+            ct.c_float(t_step), t_cells, ct.c_float(t_inlier), ct.byref(t), ct.byref(votes),
+            ct.byref(inl), ct.c_void_p(mask_ptr)))
+        return [t[0], t[1], t[2]], int(votes.value), int(inl.value)
+
+    def translation(self, x: torch.Tensor, y: torch.Tensor, q, t_min: float, t_step: float,
+                    t_cells: int, t_inlier: float, mask: torch.Tensor | None = None):
+        """Translation vote for a fixed rotation q (Sec. 4.5.2).  Returns
+        (t, votes, inliers, mask uint8 [N])."""
+        x, y = _points(x, y)
+        n = x.shape[1]
+        if mask is None:
+            mask = torch.empty(n, dtype=torch.uint8, device=x.device)
+        t, votes, inl = self.translation_raw(x.data_ptr(), y.data_ptr(), n, q, t_min, t_step,
+                                             t_cells, t_inlier, mask.data_ptr() if n else 0)
+        return t, votes, inl, mask
+
+    def solve_rigid_raw(self, x_ptr: int, y_ptr: int, n: int, params: RigidParams, mask_ptr: int):
+        """Direct C-ABI call; returns the RigidResult."""
+        res = RigidResult()
+        self._check(self._lib.rot_vote_solve_rigid(self._h, ct.c_void_p(x_ptr), ct.c_void_p(y_ptr),
+                                                   n, ct.byref(params), ct.byref(res),
+                                                   ct.c_void_p(mask_ptr)))
+        return res
+
+    def solve_rigid(self, x: torch.Tensor, y: torch.Tensor, mu: float, grid: int, eps_deg: float,
+                    t_min: float, t_step: float, t_cells: int, t_inlier: float,
+                    refine_rounds: int = 0, mask: torch.Tensor | None = None):
+        """Rigid pose (R, t) from point correspondences (Sec. 4.5).  Returns a
+        dict (q, t, pairs, rot_inliers, t_votes, inliers, refine_rounds_run,
+        mask uint8 [N])."""
+        x, y = _points(x, y)
+        n = x.shape[1]
+        if mask is None:
+            mask = torch.empty(n, dtype=torch.uint8, device=x.device)
+        p = RigidParams(mu, eps_deg_to_rad(eps_deg), grid, refine_rounds, t_min, t_step, t_cells,
+                        t_inlier)
+        r = self.solve_rigid_raw(x.data_ptr(), y.data_ptr(), n, p, mask.data_ptr() if n else 0)
+        self._last_grid = grid
+        return dict(q=list(r.q), t=list(r.t), pairs=int(r.pairs), rot_inliers=int(r.rot_inliers),
+                    t_votes=int(r.t_votes), inliers=int(r.inliers),
+                    refine_rounds_run=int(r.refine_rounds_run), mask=mask)
 
     def tune_batch(self, x: torch.Tensor, y: torch.Tensor, offsets, grid: int, eps_deg: float,
                    reps: int = 2):

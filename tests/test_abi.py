@@ -90,7 +90,18 @@ def test_default_config_and_create_without_gpu(lib_path):
     assert b"topk" in lib.rot_vote_last_error(None)
     assert not h.value
     cfg_sz = ct.sizeof(RvConfig)
-    assert cfg_sz == 64, cfg_sz  # rv_config: 4 + 4 pad + 8 + 8 + 4*4 + 4 + 4 + 12 + 4 pad
+    assert cfg_sz == 64, cfg_sz  # rv_config: 4 + 4 pad + 8 + 8 + 4*4 + 4 + 4 + 4 + 4 + 8
+    from paper_2506_11547_amd.rotvote import RigidParams, RigidResult
+    assert ct.sizeof(RigidParams) == 32 and ct.sizeof(RigidResult) == 64
+    for field, value, word in (("max_pairs", 1 << 21, b"max_pairs"), ("max_pairs", -1, b"max_pairs"),
+                               ("reserved", 1, b"reserved")):
+        bad = RvConfig()
+        lib.rot_vote_default_config(ct.byref(bad))
+        assert bad.max_pairs == 0
+        setattr(bad, field, value)
+        assert lib.rot_vote_create(ct.byref(h), ct.byref(bad)) == -1, field
+        assert word in lib.rot_vote_last_error(None)
+        assert not h.value
     bad = RvConfig()
     lib.rot_vote_default_config(ct.byref(bad))
     assert bad.max_batch == 0

@@ -1,0 +1,253 @@
+"""GPU: the rigid-pose front end (rot_vote_pairs, rot_vote_translation,
+rot_vote_solve_rigid; Sec. 4.5) against the oracle (oracle/rigid.py).
+
+* pairs: kept set, order, differences and indices bit-exact, over ragged
+  sizes around the 64-lane row chunks, mu = 0, coincident and non-finite
+  points; the capacity check;
+* translation: cell, centre, votes, inlier count and mask bit-exact for the
+  true, a perturbed and the identity rotation, one-cell and 1024-cell grids,
+  planted ties, candidates outside the domain, non-finite inputs;
+* the combined solve without refinement bit-exact end to end (pairs, rotation
+  vote, rescoring, translation), in the benchmark's configuration too
+  (N = 5000, 90 % outliers, G = 360, J = 180);
+* with refinement: equal to the separate calls chained, the translation
+  bit-exact against the oracle's for the refined rotation, the refined
+  rotation within 2 float32 ulps of the oracle's least squares;
+* argument errors.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import rigid as RG
+from paper_2506_11547_amd import datagen
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+F = np.float32
+T_MIN, STEP, NC = -5.0, 0.025, 400
+
+
+@pytest.fixture(scope="module")
+def rv():
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    from paper_2506_11547_amd import rotvote
+    return rotvote
+
+
+@pytest.fixture(scope="module")
+def orc():
+    return oracle.get()
+
+
+@pytest.fixture(scope="module")
+def solver(rv):
+    with rv.Solver(max_n=1 << 20, max_grid=360, topk=16, samples_per_circle=0,
+                   max_pairs=1 << 20) as s:
+        yield s
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def bits(a):
+    return np.ascontiguousarray(np.asarray(a, F)).view(np.uint32)
+
+
+def check_pairs(solver, x, y, mu):
+    m, n, idx = solver.pairs(dev(x), dev(y), mu, capacity=1024)
+    om, on, oi, oj = RG.pairs(x, y, mu)
+    assert m.shape[1] == om.shape[1]
+    assert np.array_equal(bits(m.cpu().numpy()), bits(om))
+    assert np.array_equal(bits(n.cpu().numpy()), bits(on))
+    ic = idx.cpu().numpy()
+    assert np.array_equal(ic[0], oi) and np.array_equal(ic[1], oj)
+    return om.shape[1]
+
+
+@pytest.mark.parametrize("n", [0, 1, 2, 3, 63, 64, 65, 129, 300])
+def test_pairs_shapes(solver, n):
+    inst = datagen.make_rigid_instance(n, 0.5, 0.01, 100 + n)
+    check_pairs(solver, inst.x, inst.y, 0.05)
+
+
+def test_pairs_edge_values(solver):
+    inst = datagen.make_rigid_instance(200, 0.3, 0.0, 7)
+    x, y = inst.x.copy(), inst.y.copy()
+    assert check_pairs(solver, x, y, 0.0) > 0          # mu = 0: exact length equality only
+    x[:, 10] = x[:, 11]                                # coincident points
+    y[:, 10] = y[:, 11]
+    x[1, 20] = np.nan
+    y[2, 30] = np.inf
+    x[0, 40] = 3e38                                    # squares overflow
+    check_pairs(solver, x, y, 0.05)
+    check_pairs(solver, x, y, 1e30)                    # everything finite passes
+
+
+def test_pairs_capacity(solver, rv):
+    inst = datagen.make_rigid_instance(150, 0.5, 0.01, 9)
+    P = RG.pairs(inst.x, inst.y, 0.05)[0].shape[1]
+    x, y = dev(inst.x), dev(inst.y)
+    buf = torch.empty(3 * P, dtype=torch.float32, device="cuda")
+    buf2 = torch.empty(3 * P, dtype=torch.float32, device="cuda")
+    st, got = solver.pairs_raw(x.data_ptr(), y.data_ptr(), inst.n, 0.05, P - 1, buf.data_ptr(),
+                               buf2.data_ptr(), 0)
+    assert st == rv.RV_ENOMEM and got == P
+    st, got = solver.pairs_raw(x.data_ptr(), y.data_ptr(), inst.n, 0.05, P, buf.data_ptr(),
+                               buf2.data_ptr(), 0)
+    assert st == rv.RV_OK and got == P
+    om, on, _, _ = RG.pairs(inst.x, inst.y, 0.05)
+    assert np.array_equal(bits(buf.view(3, P).cpu().numpy()), bits(om))
+
+
+def check_translation(solver, x, y, q, t_min=T_MIN, step=STEP, nc=NC, tau=0.06):
+    t, votes, inl, mask = solver.translation(dev(x), dev(y), q, t_min, step, nc, tau)
+    o = RG.translation(x, y, F(q), t_min, step, nc, tau)
+    assert np.array_equal(bits(t), bits(o["t"]))
+    assert votes == o["votes"] and inl == o["inliers"]
+    assert np.array_equal(mask.cpu().numpy().astype(bool), o["mask"])
+    return o
+
+
+def planted(seed):
+    """Identity rotation, candidates at cell coordinates: clusters 40, 40
+    (a tie), 15, plus 60 scattered."""
+    rng = np.random.default_rng(seed)
+    cl = [np.array([10, 200, 300]), np.array([9, 200, 300]), np.array([50, 60, 70])]
+    cs = [np.repeat(c[None, :], s, axis=0) for c, s in zip(cl, [40, 40, 15])]
+    cs.append(rng.integers(0, NC, size=(60, 3)))
+    c = np.concatenate(cs)
+    t = T_MIN + (c + 0.5 + rng.uniform(-0.3, 0.3, size=c.shape)) * STEP
+    x = rng.uniform(-1, 1, size=c.shape)
+    return np.ascontiguousarray(x.T.astype(F)), np.ascontiguousarray((x + t).T.astype(F))
+
+
+def test_translation_parity(solver):
+    inst = datagen.make_rigid_instance(3000, 0.8, 0.01, 31)
+    qg = F(inst.q_gt)
+    o = check_translation(solver, inst.x, inst.y, qg)
+    assert o["votes"] > 50
+    rng = np.random.default_rng(2)
+    qp = inst.q_gt + 0.002 * rng.normal(size=4)
+    check_translation(solver, inst.x, inst.y, F(qp / np.linalg.norm(qp)))
+    check_translation(solver, inst.x, inst.y, F([1, 0, 0, 0]))
+    check_translation(solver, inst.x, inst.y, qg, t_min=-2.0, step=4.0, nc=1, tau=0.0)
+    check_translation(solver, inst.x, inst.y, qg, t_min=-3.0, step=0.006, nc=1024, tau=0.02)
+    x, y = planted(4)
+    o = check_translation(solver, x, y, F([1, 0, 0, 0]), tau=0.02)
+    assert o["votes"] == 40 and o["key"] == (300 * NC + 200) * NC + 9
+
+
+def test_translation_edges(solver):
+    x = np.zeros((3, 5), F)
+    y = np.full((3, 5), 7.0, F)                        # outside the domain
+    o = check_translation(solver, x, y, F([1, 0, 0, 0]))
+    assert o["votes"] == 0
+    y[:, 3] = 0.1
+    y[1, 1] = np.nan
+    x[0, 4] = np.inf
+    check_translation(solver, x, y, F([1, 0, 0, 0]))
+    e = torch.empty(3, 0, device="cuda")
+    t, votes, inl, _ = solver.translation(e, e, [1, 0, 0, 0], T_MIN, STEP, NC, 0.1)
+    assert t == [0.0, 0.0, 0.0] and votes == 0 and inl == 0
+
+
+def check_rigid(solver, orc, inst, G, J, eps_deg, mu=0.05, tau=0.06):
+    eps = float(F(math.radians(eps_deg)))
+    r = solver.solve_rigid(dev(inst.x), dev(inst.y), mu, G, eps_deg, T_MIN, STEP, NC, tau)
+    o = RG.solve_rigid(orc, inst.x, inst.y, mu, G, J, eps, solver.topk_k, 0, T_MIN, STEP, NC, tau,
+                       nthreads=oracle.threads())
+    assert r["pairs"] == o["pairs"]
+    assert np.array_equal(bits(r["q"]), bits(o["q"]))
+    assert r["rot_inliers"] == o["rot_count"]
+    assert np.array_equal(bits(r["t"]), bits(o["t"]))
+    assert r["t_votes"] == o["votes"] and r["inliers"] == o["inliers"]
+    assert np.array_equal(r["mask"].cpu().numpy().astype(bool), o["mask"])
+    return r, o
+
+
+@pytest.mark.parametrize("n,rho,G", [(0, 0.5, 64), (1, 0.5, 64), (2, 0.0, 64), (120, 0.6, 48),
+                                     (700, 0.8, 64)])
+def test_solve_rigid_parity(solver, orc, n, rho, G):
+    inst = datagen.make_rigid_instance(n, rho, 0.01, 40 + n)
+    check_rigid(solver, orc, inst, G, 8 * G, 3.0)
+
+
+def test_solve_rigid_benchmark_configuration(rv, orc):
+    inst = datagen.make_rigid_instance(5000, 0.9, 0.01, 7)
+    with rv.Solver(max_n=1 << 21, max_grid=360, topk=16, samples_per_circle=180,
+                   max_pairs=1 << 21) as s:
+        r, o = check_rigid(s, orc, inst, 360, 180, 2.0)
+    assert r["pairs"] > 500000
+    assert datagen.rotation_error_deg(np.float64(r["q"]), inst.q_gt) < 1.0
+
+
+def test_solve_rigid_refined(solver, orc, rv):
+    inst = datagen.make_rigid_instance(1500, 0.85, 0.01, 8)
+    G, eps_deg, tau = 64, 3.0, 0.06
+    eps = float(F(math.radians(eps_deg)))
+    x, y = dev(inst.x), dev(inst.y)
+    r = solver.solve_rigid(x, y, 0.05, G, eps_deg, T_MIN, STEP, NC, tau, refine_rounds=8)
+    # the separate calls chained give the same, bit for bit
+    m, n, _ = solver.pairs(x, y, 0.05)
+    pm = torch.empty(m.shape[1], dtype=torch.uint8, device="cuda")
+    q, c, _ = solver.solve(m, n, G, eps_deg, mask=pm)
+    q, c, ran = solver.refine(m, n, q, pm, eps_deg, max_rounds=8)
+    t, votes, inl, mask = solver.translation(x, y, q, T_MIN, STEP, NC, tau)
+    assert r["q"] == q and r["rot_inliers"] == c and r["refine_rounds_run"] == ran
+    assert r["t"] == t and r["t_votes"] == votes and r["inliers"] == inl
+    assert torch.equal(r["mask"], mask)
+    # the translation stage against the oracle for this rotation
+    o = RG.translation(inst.x, inst.y, F(q), T_MIN, STEP, NC, tau)
+    assert np.array_equal(bits(t), bits(o["t"])) and votes == o["votes"] and inl == o["inliers"]
+    # the pairs' vote mask is the oracle's; at the fixed point the refined
+    # rotation is the oracle's least squares on the final mask (2 ulps) and
+    # that mask is the oracle's rescoring of the refined rotation
+    from oracle import refine as RF
+    mh, nh = m.cpu().numpy(), n.cpu().numpy()
+    o = orc.solve(mh, nh, G, 8 * G, eps, solver.topk_k, oracle.threads())
+    assert ran < 8
+    fin = pm.cpu().numpy()
+    q64, _ = RF.refine_once(orc, mh, nh, fin)
+    assert np.max(np.abs(np.float64(q) - q64)) <= 2.0 ** -22
+    cnt, om = orc.rescore(mh, nh, F(q), orc.residual_bound(eps), want_mask=True)
+    assert cnt == c and np.array_equal(om, fin)
+    assert o["count"] > 0
+    assert datagen.rotation_error_deg(np.float64(q), inst.q_gt) < 0.5
+    assert np.linalg.norm(np.float64(t) - inst.t_gt) < 0.03
+    assert int((mask.cpu().numpy().astype(bool) & inst.inlier).sum()) >= 0.95 * inst.inlier.sum()
+
+
+def test_rigid_errors(rv, solver):
+    x = torch.zeros(3, 10, device="cuda")
+    m = torch.empty(10, dtype=torch.uint8, device="cuda")
+    with rv.Solver(max_n=100, max_grid=64) as plain:
+        with pytest.raises(rv.RotVoteError) as e:
+            plain.solve_rigid(x, x, 0.1, 16, 2.0, T_MIN, STEP, NC, 0.1)
+        assert e.value.status == rv.RV_EUNSUPPORTED
+    for kw in (dict(grid=0), dict(grid=361), dict(eps_deg=0.0), dict(t_step=0.0),
+               dict(t_cells=0), dict(t_cells=1025), dict(t_inlier=-1.0), dict(refine_rounds=65)):
+        args = dict(mu=0.1, grid=16, eps_deg=2.0, t_min=T_MIN, t_step=STEP, t_cells=NC,
+                    t_inlier=0.1, refine_rounds=0)
+        args.update(kw)
+        with pytest.raises(rv.RotVoteError) as e:
+            solver.solve_rigid(x, x, mask=m, **args)
+        assert e.value.status == rv.RV_EINVAL, kw
+    with pytest.raises(rv.RotVoteError) as e:
+        solver.pairs_raw(x.data_ptr(), x.data_ptr(), 10, -1.0, 10, 0, 0, 0)
+    assert e.value.status == rv.RV_EINVAL
+    with pytest.raises(rv.RotVoteError) as e:
+        solver.translation(x, x, [float("nan"), 0, 0, 0], T_MIN, STEP, NC, 0.1, mask=m)
+    assert e.value.status == rv.RV_EINVAL
+    # more kept pairs than the handle's buffers
+    inst = datagen.make_rigid_instance(200, 0.0, 0.0, 3)
+    with rv.Solver(max_n=1000, max_grid=64, max_pairs=1000) as small:
+        with pytest.raises(rv.RotVoteError) as e:
+            small.solve_rigid(dev(inst.x), dev(inst.y), 0.05, 16, 2.0, T_MIN, STEP, NC, 0.1)
+        assert e.value.status == rv.RV_ENOMEM
