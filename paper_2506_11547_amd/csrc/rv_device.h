@@ -108,6 +108,7 @@ __device__ __forceinline__ float recip_1_2(float d)
 // 1 + |w| is the canonical denominator in every case, w = -0 included.
 struct Cell {
     unsigned x, y, z;
+    unsigned y_b1;  // y << 8 when G <= 256 (see cell_coords); unused values cost nothing
 };
 
 template <bool kFastRecip>
@@ -128,9 +129,16 @@ __device__ __forceinline__ Cell cell_coords(float qw, float qx, float qy, float 
     // clamp(floor(t), 0, G-1) == trunc(med3(t, 0, G - 1/2)) for every finite t:
     // below 0 both give 0, on [0, G-1/2] trunc is floor, above both give G-1.
     Cell c;
+    const float my = __builtin_amdgcn_fmed3f(ty, 0.0f, gm);
     c.x = (unsigned)__builtin_amdgcn_fmed3f(tx, 0.0f, gm);
-    c.y = (unsigned)__builtin_amdgcn_fmed3f(ty, 0.0f, gm);
+    c.y = (unsigned)my;
     c.z = (unsigned)__builtin_amdgcn_fmed3f(tz, 0.0f, gm);
+    // The same conversion written into byte 1 of a zeroed register: y << 8
+    // for y < 256 in one instruction (the compiler only forms the word-1
+    // variant by itself).
+    asm("v_cvt_u32_f32_sdwa %0, %1 dst_sel:BYTE_1 dst_unused:UNUSED_PAD src0_sel:DWORD"
+        : "=v"(c.y_b1)
+        : "v"(my));
     return c;
 }
 
@@ -146,6 +154,8 @@ template <bool kWide = false>
 __device__ __forceinline__ unsigned packed_coords(const Cell& c)
 {
     constexpr int kBits = kWide ? 9 : 8;
+    if constexpr (!kWide)
+        return c.x | c.y_b1 | (c.z << 16);
     return c.x | (c.y << kBits) | (c.z << (2 * kBits));
 }
 
