@@ -167,7 +167,7 @@ def loop_baseline(args, w, bt, x, y, mask, stream, q, cnt) -> dict:
     import torch
 
     from paper_2506_11547_amd import rotvote
-    offs = bt.offsets.tolist()
+    offs = bt.offsets
     single = rotvote.Solver(device=0, max_n=int(np.diff(bt.offsets).max()), max_grid=w.grid,
                             topk=w.topk, samples_per_circle=w.samples, stream=stream)
     views = [(x[:, offs[b]:offs[b + 1]], y[:, offs[b]:offs[b + 1]], mask[offs[b]:offs[b + 1]])
@@ -179,7 +179,7 @@ def loop_baseline(args, w, bt, x, y, mask, stream, q, cnt) -> dict:
     same = 0
     for b, (xb, yb, mb) in enumerate(views):
         qb, cb, _ = single.solve(xb, yb, w.grid, w.eps_deg, mask=mb)
-        same += int(qb == q[b] and cb == cnt[b])
+        same += int(qb == q[b].tolist() and cb == cnt[b])
     torch.cuda.synchronize()
     dt = time.perf_counter() - t1
     plan = single.plan()
@@ -442,7 +442,7 @@ def run_batch(args):
     n = int(bt.offsets[-1])
     mask = torch.empty(n, dtype=torch.bool, device=dev)
     stream = torch.cuda.current_stream(dev)
-    offs = bt.offsets.tolist()
+    offs = bt.offsets
     solver = rotvote.Solver(device=0, max_n=n, max_grid=w.grid, topk=w.topk,
                             samples_per_circle=w.samples, timing=True, stream=stream,
                             max_batch=bt.B)

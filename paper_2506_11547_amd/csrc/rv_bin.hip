@@ -247,10 +247,12 @@ __device__ __forceinline__ void bin_flush(uint32_t (*stage)[kStageCap], const ui
             const uint32_t cap = a.cap[qoff + b];
             s_dst[b] = make_uint2(a.qbase[q] + g, cap > g ? cap - g : 0u);
         }
-        s_cnt[b] = 0;
     }
     __syncthreads();
-    // 3: each run to its slot (brick and cell recomputed from the staged entry)
+    // 3: each run to its slot (brick and cell recomputed from the staged
+    //    entry).  Ranks count each brick's total back down to zero, so the
+    //    counters are clear for the next flush once every wave is through
+    //    here; the step barrier that precedes any flush guarantees that.
     for (uint32_t k = lane; k < my; k += kWave) {
         const uint32_t e = stage[wave][k];
         if (e == kDropped)
@@ -258,7 +260,7 @@ __device__ __forceinline__ void bin_flush(uint32_t (*stage)[kStageCap], const ui
         const uint32_t pc = e & Pack<kWide>::kCellMask;
         const uint32_t len = e >> Pack<kWide>::kLenShift;
         const uint32_t b = brick_of<kLog, kWide>(pc, nba);
-        const uint32_t rank = atomicAdd(&s_cnt[b], 1u);
+        const uint32_t rank = atomicSub(&s_cnt[b], 1u) - 1u;
         const uint2 d = s_dst[b];
         if (rank < d.y) {
             a.pool[(uint64_t)(d.x + rank)] = local_of<kLog, kWide>(pc) | (len << 15);
@@ -270,10 +272,6 @@ __device__ __forceinline__ void bin_flush(uint32_t (*stage)[kStageCap], const ui
             a.flags[qoff + b] = 1u;
         }
     }
-    __syncthreads();
-    for (int b = threadIdx.x; b < nb; b += kBinThreads)
-        s_cnt[b] = 0;
-    __syncthreads();
 }
 
 // One block per (512 correspondences, chunk of samples); chunks are whole run

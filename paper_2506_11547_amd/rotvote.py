@@ -13,6 +13,7 @@ import ctypes as ct
 import math
 from pathlib import Path
 
+import numpy as np
 import torch
 
 PKG = Path(__file__).resolve().parent
@@ -128,8 +129,7 @@ def load_library(path: Path | str = LIB_PATH) -> ct.CDLL:
     L.rot_vote_get_plan.restype = i32
     L.rot_vote_get_timings.argtypes = [vp, ct.POINTER(f32 * NUM_STAGES)]
     L.rot_vote_get_timings.restype = i32
-    L.rot_vote_solve_batch.argtypes = [vp, vp, vp, ct.POINTER(i64), i32, i32, f32,
-                                       ct.POINTER(f32), ct.POINTER(i64), vp]
+    L.rot_vote_solve_batch.argtypes = [vp, vp, vp, vp, i32, i32, f32, vp, vp, vp]
     L.rot_vote_solve_batch.restype = i32
     L.rot_vote_get_batch_histogram.argtypes = [vp, i32, vp]
     L.rot_vote_get_batch_histogram.restype = i32
@@ -185,6 +185,11 @@ def _points(x: torch.Tensor, y: torch.Tensor):
     if x.shape != y.shape:
         raise ValueError("x and y must have the same shape")
     return x.contiguous(), y.contiguous()
+
+
+def _offsets(offsets) -> np.ndarray:
+    """Batch offsets as a contiguous int64 array (no copy when they already are one)."""
+    return np.ascontiguousarray(offsets, dtype=np.int64).reshape(-1)
 
 
 def eps_deg_to_rad(eps_deg: float) -> float:
@@ -467,32 +472,36 @@ class Solver:
 
     def solve_batch_raw(self, x_ptr: int, y_ptr: int, offsets, grid: int, eps_rad: float,
                         mask_ptr: int):
-        """Direct C-ABI call: offsets is a sequence of B+1 ints.  Returns (q [B,4], counts [B])."""
-        B = len(offsets) - 1
-        offs = (ct.c_int64 * (B + 1))(*[int(o) for o in offsets])
-        q = (ct.c_float * (4 * max(B, 1)))()
-        cnt = (ct.c_int64 * max(B, 1))()
+        """Direct C-ABI call: offsets holds B+1 ints (an int64 array is used
+        without a copy).  Returns (q float32 [B, 4], counts int64 [B]) arrays."""
+        offs = _offsets(offsets)
+        B = offs.shape[0] - 1
+        q = np.empty((max(B, 1), 4), np.float32)
+        cnt = np.empty(max(B, 1), np.int64)
         self._check(self._lib.rot_vote_solve_batch(self._h, ct.c_void_p(x_ptr), ct.c_void_p(y_ptr),
-                                                   offs, B, grid, ct.c_float(eps_rad), q, cnt,
+                                                   ct.c_void_p(offs.ctypes.data), B, grid,
+                                                   ct.c_float(eps_rad), ct.c_void_p(q.ctypes.data),
+                                                   ct.c_void_p(cnt.ctypes.data),
                                                    ct.c_void_p(mask_ptr)))
         self._last_bgrid = grid
-        return [list(q[4 * b:4 * b + 4]) for b in range(B)], [int(c) for c in cnt[:B]]
+        return q[:B], cnt[:B]
 
     def solve_batch(self, x: torch.Tensor, y: torch.Tensor, offsets, grid: int, eps_deg: float,
                     mask: torch.Tensor | None = None):
         """Instances are the column ranges [offsets[b], offsets[b+1]) of x, y
-        (float32 [3, N] device tensors).  Returns (q [B][4], counts [B], mask)."""
+        (float32 [3, N] device tensors).  Returns (q float32 [B, 4] and
+        counts int64 [B] host arrays, mask)."""
         for t, nm in ((x, "x"), (y, "y")):
             if t.dtype != torch.float32 or t.dim() != 2 or t.shape[0] != 3 or not t.is_cuda:
                 raise ValueError(f"{nm} must be a float32 [3, N] device tensor")
         if x.shape != y.shape:
             raise ValueError("x and y must have the same shape")
-        offsets = [int(o) for o in offsets]
-        if not offsets or offsets[-1] > x.shape[1]:
+        offsets = _offsets(offsets)
+        if offsets.shape[0] == 0 or offsets[-1] > x.shape[1]:
             raise ValueError("offsets must hold B+1 entries with offsets[B] <= N")
         x = x.contiguous()
         y = y.contiguous()
-        n = offsets[-1]
+        n = int(offsets[-1])
         if mask is None:
             mask = torch.empty(x.shape[1], dtype=torch.bool, device=x.device)
         q, cnt = self.solve_batch_raw(x.data_ptr(), y.data_ptr(), offsets, grid,

@@ -131,7 +131,7 @@ def test_batch_equals_single_solves(rv):
         mb = mask.cpu().numpy()
         for b, (xb, yb) in enumerate(inst):
             q1, c1, m1 = s.solve(dev(xb), dev(yb), 64, 1.0)
-            assert q1 == q[b] and c1 == cnt[b], b
+            assert q1 == q[b].tolist() and c1 == cnt[b], b
             assert np.array_equal(m1.cpu().numpy(), mb[offs[b]:offs[b + 1]]), b
 
 
@@ -188,7 +188,7 @@ def test_tuned_brick_edge_changes_speed_only(rv):
         assert edge in (16, 32) and ms[16] > 0 and ms[32] > 0
         assert edge == (16 if ms[16] < ms[32] else 32)
         q1, c1, m1 = s.solve_batch(x, y, bt.offsets, 64, 1.0)
-        assert q0 == q1 and c0 == c1 and torch.equal(m0, m1)
+        assert np.array_equal(q0, q1) and np.array_equal(c0, c1) and torch.equal(m0, m1)
     with rv.Solver(max_n=1000, max_grid=64, max_batch=4, batch_brick_edge=16) as s:
         with pytest.raises(rv.RotVoteError):
             s.tune_batch(x, y, [0, 10], 64, 1.0)
@@ -211,9 +211,9 @@ def test_batch_error_conventions(rv):
                 s.solve_batch_raw(x.data_ptr(), x.data_ptr(), offs, G, 0.01, mask.data_ptr())
             assert e.value.status == status, offs
         q, c = s.solve_batch_raw(x.data_ptr(), x.data_ptr(), [0], 16, 0.01, mask.data_ptr())
-        assert q == [] and c == []
+        assert q.shape == (0, 4) and c.shape == (0,)
         q, c, m = s.solve_batch(x, x, [0, 0, 0], 16, 1.0)
-        assert q == [[1.0, 0.0, 0.0, 0.0]] * 2 and c == [0, 0]
+        assert q.tolist() == [[1.0, 0.0, 0.0, 0.0]] * 2 and c.tolist() == [0, 0]
     with rv.Solver(max_n=100, max_grid=32, topk=4) as s:
         with pytest.raises(rv.RotVoteError) as e:
             s.solve_batch(x, x, [0, 10], 16, 1.0)
