@@ -92,7 +92,8 @@ def copy_calibration(mib: int):
 
 TRAFFIC_RECORDS = {"large": ROOT / "profiles" / "vote_bin__large_traffic.json",
                    "batch": ROOT / "profiles" / "vote_bin__batch_traffic.json",
-                   "paper_default": ROOT / "profiles" / "vote_bin__paper_default_traffic.json"}
+                   "paper_default": ROOT / "profiles" / "vote_bin__paper_default_traffic.json",
+                   "rigid": ROOT / "profiles" / "vote_bin__rigid_traffic.json"}
 
 
 def vote_kernel_name(grid: int, edge: int = 32) -> str:
@@ -402,7 +403,8 @@ def run_rigid(args):
            "stage_ms": stage_ms, "vote_ms": vote_ms,
            "roofline": {"bound": "alu", "kernel": "vote (pairs)", "achieved": achieved / 1e3,
                         "peak": ALU_PEAK_GOPS / 1e3, "unit": "TOP/s",
-                        "frac": achieved / ALU_PEAK_GOPS, "traffic": None,
+                        "frac": achieved / ALU_PEAK_GOPS,
+                        "traffic": measured_traffic("rigid", vote_kernel_name(G)),
                         "ops_per_sample": OPS_PER_SAMPLE, "samples_per_launch": P * J,
                         "vote_ms": vote_ms},
            "result": {"pairs": P, "rot_inliers": r["rot_inliers"],
