@@ -221,12 +221,11 @@ __global__ __launch_bounds__(kPlanThreads) void k_bin_plan(BinArgs a, int nb)
 // counted per brick, one reservation atomic per brick, then written to its
 // queue slot (or, past the queue's capacity, added to the overflow grid).
 template <int kLog, bool kWide>
-__device__ __forceinline__ void bin_flush(uint32_t (*stage)[kStageCap], const uint32_t* s_fillw,
+__device__ __forceinline__ void bin_flush(uint32_t (*stage)[kStageCap], uint32_t my,
                                           uint32_t* s_cnt, uint2* s_dst, int wave, int lane, int nb,
                                           int nba, int G, int xs, int qoff, int64_t ovf_off,
                                           const BinArgs& a)
 {
-    const uint32_t my = s_fillw[wave];
     // 1: runs per brick (zero-length entries are marked dropped)
     for (uint32_t k = lane; k < my; k += kWave) {
         const uint32_t e = stage[wave][k];
@@ -289,9 +288,12 @@ __global__ __launch_bounds__(kBinThreads, kWide ? 2 : 3) void k_vote_bin(const f
     __shared__ uint32_t stage[kBinWaves][kStageCap];
     __shared__ uint32_t s_cnt[P::kMaxBricksHere];
     __shared__ uint2 s_dst[P::kMaxBricksHere];
-    // double-buffered by check parity: a wave that runs ahead writes the other
-    // half, so every wave reads the same counts and takes the same decision
-    __shared__ uint32_t s_fill[2][kBinWaves];
+    // The flush decision: the largest staged count of the block's waves, by
+    // an LDS atomic max into one of three slots used in turn.  Each check
+    // clears the previous check's slot, which every wave has read before
+    // this check's barrier and none writes again before the next barrier, so
+    // every wave reads the same maximum and takes the same decision.
+    __shared__ uint32_t s_maxfill[3];
     __shared__ uint32_t s_dummy[kBinWaves][kWave];
     const int nb = nba * nba * nba;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -319,6 +321,9 @@ __global__ __launch_bounds__(kBinThreads, kWide ? 2 : 3) void k_vote_bin(const f
     for (int b = threadIdx.x; b < nb; b += kBinThreads) {
         s_cnt[b] = 0;
     }
+    if (threadIdx.x < 3)
+        s_maxfill[threadIdx.x] = 0u;
+    __syncthreads();
     Quat u, v;
     const bool ok = load_circle(x, y, n, i0 + threadIdx.x, u, v) && (i0 + threadIdx.x < iend);
     uint32_t fill = 0;  // this wave's staged runs (wave-uniform)
@@ -330,7 +335,7 @@ __global__ __launch_bounds__(kBinThreads, kWide ? 2 : 3) void k_vote_bin(const f
     uint32_t cur = 0u;
     uint32_t cnt = 0u;
     uint32_t* my_stage = stage[wave];
-    int parity = 0;
+    int slot = 0;
 
     // Branch-free emission: the ballot of the bare compare stays a scalar
     // mask (usable lanes are masked in the scalar domain); lanes that do not
@@ -357,32 +362,27 @@ __global__ __launch_bounds__(kBinThreads, kWide ? 2 : 3) void k_vote_bin(const f
                 cur = change ? pc : cur;
             });
             if (lane == 0)
-                s_fill[parity][wave] = fill;
+                atomicMax(&s_maxfill[slot], fill);
             __syncthreads();
-            bool need = false;
-#pragma unroll
-            for (int w = 0; w < kBinWaves; ++w)
-                need |= s_fill[parity][w] > (uint32_t)kFlushAt;
+            const bool need = s_maxfill[slot] > (uint32_t)kFlushAt;
+            if (threadIdx.x == 0)
+                s_maxfill[slot == 0 ? 2 : slot - 1] = 0u;
             if (need) {
-                bin_flush<kLog, kWide>(stage, s_fill[parity], s_cnt, s_dst, wave, lane, nb, nba,
-                          G, xs, qoff, ovf_off, a);
+                bin_flush<kLog, kWide>(stage, fill, s_cnt, s_dst, wave, lane, nb, nba, G, xs, qoff,
+                                       ovf_off, a);
                 fill = 0;
             }
-            parity ^= 1;
+            slot = slot == 2 ? 0 : slot + 1;
         }
         emit(true);  // close every run at the block end (run lengths stay below 256)
         cnt = 0u;
     }
     if (lane == 0)
-        s_fill[parity][wave] = fill;
+        atomicMax(&s_maxfill[slot], fill);
     __syncthreads();
-    bool any = false;
-#pragma unroll
-    for (int w = 0; w < kBinWaves; ++w)
-        any |= s_fill[parity][w] > 0;
-    if (any)
-        bin_flush<kLog, kWide>(stage, s_fill[parity], s_cnt, s_dst, wave, lane, nb, nba, G, xs,
-                  qoff, ovf_off, a);
+    if (s_maxfill[slot] > 0u)
+        bin_flush<kLog, kWide>(stage, fill, s_cnt, s_dst, wave, lane, nb, nba, G, xs, qoff, ovf_off,
+                               a);
 }
 
 // ----------------------------------------------------------- accumulate
