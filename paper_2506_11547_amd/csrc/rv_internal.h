@@ -107,8 +107,6 @@ struct RefineState {
     uint32_t done;        // the last round changed no mask entry
     uint32_t ill_posed;   // the last solve kept the previous rotation
     uint64_t count;       // inliers of the current rotation
-    uint64_t count_next;  // accumulators of the running round
-    uint64_t changed;
     int64_t m;            // correspondences in the last solve
     int32_t rounds;       // rounds that ran (a converged round ends the rest)
     int32_t reserved;

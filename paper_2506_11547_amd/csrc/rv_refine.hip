@@ -122,33 +122,24 @@ __device__ void jacobi_sweep(double A[4][4], double V[4][4])
         }
 }
 
-__global__ __launch_bounds__(64) void k_refine_solve(const double* __restrict__ partial, int nblk,
-                                                     RefineState* __restrict__ st)
+// The block partials summed in a fixed order (each thread a fixed subset,
+// then a tree), then one thread solves the 4x4 eigenproblem.
+__global__ __launch_bounds__(kThreads) void k_refine_solve(const double* __restrict__ partial,
+                                                           int nblk, RefineState* __restrict__ st)
 {
-    __shared__ double sh[kSums][64];
+    __shared__ double sh[kSums][kThreads];
     if (st->done)
         return;
-    const int lane = threadIdx.x;
     double s[kSums];
 #pragma unroll
     for (int k = 0; k < kSums; ++k)
         s[k] = 0.0;
-    for (int b = lane; b < nblk; b += 64)
+    for (int b = threadIdx.x; b < nblk; b += kThreads)
 #pragma unroll
         for (int k = 0; k < kSums; ++k)
             s[k] += partial[(int64_t)b * kSums + k];
-#pragma unroll
-    for (int k = 0; k < kSums; ++k)
-        sh[k][lane] = s[k];
-    __syncthreads();
-    for (int w = 32; w > 0; w >>= 1) {
-        if (lane < w)
-#pragma unroll
-            for (int k = 0; k < kSums; ++k)
-                sh[k][lane] += sh[k][lane + w];
-        __syncthreads();
-    }
-    if (lane != 0)
+    block_sum(s, sh);
+    if (threadIdx.x != 0)
         return;
     const double m = sh[10][0];
     // Q^T Q = (m I - S) / 2
@@ -200,7 +191,8 @@ __global__ __launch_bounds__(64) void k_refine_solve(const double* __restrict__ 
 __global__ __launch_bounds__(kThreads) void k_refine_mask(const float* __restrict__ x,
                                                           const float* __restrict__ y, int64_t n,
                                                           float T2, RefineState* __restrict__ st,
-                                                          uint8_t* __restrict__ mask)
+                                                          uint8_t* __restrict__ mask,
+                                                          uint64_t* __restrict__ counts)
 {
     __shared__ uint32_t sh_in[kThreads / 64], sh_ch[kThreads / 64];
     if (st->done)
@@ -243,23 +235,44 @@ __global__ __launch_bounds__(kThreads) void k_refine_mask(const float* __restric
             a += sh_in[w];
             c += sh_ch[w];
         }
-        atomicAdd(reinterpret_cast<unsigned long long*>(&st->count_next), (unsigned long long)a);
-        atomicAdd(reinterpret_cast<unsigned long long*>(&st->changed), (unsigned long long)c);
+        // per-block counts, summed by k_refine_finish (no same-address
+        // atomics from every XCD)
+        counts[2 * blockIdx.x] = a;
+        counts[2 * blockIdx.x + 1] = c;
     }
 }
 
-// End of a round: publish the count; a round that changed nothing marks the
-// refinement as converged.
-__global__ void k_refine_finish(RefineState* __restrict__ st)
+// End of a round: publish the count (the blocks' counts summed); a round that
+// changed nothing marks the refinement as converged.
+__global__ __launch_bounds__(kThreads) void k_refine_finish(RefineState* __restrict__ st,
+                                                            const uint64_t* __restrict__ counts,
+                                                            int nblk)
 {
-    if (threadIdx.x != 0 || st->done)
+    __shared__ uint64_t sh[2][kThreads];
+    if (st->done)
         return;
-    st->count = st->count_next;
+    const int t = threadIdx.x;
+    uint64_t a = 0, c = 0;
+    for (int b = t; b < nblk; b += kThreads) {
+        a += counts[2 * b];
+        c += counts[2 * b + 1];
+    }
+    sh[0][t] = a;
+    sh[1][t] = c;
+    __syncthreads();
+    for (int w = kThreads / 2; w > 0; w >>= 1) {
+        if (t < w) {
+            sh[0][t] += sh[0][t + w];
+            sh[1][t] += sh[1][t + w];
+        }
+        __syncthreads();
+    }
+    if (t != 0)
+        return;
+    st->count = sh[0][0];
     st->rounds += 1;
-    if (st->changed == 0)
+    if (sh[1][0] == 0)
         st->done = 1u;
-    st->count_next = 0;
-    st->changed = 0;
 }
 
 __global__ void k_refine_init(RefineState* __restrict__ st, float qw, float qx, float qy, float qz)
@@ -273,8 +286,6 @@ __global__ void k_refine_init(RefineState* __restrict__ st, float qw, float qx, 
     st->done = 0u;
     st->ill_posed = 0u;
     st->count = 0;
-    st->count_next = 0;
-    st->changed = 0;
     st->m = 0;
     st->rounds = 0;
 }
@@ -299,9 +310,12 @@ hipError_t launch_refine(const float* x, const float* y, int64_t n, float T2, in
     for (int r = 0; r < rounds; ++r) {
         hipLaunchKernelGGL(k_refine_accum, dim3(nblk), dim3(kThreads), 0, s, x, y, n, mask, st,
                            partial);
-        hipLaunchKernelGGL(k_refine_solve, dim3(1), dim3(64), 0, s, partial, nblk, st);
-        hipLaunchKernelGGL(k_refine_mask, dim3(nblk), dim3(kThreads), 0, s, x, y, n, T2, st, mask);
-        hipLaunchKernelGGL(k_refine_finish, dim3(1), dim3(64), 0, s, st);
+        hipLaunchKernelGGL(k_refine_solve, dim3(1), dim3(kThreads), 0, s, partial, nblk, st);
+        // the mask's per-block counts reuse the partial buffer (its sums are consumed)
+        uint64_t* counts = reinterpret_cast<uint64_t*>(partial);
+        hipLaunchKernelGGL(k_refine_mask, dim3(nblk), dim3(kThreads), 0, s, x, y, n, T2, st, mask,
+                           counts);
+        hipLaunchKernelGGL(k_refine_finish, dim3(1), dim3(kThreads), 0, s, st, counts, nblk);
         if (hipError_t e = hipGetLastError(); e != hipSuccess)
             return e;
     }
