@@ -70,7 +70,8 @@ enum {
     RV_NUM_STAGES = 6,
     RV_MAX_BATCH_GRID = 64,
     RV_MAX_REFINE_ROUNDS = 64,
-    RV_MAX_T_CELLS = 1024
+    RV_MAX_T_CELLS = 1024,
+    RV_MAX_RIGID_N = 1 << 18  /* point correspondences of the quadratic rigid stages */
 };
 
 typedef struct rv_config {
@@ -191,7 +192,8 @@ rv_status rot_vote_refine(rv_handle *h, const float *x, const float *y, int64_t 
  * sqrt((c0*c0 + c1*c1) + c2*c2); a pair with a non-finite value is dropped).
  * Kept pairs are written in row order (i ascending, then j ascending).
  *   x, y          device float32 SoA [3][n] points (not directions).
- *   n             0..max_n correspondences; the work is n(n-1)/2 pair tests.
+ *   n             0..min(max_n, RV_MAX_RIGID_N) correspondences; the work is
+ *                 n(n-1)/2 pair tests (RV_EUNSUPPORTED above RV_MAX_RIGID_N).
  *   mu            length tolerance >= 0, in the points' units.
  *   capacity      room of the outputs, in pairs.
  *   m_out, n_out  device float32 SoA [3][P] for the P kept pairs (component c
@@ -218,7 +220,8 @@ rv_status rot_vote_pairs(rv_handle *h, const float *x, const float *y, int64_t n
  *   t_out         host float[3];  t_votes, inliers: host.
  *   inlier_mask   device uint8[n].
  * The vote costs O(n^2) comparisons (the mode of n cell indices), like the
- * pair stage it follows.  Synchronous on the handle's stream. */
+ * pair stage it follows: n is at most RV_MAX_RIGID_N (RV_EUNSUPPORTED above).
+ * Synchronous on the handle's stream. */
 rv_status rot_vote_translation(rv_handle *h, const float *x, const float *y, int64_t n,
                                const float q[4], float t_min, float t_step, int32_t t_cells,
                                float t_inlier, float t_out[3], int64_t *t_votes, int64_t *inliers,

@@ -794,8 +794,8 @@ RV_API rv_status rot_vote_pairs(rv_handle* h, const float* x, const float* y, in
         return fail(h, RV_EINVAL, "rot_vote_pairs: pairs must not be NULL");
     if (n < 0 || n > h->max_n)
         return fail(h, RV_EINVAL, "rot_vote_pairs: n outside 0..max_n");
-    if (n > (int64_t)INT32_MAX)
-        return fail(h, RV_EUNSUPPORTED, "rot_vote_pairs: n exceeds int32 pair indices");
+    if (n > (int64_t)RV_MAX_RIGID_N)
+        return fail(h, RV_EUNSUPPORTED, "rot_vote_pairs: n above RV_MAX_RIGID_N (quadratic work)");
     if (!(mu >= 0.0f))
         return fail(h, RV_EINVAL, "rot_vote_pairs: mu must be >= 0");
     if (capacity < 0)
@@ -841,6 +841,9 @@ RV_API rv_status rot_vote_translation(rv_handle* h, const float* x, const float*
         return fail(h, RV_EINVAL, "rot_vote_translation: q, t_out, t_votes and inliers must not be NULL");
     if (n < 0 || n > h->max_n)
         return fail(h, RV_EINVAL, "rot_vote_translation: n outside 0..max_n");
+    if (n > (int64_t)RV_MAX_RIGID_N)
+        return fail(h, RV_EUNSUPPORTED,
+                    "rot_vote_translation: n above RV_MAX_RIGID_N (quadratic work)");
     for (int k = 0; k < 4; ++k)
         if (!std::isfinite(q[k]))
             return fail(h, RV_EINVAL, "rot_vote_translation: q must be finite");

@@ -245,6 +245,16 @@ def test_rigid_errors(rv, solver):
     with pytest.raises(rv.RotVoteError) as e:
         solver.translation(x, x, [float("nan"), 0, 0, 0], T_MIN, STEP, NC, 0.1, mask=m)
     assert e.value.status == rv.RV_EINVAL
+    # the quadratic stages refuse more than RV_MAX_RIGID_N points (checked before any work)
+    with rv.Solver(max_n=(1 << 18) + 1, max_grid=64, max_pairs=100) as big:
+        z = torch.empty(3, (1 << 18) + 1, device="cuda")
+        with pytest.raises(rv.RotVoteError) as e:
+            big.pairs_raw(z.data_ptr(), z.data_ptr(), (1 << 18) + 1, 0.1, 10, 0, 0, 0)
+        assert e.value.status == rv.RV_EUNSUPPORTED
+        zm = torch.empty((1 << 18) + 1, dtype=torch.uint8, device="cuda")
+        with pytest.raises(rv.RotVoteError) as e:
+            big.translation(z, z, [1, 0, 0, 0], T_MIN, STEP, NC, 0.1, mask=zm)
+        assert e.value.status == rv.RV_EUNSUPPORTED
     # more kept pairs than the handle's buffers
     inst = datagen.make_rigid_instance(200, 0.0, 0.0, 3)
     with rv.Solver(max_n=1000, max_grid=64, max_pairs=1000) as small:
