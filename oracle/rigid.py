@@ -66,19 +66,25 @@ def pairs(x, y, mu: float):
             np.concatenate(ii), np.concatenate(jj))
 
 
+def pairs_of_row(x, y, mu, i: int):
+    """Row i of steps 1-2: the kept j > i, with their m and n (binary32)."""
+    m = x[:, i:i + 1] - x[:, i + 1:]
+    d = y[:, i:i + 1] - y[:, i + 1:]
+    lm = np.sqrt((m[0] * m[0] + m[1] * m[1]) + m[2] * m[2])
+    ln = np.sqrt((d[0] * d[0] + d[1] * d[1]) + d[2] * d[2])
+    keep = (lm > 0) & (ln > 0) & (np.abs(lm - ln) <= mu)
+    k = np.nonzero(keep)[0]
+    return (k + i + 1).astype(np.int32), m[:, k], d[:, k]
+
+
 def _pair_rows(x, y, mu, N, ms, ns, ii, jj):
     for i in range(N - 1):
-        m = x[:, i:i + 1] - x[:, i + 1:]
-        d = y[:, i:i + 1] - y[:, i + 1:]
-        lm = np.sqrt((m[0] * m[0] + m[1] * m[1]) + m[2] * m[2])
-        ln = np.sqrt((d[0] * d[0] + d[1] * d[1]) + d[2] * d[2])
-        keep = (lm > 0) & (ln > 0) & (np.abs(lm - ln) <= mu)
-        k = np.nonzero(keep)[0]
-        if len(k):
-            ms.append(m[:, k])
-            ns.append(d[:, k])
-            ii.append(np.full(len(k), i, np.int32))
-            jj.append((k + i + 1).astype(np.int32))
+        j, m, d = pairs_of_row(x, y, mu, i)
+        if len(j):
+            ms.append(m)
+            ns.append(d)
+            ii.append(np.full(len(j), i, np.int32))
+            jj.append(j)
 
 
 def rotation_matrix(q):

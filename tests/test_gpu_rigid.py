@@ -106,6 +106,34 @@ def test_pairs_capacity(solver, rv):
     assert np.array_equal(bits(buf.view(3, P).cpu().numpy()), bits(om))
 
 
+def test_rigid_stages_at_the_maximum_size(rv):
+    """RV_MAX_RIGID_N points (3.4e10 pair tests): sampled rows of the pair
+    stage bit-exact against the oracle's row computation (with the first and
+    the last rows), the row order everywhere, the translation stage in full."""
+    n = 1 << 18
+    inst = datagen.make_rigid_instance(n, 0.9, 0.01, 77)
+    mu = 1e-4
+    with rv.Solver(max_n=n, max_grid=64, max_pairs=1) as s:
+        m, nn, idx = s.pairs(dev(inst.x), dev(inst.y), mu, capacity=1 << 24)
+        P = m.shape[1]
+        assert P > 1000000
+        ic = idx.cpu().numpy()
+        assert np.all(ic[0] < ic[1])
+        key = ic[0].astype(np.int64) * n + ic[1]
+        assert np.all(np.diff(key) > 0)                       # row order, no duplicates
+        starts = np.searchsorted(ic[0], np.arange(n + 1))
+        mh, nh = m.cpu().numpy(), nn.cpu().numpy()
+        x32, y32 = np.ascontiguousarray(inst.x), np.ascontiguousarray(inst.y)
+        rows = [0, 1, n - 3, n - 2] + np.random.default_rng(5).integers(0, n - 1, 40).tolist()
+        for i in rows:
+            j, om, on = RG.pairs_of_row(x32, y32, np.float32(mu), i)
+            a, b = starts[i], starts[i + 1]
+            assert np.array_equal(ic[1, a:b], j), i
+            assert np.array_equal(bits(mh[:, a:b]), bits(om)), i
+            assert np.array_equal(bits(nh[:, a:b]), bits(on)), i
+        check_translation(s, inst.x, inst.y, F(inst.q_gt))
+
+
 def check_translation(solver, x, y, q, t_min=T_MIN, step=STEP, nc=NC, tau=0.06):
     t, votes, inl, mask = solver.translation(dev(x), dev(y), q, t_min, step, nc, tau)
     o = RG.translation(x, y, F(q), t_min, step, nc, tau)
