@@ -36,15 +36,7 @@ struct Brick {
     static constexpr int kWaves = kThreads / kWave;
 };
 constexpr int kSets = kQueueSets;
-constexpr int kBinWaves = 8;
-constexpr int kBinThreads = kBinWaves * kWave;
-static_assert(kBinThreads == kUnitSize, "a batch work unit is one vote block");
-// 1280 runs staged per wave between flushes and a flush check every 8 samples
-// keep a workgroup's LDS at 48 KiB, so three vote workgroups share a CU (two
-// with the wide layout's larger brick tables): measured 7-10 % faster than
-// two workgroups with twice the staging.
-constexpr int kStageCap = 1280;
-constexpr int kStep = 8;
+constexpr int kStep = 8;  // samples between flush checks
 // A staged run is its packed cell with the run length above it: 8-bit axes
 // and an 8-bit length (runs cut every 240 samples) for G <= 256, 9-bit axes
 // and a 5-bit length (cut every 24 samples) for G <= 384.  Cuts are multiples
@@ -58,10 +50,21 @@ struct Pack {
     static constexpr int kSplit = kWide ? 24 : 240;
     static_assert(kSplit % 8 == 0 && kSplit < (1 << (32 - kLenShift)), "cut and length field");
     static constexpr int kMaxBricksHere = kWide ? kMaxBricksAll : kMaxBricks;
+    // Vote workgroups.  8-bit cells: 8 waves staging 1280 runs each keep a
+    // workgroup's LDS at 48 KiB, so three share a CU (measured 7-10 % faster
+    // than two with twice the staging).  9-bit cells: nearly every sample of
+    // a short circle starts a run and 1728 bricks share a flush, so the runs
+    // are stored in brick order (bin_flush_sorted): one 16-wave workgroup per
+    // CU holds the staging and the 16-bit sort index (148 KiB of LDS).
+    static constexpr int kWaves = kWide ? 16 : 8;
+    static constexpr int kThreads = kWaves * kWave;
+    static constexpr int kStageCap = 1280;
+    static constexpr int kBlocksPerCU = kWide ? 1 : 3;
+    // flush before a step could overflow a wave's staging: one step adds at
+    // most kWave * kStep runs and a run-block boundary at most kWave more
+    static constexpr int kFlushAt = kStageCap - kWave * kStep - kWave;
 };
-// flush before a step could overflow a wave's staging: one step adds at most
-// kWave * kStep runs and a run-block boundary at most kWave more.
-constexpr int kFlushAt = kStageCap - kWave * kStep - kWave;
+static_assert(Pack<false>::kThreads == kUnitSize, "a batch work unit is one vote block");
 // Marks a dropped zero-length staged run.  A staged run never equals it: its
 // length field is at most 240 (of 8 bits) or 24 (of 5 bits).
 constexpr uint32_t kDropped = 0xFFFFFFFFu;
@@ -221,7 +224,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_bin_plan(BinArgs a, int nb)
 // counted per brick, one reservation atomic per brick, then written to its
 // queue slot (or, past the queue's capacity, added to the overflow grid).
 template <int kLog, bool kWide>
-__device__ __forceinline__ void bin_flush(uint32_t (*stage)[kStageCap], uint32_t my,
+__device__ __forceinline__ void bin_flush(uint32_t (*stage)[Pack<kWide>::kStageCap], uint32_t my,
                                           uint32_t* s_cnt, uint2* s_dst, int wave, int lane, int nb,
                                           int nba, int G, int xs, int qoff, int64_t ovf_off,
                                           const BinArgs& a)
@@ -238,7 +241,7 @@ __device__ __forceinline__ void bin_flush(uint32_t (*stage)[kStageCap], uint32_t
     __syncthreads();
     // 2: one reservation per brick in its queue; the first pool slot of this
     //    flush's runs and the room left before the queue's capacity
-    for (int b = threadIdx.x; b < nb; b += kBinThreads) {
+    for (int b = threadIdx.x; b < nb; b += Pack<kWide>::kThreads) {
         const uint32_t c = s_cnt[b];
         if (c) {
             const int64_t q = (int64_t)xs * a.qstride + qoff + b;
@@ -273,10 +276,114 @@ __device__ __forceinline__ void bin_flush(uint32_t (*stage)[kStageCap], uint32_t
     }
 }
 
+// The wide layout's flush: as bin_flush, but the runs are stored in brick
+// order.  Phase 2 also gives every brick a block-local range of sorted
+// positions (an exclusive scan of the counts), phase 3a puts each staged run's
+// index at its position, and phase 3b stores the runs position by position,
+// so a store instruction writes consecutive slots of a few bricks' queues
+// instead of one slot in each of 64.
+template <int kLog>
+__device__ __forceinline__ void bin_flush_sorted(uint32_t (*stage)[Pack<true>::kStageCap],
+                                                 uint32_t my, uint32_t* s_cnt, uint2* s_dst,
+                                                 uint32_t* s_scan, uint16_t* s_idx,
+                                                 uint32_t& s_total, int wave, int lane, int nb,
+                                                 int nba, int G, int xs, int qoff,
+                                                 int64_t ovf_off, const BinArgs& a)
+{
+    using P = Pack<true>;
+    constexpr int kT = P::kThreads;
+    constexpr int kPer = P::kMaxBricksHere / kT;
+    static_assert(P::kWaves * P::kStageCap <= 65536, "16-bit sort index");
+    const int t = threadIdx.x;
+    // 1: runs per brick (zero-length entries are marked dropped)
+    for (uint32_t k = lane; k < my; k += kWave) {
+        const uint32_t e = stage[wave][k];
+        if ((e >> P::kLenShift) == 0u) {
+            stage[wave][k] = kDropped;
+            continue;
+        }
+        atomicAdd(&s_cnt[brick_of<kLog, true>(e & P::kCellMask, nba)], 1u);
+    }
+    __syncthreads();
+    // 2: each thread's bricks t*kPer.. (consecutive, so a scan of the
+    //    per-thread sums orders the bricks); a reservation per brick, and the
+    //    first sorted position of its runs in s_cnt
+    uint32_t c[kPer];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        const int b = t * kPer + u;
+        c[u] = b < nb ? s_cnt[b] : 0u;
+        sum += c[u];
+    }
+    s_scan[t] = sum;
+    __syncthreads();
+    for (int off = 1; off < kT; off <<= 1) {  // inclusive (Hillis-Steele)
+        const uint32_t v = t >= off ? s_scan[t - off] : 0u;
+        __syncthreads();
+        s_scan[t] += v;
+        __syncthreads();
+    }
+    uint32_t pre = s_scan[t] - sum;
+    if (t == kT - 1)
+        s_total = s_scan[t];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        const int b = t * kPer + u;
+        if (b < nb) {
+            if (c[u]) {
+                const int64_t q = (int64_t)xs * a.qstride + qoff + b;
+                const uint32_t g = atomicAdd(a.fill + q, c[u]);
+                const uint32_t cap = a.cap[qoff + b];
+                const uint32_t room = cap > g ? cap - g : 0u;
+                // slot of sorted position p: qbase + g + (p - pre) (mod 2^32);
+                // positions from pre + room on overflow
+                s_dst[b] = make_uint2(a.qbase[q] + g - pre, pre + min(room, c[u]));
+            }
+            s_cnt[b] = pre;
+            pre += c[u];
+        }
+    }
+    __syncthreads();
+    // 3a: each run's stage index at its sorted position
+    for (uint32_t k = lane; k < my; k += kWave) {
+        const uint32_t e = stage[wave][k];
+        if (e == kDropped)
+            continue;
+        const uint32_t pos = atomicAdd(&s_cnt[brick_of<kLog, true>(e & P::kCellMask, nba)], 1u);
+        s_idx[pos] = (uint16_t)(wave * P::kStageCap + k);
+    }
+    __syncthreads();
+    // 3b: the runs in brick order; then the counters are cleared for the next
+    //    flush (phase 3a is done everywhere, and a step barrier precedes it).
+    //    The runs come from every wave's staging, so no wave may stage again
+    //    before all are stored: the closing barrier.
+    const uint32_t total = s_total;
+    const uint32_t* flat = &stage[0][0];
+    for (uint32_t p = t; p < total; p += kT) {
+        const uint32_t e = flat[s_idx[p]];
+        const uint32_t pc = e & P::kCellMask;
+        const uint32_t len = e >> P::kLenShift;
+        const uint32_t b = brick_of<kLog, true>(pc, nba);
+        const uint2 d = s_dst[b];
+        if (p < d.y) {
+            a.pool[(uint64_t)(d.x + p)] = local_of<kLog, true>(pc) | (len << 15);
+        } else {
+            const int64_t cell = ((int64_t)((pc >> (2 * P::kBits)) & P::kAxis) * G +
+                                  ((pc >> P::kBits) & P::kAxis)) * G + (pc & P::kAxis);
+            atomicAdd(a.ovf + ovf_off + cell, (int32_t)len);
+            a.flags[qoff + b] = 1u;
+        }
+    }
+    for (int b = t; b < nb; b += kT)
+        s_cnt[b] = 0u;
+    __syncthreads();
+}
+
 // One block per (512 correspondences, chunk of samples); chunks are whole run
 // blocks, so splitting J across blocks only adds run boundaries.
 template <int kLog, bool kWide>
-__global__ __launch_bounds__(kBinThreads, kWide ? 2 : 3) void k_vote_bin(const float* __restrict__ x,
+__global__ __launch_bounds__(Pack<kWide>::kThreads, Pack<kWide>::kBlocksPerCU) void k_vote_bin(const float* __restrict__ x,
                                                               const float* __restrict__ y,
                                                               int64_t n, int G, float H, float gm,
                                                               int J, int chunk, int ngroups,
@@ -285,7 +392,7 @@ __global__ __launch_bounds__(kBinThreads, kWide ? 2 : 3) void k_vote_bin(const f
 {
     using P = Pack<kWide>;
     constexpr int kSplit = P::kSplit;
-    __shared__ uint32_t stage[kBinWaves][kStageCap];
+    __shared__ uint32_t stage[P::kWaves][P::kStageCap];
     __shared__ uint32_t s_cnt[P::kMaxBricksHere];
     __shared__ uint2 s_dst[P::kMaxBricksHere];
     // The flush decision: the largest staged count of the block's waves, by
@@ -294,7 +401,10 @@ __global__ __launch_bounds__(kBinThreads, kWide ? 2 : 3) void k_vote_bin(const f
     // this check's barrier and none writes again before the next barrier, so
     // every wave reads the same maximum and takes the same decision.
     __shared__ uint32_t s_maxfill[3];
-    __shared__ uint32_t s_dummy[kBinWaves][kWave];
+    __shared__ uint32_t s_dummy[P::kWaves][kWave];
+    // the wide layout's sort index and run total (bin_flush_sorted)
+    __shared__ uint16_t s_idx[kWide ? P::kWaves * P::kStageCap : 1];
+    __shared__ uint32_t s_total;
     const int nb = nba * nba * nba;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
@@ -311,14 +421,14 @@ __global__ __launch_bounds__(kBinThreads, kWide ? 2 : 3) void k_vote_bin(const f
     } else {
         const int cb = blockIdx.x / ngroups;
         const int gb = blockIdx.x - cb * ngroups;
-        i0 = (int64_t)gb * kBinThreads;
+        i0 = (int64_t)gb * P::kThreads;
         iend = n;
         j0 = cb * chunk;
         j1 = min(J, j0 + chunk);
     }
     const int qoff = inst * nb;
     const int64_t ovf_off = (int64_t)inst * G * G * G;
-    for (int b = threadIdx.x; b < nb; b += kBinThreads) {
+    for (int b = threadIdx.x; b < nb; b += P::kThreads) {
         s_cnt[b] = 0;
     }
     if (threadIdx.x < 3)
@@ -351,6 +461,15 @@ __global__ __launch_bounds__(kBinThreads, kWide ? 2 : 3) void k_vote_bin(const f
         fill += (uint32_t)__popcll(m);
     };
 
+    auto flush = [&](uint32_t my) {
+        if constexpr (kWide)
+            bin_flush_sorted<kLog>(stage, my, s_cnt, s_dst, &s_dummy[0][0], s_idx, s_total, wave,
+                                   lane, nb, nba, G, xs, qoff, ovf_off, a);
+        else
+            bin_flush<kLog, kWide>(stage, my, s_cnt, s_dst, wave, lane, nb, nba, G, xs, qoff,
+                                   ovf_off, a);
+    };
+
     for (int jb = j0; jb < j1; jb += kSplit) {
         const int je = min(j1, jb + kSplit);
         for (int js = jb; js < je; js += kStep) {
@@ -364,12 +483,11 @@ __global__ __launch_bounds__(kBinThreads, kWide ? 2 : 3) void k_vote_bin(const f
             if (lane == 0)
                 atomicMax(&s_maxfill[slot], fill);
             __syncthreads();
-            const bool need = s_maxfill[slot] > (uint32_t)kFlushAt;
+            const bool need = s_maxfill[slot] > (uint32_t)P::kFlushAt;
             if (threadIdx.x == 0)
                 s_maxfill[slot == 0 ? 2 : slot - 1] = 0u;
             if (need) {
-                bin_flush<kLog, kWide>(stage, fill, s_cnt, s_dst, wave, lane, nb, nba, G, xs, qoff,
-                                       ovf_off, a);
+                flush(fill);
                 fill = 0;
             }
             slot = slot == 2 ? 0 : slot + 1;
@@ -381,8 +499,7 @@ __global__ __launch_bounds__(kBinThreads, kWide ? 2 : 3) void k_vote_bin(const f
         atomicMax(&s_maxfill[slot], fill);
     __syncthreads();
     if (s_maxfill[slot] > 0u)
-        bin_flush<kLog, kWide>(stage, fill, s_cnt, s_dst, wave, lane, nb, nba, G, xs, qoff, ovf_off,
-                               a);
+        flush(fill);
 }
 
 // ----------------------------------------------------------- accumulate
@@ -577,11 +694,13 @@ hipError_t launch_bin_vote(const float* x, const float* y, int64_t n, int G, int
     if (n <= 0)
         return hipSuccess;
     const bool wide = G > kNarrowGrid;
-    const int64_t ngroups = (n + kBinThreads - 1) / kBinThreads;
-    // at least ~4 rounds of workgroups over the GPU (3 resident per CU, 2 wide),
+    const int threads = wide ? Pack<true>::kThreads : Pack<false>::kThreads;
+    const int64_t ngroups = (n + threads - 1) / threads;
+    // at least ~4 rounds of workgroups over the GPU (3 resident per CU, 1 wide),
     // by splitting J into whole run blocks when there are few correspondences
     const int split_len = wide ? Pack<true>::kSplit : Pack<false>::kSplit;
-    const int64_t want = 4 * (wide ? 2 : 3) * 256;
+    const int64_t want =
+        4 * (wide ? Pack<true>::kBlocksPerCU : Pack<false>::kBlocksPerCU) * 256;
     const int64_t nblk = (J + split_len - 1) / split_len;
     const int64_t split = std::max<int64_t>(1, std::min<int64_t>(nblk, want / ngroups));
     const int chunk = (int)(((nblk + split - 1) / split) * split_len);
@@ -590,11 +709,11 @@ hipError_t launch_bin_vote(const float* x, const float* y, int64_t n, int G, int
     if (blocks > INT32_MAX || G > kMaxBrickGrid)
         return hipErrorInvalidValue;
     if (wide)
-        hipLaunchKernelGGL((k_vote_bin<5, true>), dim3((unsigned)blocks), dim3(kBinThreads), 0, s, x,
+        hipLaunchKernelGGL((k_vote_bin<5, true>), dim3((unsigned)blocks), dim3(threads), 0, s, x,
                            y, n, G, (float)G * 0.5f, (float)G - 0.5f, J, chunk, (int)ngroups, table,
                            brick_axis(G, 5), a);
     else
-        hipLaunchKernelGGL((k_vote_bin<5, false>), dim3((unsigned)blocks), dim3(kBinThreads), 0, s, x,
+        hipLaunchKernelGGL((k_vote_bin<5, false>), dim3((unsigned)blocks), dim3(threads), 0, s, x,
                            y, n, G, (float)G * 0.5f, (float)G - 0.5f, J, chunk, (int)ngroups, table,
                            brick_axis(G, 5), a);
     return hipGetLastError();
@@ -633,10 +752,10 @@ hipError_t launch_bin_vote_batch(const float* x, const float* y, int64_t n, int 
     if (nba * nba * nba > kMaxBricks)
         return hipErrorInvalidValue;
     if (edge_log2 == 5)
-        hipLaunchKernelGGL((k_vote_bin<5, false>), dim3((unsigned)nunits), dim3(kBinThreads), 0, s, x,
+        hipLaunchKernelGGL((k_vote_bin<5, false>), dim3((unsigned)nunits), dim3(Pack<false>::kThreads), 0, s, x,
                            y, n, G, (float)G * 0.5f, (float)G - 0.5f, J, J, 1, table, nba, a);
     else
-        hipLaunchKernelGGL((k_vote_bin<4, false>), dim3((unsigned)nunits), dim3(kBinThreads), 0, s, x,
+        hipLaunchKernelGGL((k_vote_bin<4, false>), dim3((unsigned)nunits), dim3(Pack<false>::kThreads), 0, s, x,
                            y, n, G, (float)G * 0.5f, (float)G - 0.5f, J, J, 1, table, nba, a);
     return hipGetLastError();
 }
