@@ -71,6 +71,9 @@ def parse():
     ap.add_argument("--workers", type=int, default=4, help="serve workload: server workers")
     ap.add_argument("--no-loop", action="store_true",
                     help="batch workload: skip the one-solve-per-call comparison")
+    ap.add_argument("--ceilings", action="store_true",
+                    help="only measure the GPU's ceilings (VALU issue, LDS and device atomics, "
+                         "copy bandwidth) with the probe library's micro-benchmarks and exit")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run plain device-to-device copies of MIB MiB (profiler "
                          "calibration of the HBM byte counters) and exit")
@@ -88,6 +91,42 @@ def copy_calibration(mib: int):
         dst.copy_(src)
     torch.cuda.synchronize()
     print(json.dumps({"copy_calibration_bytes": n * 4, "dispatches": 5}), flush=True)
+
+
+_CEILINGS = {}
+
+
+def measured_ceilings(full: bool = False) -> dict:
+    """Ceilings measured on this GPU by the probe library's micro-benchmarks:
+    32-bit FMA lane-operations/s (independent chains); with ``full`` also LDS
+    atomic adds/s (random and bank-distinct cells, 128 KiB array), relaxed
+    device-scope atomic adds/s into random cells of 1, 8 and 64 MiB int32
+    grids, and device copy bandwidth (read + write bytes/s of a 1 GiB copy)."""
+    key = "full" if full else "valu"
+    if key in _CEILINGS:
+        return _CEILINGS[key]
+    from paper_2506_11547_amd import rotvote
+    p = rotvote.Probe()
+    out = {"valu_top_s": p.ceiling_valu() / 1e12}
+    if full:
+        out["lds_atomic_random_per_s"] = p.ceiling_lds_atomic(True)
+        out["lds_atomic_distinct_per_s"] = p.ceiling_lds_atomic(False)
+        out["global_atomic_per_s"] = {f"{mib}MiB": p.ceiling_global_atomic(mib << 18)
+                                      for mib in (1, 8, 64)}
+        out["copy_gb_s"] = p.ceiling_copy() / 1e9
+    _CEILINGS[key] = out
+    return out
+
+
+def alu_roofline(kernel: str, achieved_gops: float, traffic, **extra) -> dict:
+    """The roofline object of an ALU-bound vote kernel: against the published
+    issue peak (``frac``) and against the FMA issue rate measured here
+    (``frac_measured``)."""
+    valu = measured_ceilings()["valu_top_s"]
+    return {"bound": "alu", "kernel": kernel, "achieved": achieved_gops / 1e3,
+            "peak": ALU_PEAK_GOPS / 1e3, "unit": "TOP/s", "frac": achieved_gops / ALU_PEAK_GOPS,
+            "traffic": traffic, "measured_peak": valu, "frac_measured": achieved_gops / 1e3 / valu,
+            **extra}
 
 
 TRAFFIC_RECORDS = {"large": ROOT / "profiles" / "vote_bin__large_traffic.json",
@@ -135,11 +174,19 @@ def cpu_baseline(w, inst, n_sample: int) -> dict:
     t0 = time.perf_counter()
     o.solve(x, y, w.grid, w.samples, eps, w.topk, nthreads=threads)
     dt = time.perf_counter() - t0
+    # the same solve on one thread, on a fifteenth of the sample
+    n1 = max(1, n_sample // 15)
+    t1 = time.perf_counter()
+    o.solve(x[:, :n1].copy(), y[:, :n1].copy(), w.grid, w.samples, eps, w.topk, nthreads=1)
+    dt1 = time.perf_counter() - t1
     return {"value": n_sample * w.samples / dt, "unit": "votes/s", "cores": threads,
             "kind": "oracle",
             "sample": f"first {n_sample} of the {inst.n} correspondences, whole solve "
                       f"(G={w.grid}, J={w.samples}, K={w.topk}); vote loop on {threads} "
-                      f"OpenMP threads, top-K and rescoring single-threaded; {dt:.2f} s"}
+                      f"OpenMP threads, top-K and rescoring single-threaded; {dt:.2f} s",
+            "single_thread": {"value": n1 * w.samples / dt1, "unit": "votes/s", "cores": 1,
+                              "sample": f"first {n1} correspondences, whole solve on one "
+                                        f"thread; {dt1:.2f} s"}}
 
 
 def cpu_baseline_batch(w, bt, max_instances: int) -> dict:
@@ -401,12 +448,10 @@ def run_rigid(args):
            "solves_per_s": 1.0 / dt,
            "pair_tests_per_s": n * (n - 1) / 2 / (stage_ms["pairs"] * 1e-3),
            "stage_ms": stage_ms, "vote_ms": vote_ms,
-           "roofline": {"bound": "alu", "kernel": "vote (pairs)", "achieved": achieved / 1e3,
-                        "peak": ALU_PEAK_GOPS / 1e3, "unit": "TOP/s",
-                        "frac": achieved / ALU_PEAK_GOPS,
-                        "traffic": measured_traffic("rigid", vote_kernel_name(G)),
-                        "ops_per_sample": OPS_PER_SAMPLE, "samples_per_launch": P * J,
-                        "vote_ms": vote_ms},
+           "roofline": alu_roofline("vote (pairs)", achieved,
+                                    measured_traffic("rigid", vote_kernel_name(G)),
+                                    ops_per_sample=OPS_PER_SAMPLE, samples_per_launch=P * J,
+                                    vote_ms=vote_ms),
            "result": {"pairs": P, "rot_inliers": r["rot_inliers"],
                       "refine_rounds_run": r["refine_rounds_run"],
                       "e_R_deg": datagen.rotation_error_deg(np.float64(r["q"]), inst.q_gt),
@@ -495,10 +540,10 @@ def run_batch(args):
         "stage_ms": stage_ms,
         "loop": loop if loop is None else dict(loop, speedup_of_batch=(bt.B * steps / dt) /
                                                   loop["solves_per_s"]),
-        "roofline": {"bound": "alu", "kernel": "vote (batched)", "achieved": achieved / 1e3,
-                     "peak": ALU_PEAK_GOPS / 1e3, "unit": "TOP/s", "frac": achieved / ALU_PEAK_GOPS,
-                     "traffic": measured_traffic(w.name, vote_kernel_name(w.grid, edge)), "ops_per_sample": OPS_PER_SAMPLE,
-                     "samples_per_launch": samples, "vote_ms": stage_ms["vote"]},
+        "roofline": alu_roofline("vote (batched)", achieved,
+                                 measured_traffic(w.name, vote_kernel_name(w.grid, edge)),
+                                 ops_per_sample=OPS_PER_SAMPLE, samples_per_launch=samples,
+                                 vote_ms=stage_ms["vote"]),
         "result": {"median_e_R_deg": float(np.median(err)), "p99_e_R_deg": float(np.percentile(err, 99)),
                    "inliers_total": int(sum(cnt))},
     }
@@ -528,6 +573,11 @@ def refine_leg(solver, x, y, q, mask, w, inst, reps: int = 5) -> dict:
 
 def main():
     args = parse()
+    if args.ceilings:
+        print(json.dumps({"ceilings": measured_ceilings(full=True),
+                          "published": {"alu_top_s": ALU_PEAK_GOPS / 1e3,
+                                        "hbm_gb_s": HBM_PEAK_GBS}}), flush=True)
+        return
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
         return
@@ -608,12 +658,11 @@ def main():
         "solves_per_s": steps / dt,
         "stage_ms": stage_ms,
         "strategy_tuning": tuned,
-        "roofline": {"bound": "alu", "kernel": "vote", "achieved": achieved / 1e3,
-                     "peak": ALU_PEAK_GOPS / 1e3, "unit": "TOP/s", "frac": achieved / ALU_PEAK_GOPS,
-                     "traffic": (measured_traffic(w.name, vote_kernel_name(w.grid))
-                                 if plan["strategy"] == "brick" else None),
-                     "ops_per_sample": OPS_PER_SAMPLE, "samples_per_launch": samples,
-                     "vote_ms": stage_ms["vote"]},
+        "roofline": alu_roofline("vote", achieved,
+                                 (measured_traffic(w.name, vote_kernel_name(w.grid))
+                                  if plan["strategy"] == "brick" else None),
+                                 ops_per_sample=OPS_PER_SAMPLE, samples_per_launch=samples,
+                                 vote_ms=stage_ms["vote"]),
         "result": {"q": q, "inliers": cnt, "e_R_deg": datagen.rotation_error_deg(q, inst.q_gt),
                    "winner": top["winner"], "true_inliers": int(inst.inlier.sum())},
         "refine": refine,

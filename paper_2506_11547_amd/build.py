@@ -43,7 +43,7 @@ def build(verbose: bool = False) -> list[Path]:
                CSRC / "rv_refine.hip", CSRC / "rv_multi.hip", CSRC / "rv_rigid.hip",
                CSRC / "rv_api.cpp",
                CSRC / "rv_serve.cpp"]),
-        (PROBE_LIB, [CSRC / "rv_probe.hip"]),
+        (PROBE_LIB, [CSRC / "rv_probe.hip", CSRC / "rv_ceil.hip"]),
     ]
     out = []
     for lib, srcs in jobs:

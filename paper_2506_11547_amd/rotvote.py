@@ -663,8 +663,14 @@ class Probe:
         L.rvp_cells.argtypes = [vp, i64, i32, vp, i32]
         L.rvp_decode.argtypes = [vp, i64, i32, vp]
         L.rvp_residual.argtypes = [vp, vp, i64, vp, vp]
+        d = ct.POINTER(ct.c_double)
+        L.rvp_ceil_valu.argtypes = [i32, i32, d]
+        L.rvp_ceil_lds_atomic.argtypes = [i32, i32, i32, d]
+        L.rvp_ceil_global_atomic.argtypes = [i64, i32, i32, d]
+        L.rvp_ceil_copy.argtypes = [i64, d]
         for f in (L.rvp_recip, L.rvp_div_sqrt, L.rvp_basis, L.rvp_cells, L.rvp_decode,
-                  L.rvp_residual):
+                  L.rvp_residual, L.rvp_ceil_valu, L.rvp_ceil_lds_atomic,
+                  L.rvp_ceil_global_atomic, L.rvp_ceil_copy):
             f.restype = i32
 
     @staticmethod
@@ -708,6 +714,29 @@ class Probe:
         q = torch.empty(idx.numel(), 4, dtype=torch.float32, device=idx.device)
         self._run(self.lib.rvp_decode(self._p(idx), idx.numel(), G, self._p(q)))
         return q
+
+    def _rate(self, fn, *args) -> float:
+        torch.cuda.synchronize()
+        r = ct.c_double()
+        self._run(fn(*args, ct.byref(r)))
+        return r.value
+
+    def ceiling_valu(self, blocks: int = 8192, iters: int = 4096) -> float:
+        """32-bit FMA lane-operations per second (independent chains)."""
+        return self._rate(self.lib.rvp_ceil_valu, blocks, iters)
+
+    def ceiling_lds_atomic(self, random: bool, blocks: int = 1024, iters: int = 1024) -> float:
+        """LDS atomic adds per second (random or bank-distinct cells)."""
+        return self._rate(self.lib.rvp_ceil_lds_atomic, blocks, iters, int(random))
+
+    def ceiling_global_atomic(self, cells: int, blocks: int = 4096, iters: int = 256) -> float:
+        """Relaxed device-scope atomic adds per second into random cells of an
+        int32 grid of ``cells`` entries (a power of two)."""
+        return self._rate(self.lib.rvp_ceil_global_atomic, cells, blocks, iters)
+
+    def ceiling_copy(self, nbytes: int = 1 << 30) -> float:
+        """Bytes read plus written per second by a device copy."""
+        return self._rate(self.lib.rvp_ceil_copy, nbytes)
 
     def residual(self, x: torch.Tensor, y: torch.Tensor, q: torch.Tensor) -> torch.Tensor:
         torch.cuda.synchronize()

@@ -69,7 +69,8 @@ def test_product_library_does_not_reference_the_oracle(lib_path):
 
 def test_probe_library_exports(lib_path):
     syms = dynamic_symbols(PROBE)
-    for n in ("rvp_recip", "rvp_div_sqrt", "rvp_basis", "rvp_cells", "rvp_decode", "rvp_residual"):
+    for n in ("rvp_recip", "rvp_div_sqrt", "rvp_basis", "rvp_cells", "rvp_decode", "rvp_residual",
+              "rvp_ceil_valu", "rvp_ceil_lds_atomic", "rvp_ceil_global_atomic", "rvp_ceil_copy"):
         assert n in syms
 
 
