@@ -307,38 +307,47 @@ __device__ __forceinline__ void bin_flush_sorted(uint32_t (*stage)[Pack<true>::k
     __syncthreads();
     // 2: each thread's bricks t*kPer.. (consecutive, so a scan of the
     //    per-thread sums orders the bricks); a reservation per brick, and the
-    //    first sorted position of its runs in s_cnt
-    uint32_t c[kPer];
+    //    first sorted position of its runs in s_cnt.  The reservation atomics
+    //    are issued first: their round trip overlaps the scan (issuing the
+    //    capacity and queue-base loads with them measured slower).
+    uint32_t c[kPer], g[kPer];
     uint32_t sum = 0;
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
         const int b = t * kPer + u;
         c[u] = b < nb ? s_cnt[b] : 0u;
         sum += c[u];
+        const int64_t q = (int64_t)xs * a.qstride + qoff + b;
+        g[u] = c[u] ? atomicAdd(a.fill + q, c[u]) : 0u;
     }
-    s_scan[t] = sum;
+    // inclusive scan of the sums within the wave, then over the wave totals
+    uint32_t incl = sum;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        const uint32_t v = __shfl_up(incl, off);
+        incl += lane >= off ? v : 0u;
+    }
+    if (lane == kWave - 1)
+        s_scan[wave] = incl;
     __syncthreads();
-    for (int off = 1; off < kT; off <<= 1) {  // inclusive (Hillis-Steele)
-        const uint32_t v = t >= off ? s_scan[t - off] : 0u;
-        __syncthreads();
-        s_scan[t] += v;
-        __syncthreads();
-    }
-    uint32_t pre = s_scan[t] - sum;
+    uint32_t wpre = 0;
+#pragma unroll
+    for (int w = 0; w < P::kWaves; ++w)
+        wpre += w < wave ? s_scan[w] : 0u;
+    uint32_t pre = wpre + incl - sum;
     if (t == kT - 1)
-        s_total = s_scan[t];
+        s_total = wpre + incl;
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
         const int b = t * kPer + u;
         if (b < nb) {
             if (c[u]) {
                 const int64_t q = (int64_t)xs * a.qstride + qoff + b;
-                const uint32_t g = atomicAdd(a.fill + q, c[u]);
                 const uint32_t cap = a.cap[qoff + b];
-                const uint32_t room = cap > g ? cap - g : 0u;
+                const uint32_t room = cap > g[u] ? cap - g[u] : 0u;
                 // slot of sorted position p: qbase + g + (p - pre) (mod 2^32);
                 // positions from pre + room on overflow
-                s_dst[b] = make_uint2(a.qbase[q] + g - pre, pre + min(room, c[u]));
+                s_dst[b] = make_uint2(a.qbase[q] + g[u] - pre, pre + min(room, c[u]));
             }
             s_cnt[b] = pre;
             pre += c[u];
