@@ -101,7 +101,8 @@ def measured_ceilings(full: bool = False) -> dict:
     32-bit FMA lane-operations/s (independent chains); with ``full`` also LDS
     atomic adds/s (random and bank-distinct cells, 128 KiB array), relaxed
     device-scope atomic adds/s into random cells of 1, 8 and 64 MiB int32
-    grids, and device copy bandwidth (read + write bytes/s of a 1 GiB copy)."""
+    grids (random cells, and a wave at a time into 64 consecutive cells), and
+    device copy bandwidth (read + write bytes/s of a 1 GiB copy)."""
     key = "full" if full else "valu"
     if key in _CEILINGS:
         return _CEILINGS[key]
@@ -113,6 +114,8 @@ def measured_ceilings(full: bool = False) -> dict:
         out["lds_atomic_distinct_per_s"] = p.ceiling_lds_atomic(False)
         out["global_atomic_per_s"] = {f"{mib}MiB": p.ceiling_global_atomic(mib << 18)
                                       for mib in (1, 8, 64)}
+        out["global_atomic_contiguous_per_s"] = {
+            f"{mib}MiB": p.ceiling_global_atomic(mib << 18, contiguous=True) for mib in (1, 64)}
         out["copy_gb_s"] = p.ceiling_copy() / 1e9
     _CEILINGS[key] = out
     return out

@@ -69,14 +69,21 @@ __global__ __launch_bounds__(kLdsThreads) void k_ceil_lds(uint32_t* out, int ite
     out[(int64_t)blockIdx.x * kLdsThreads + threadIdx.x] = t;
 }
 
+// kContiguous: the 64 lanes of a wave add to 64 consecutive cells at a random
+// 64-cell-aligned base (one draw per wave and iteration); otherwise every lane
+// draws its own random cell.
+template <bool kContiguous>
 __global__ __launch_bounds__(256) void k_ceil_gatomic(int32_t* grid, uint32_t mask, int iters,
                                                       uint32_t seed)
 {
-    uint32_t h = seed ^ ((uint32_t)(blockIdx.x * 256 + threadIdx.x) * 0x9E3779B9u);
+    const uint32_t id = kContiguous ? (blockIdx.x * 256 + threadIdx.x) >> 6
+                                    : blockIdx.x * 256 + threadIdx.x;
+    uint32_t h = seed ^ (id * 0x9E3779B9u);
     for (int i = 0; i < iters; ++i) {
         h = h * 1664525u + 1013904223u;
-        __hip_atomic_fetch_add(grid + ((h >> 4) & mask), 1, __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t c = kContiguous ? (((h >> 4) & mask & ~63u) | (threadIdx.x & 63u))
+                                       : ((h >> 4) & mask);
+        __hip_atomic_fetch_add(grid + c, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
@@ -178,13 +185,14 @@ RVP_API int rvp_ceil_lds_atomic(int blocks, int iters, int random, double* atomi
     return 0;
 }
 
-// Relaxed device-scope atomic adds per second into random cells of an int32
-// grid of `cells` entries (a power of two, at most 2^26): `blocks`
-// workgroups of 256 threads, `iters` adds per lane.  The grid's total is
-// checked.
-RVP_API int rvp_ceil_global_atomic(int64_t cells, int blocks, int iters, double* atomics_per_s)
+// Relaxed device-scope atomic adds per second into an int32 grid of `cells`
+// entries (a power of two, from 64 to 2^26): `blocks` workgroups of 256
+// threads, `iters` adds per lane, at random cells or (contiguous != 0) a wave
+// at a time into 64 consecutive cells.  The grid's total is checked.
+RVP_API int rvp_ceil_global_atomic(int64_t cells, int blocks, int iters, int contiguous,
+                                   double* atomics_per_s)
 {
-    if (cells <= 0 || cells > (int64_t(1) << 26) || (cells & (cells - 1)) || blocks <= 0 ||
+    if (cells < 64 || cells > (int64_t(1) << 26) || (cells & (cells - 1)) || blocks <= 0 ||
         iters <= 0 || !atomics_per_s)
         return -1;
     int32_t* grid = nullptr;
@@ -194,8 +202,12 @@ RVP_API int rvp_ceil_global_atomic(int64_t cells, int blocks, int iters, double*
     float ms = 0.0f;
     if (!rc)
         rc = timed([&] {
-            hipLaunchKernelGGL(k_ceil_gatomic, dim3(blocks), dim3(256), 0, 0, grid,
-                               (uint32_t)(cells - 1), iters, 777u);
+            if (contiguous)
+                hipLaunchKernelGGL(k_ceil_gatomic<true>, dim3(blocks), dim3(256), 0, 0, grid,
+                                   (uint32_t)(cells - 1), iters, 777u);
+            else
+                hipLaunchKernelGGL(k_ceil_gatomic<false>, dim3(blocks), dim3(256), 0, 0, grid,
+                                   (uint32_t)(cells - 1), iters, 777u);
         }, &ms);
     std::vector<int32_t> h(rc ? 0 : (size_t)cells);
     if (!rc && hipMemcpy(h.data(), grid, (size_t)cells * sizeof(int32_t),

@@ -666,7 +666,7 @@ class Probe:
         d = ct.POINTER(ct.c_double)
         L.rvp_ceil_valu.argtypes = [i32, i32, d]
         L.rvp_ceil_lds_atomic.argtypes = [i32, i32, i32, d]
-        L.rvp_ceil_global_atomic.argtypes = [i64, i32, i32, d]
+        L.rvp_ceil_global_atomic.argtypes = [i64, i32, i32, i32, d]
         L.rvp_ceil_copy.argtypes = [i64, d]
         for f in (L.rvp_recip, L.rvp_div_sqrt, L.rvp_basis, L.rvp_cells, L.rvp_decode,
                   L.rvp_residual, L.rvp_ceil_valu, L.rvp_ceil_lds_atomic,
@@ -729,10 +729,12 @@ class Probe:
         """LDS atomic adds per second (random or bank-distinct cells)."""
         return self._rate(self.lib.rvp_ceil_lds_atomic, blocks, iters, int(random))
 
-    def ceiling_global_atomic(self, cells: int, blocks: int = 4096, iters: int = 256) -> float:
-        """Relaxed device-scope atomic adds per second into random cells of an
-        int32 grid of ``cells`` entries (a power of two)."""
-        return self._rate(self.lib.rvp_ceil_global_atomic, cells, blocks, iters)
+    def ceiling_global_atomic(self, cells: int, blocks: int = 4096, iters: int = 256,
+                              contiguous: bool = False) -> float:
+        """Relaxed device-scope atomic adds per second into an int32 grid of
+        ``cells`` entries (a power of two): random cells, or each wave into 64
+        consecutive cells."""
+        return self._rate(self.lib.rvp_ceil_global_atomic, cells, blocks, iters, int(contiguous))
 
     def ceiling_copy(self, nbytes: int = 1 << 30) -> float:
         """Bytes read plus written per second by a device copy."""

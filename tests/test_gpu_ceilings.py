@@ -33,9 +33,10 @@ def test_lds_atomic_ceiling(probe, random):
     assert r > 1e11, r
 
 
+@pytest.mark.parametrize("contiguous", [False, True])
 @pytest.mark.parametrize("mib", [1, 64])
-def test_global_atomic_ceiling(probe, mib):
-    r = probe.ceiling_global_atomic(mib << 18, blocks=1024, iters=64)
+def test_global_atomic_ceiling(probe, mib, contiguous):
+    r = probe.ceiling_global_atomic(mib << 18, blocks=1024, iters=64, contiguous=contiguous)
     assert r > 1e9, r
 
 
