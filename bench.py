@@ -574,6 +574,46 @@ def refine_leg(solver, x, y, q, mask, w, inst, reps: int = 5) -> dict:
             "q": qr, "e_R_deg": datagen.rotation_error_deg(qr, inst.q_gt)}
 
 
+def async_leg(w, inst, x, y, q_sync, cnt_sync, steps: int) -> dict:
+    """The same solve enqueued without waiting (rot_vote_solve_async): ms per
+    solve for `steps` solves back to back on one stream with one wait at the
+    end, and for `steps` replays of one solve captured in a HIP graph.  Uses a
+    handle of its own (no timing events); the last result of each mode is
+    checked against the synchronous solve."""
+    import torch
+
+    from paper_2506_11547_amd import rotvote
+    stream = torch.cuda.Stream()
+    res = torch.zeros(rotvote.RESULT_BYTES, dtype=torch.uint8, device=x.device)
+    mask = torch.empty(inst.n, dtype=torch.bool, device=x.device)
+    out = {"solves": steps}
+    with rotvote.Solver(device=0, max_n=inst.n, max_grid=w.grid, topk=w.topk,
+                        samples_per_circle=w.samples, stream=stream) as s:
+        s.solve_async(x, y, w.grid, w.eps_deg, result=res, mask=mask)   # sample table
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            s.solve_async(x, y, w.grid, w.eps_deg, result=res, mask=mask)
+        stream.synchronize()
+        out["ms_per_solve"] = (time.perf_counter() - t0) / steps * 1e3
+        r = rotvote.decode_result(res)
+        out["identical"] = r["q"] == list(q_sync) and r["count"] == cnt_sync
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=stream, capture_error_mode="relaxed"):
+            s.solve_async(x, y, w.grid, w.eps_deg, result=res, mask=mask)
+        res.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            g.replay()
+        torch.cuda.synchronize()
+        out["graph_ms_per_solve"] = (time.perf_counter() - t0) / steps * 1e3
+        r = rotvote.decode_result(res)
+        out["graph_identical"] = r["q"] == list(q_sync) and r["count"] == cnt_sync
+        del g
+    return out
+
+
 def main():
     args = parse()
     if args.ceilings:
@@ -634,6 +674,7 @@ def main():
     top = solver.topk()
     refine = refine_leg(solver, x, y, q, mask, w, inst)
     solver.close()
+    pipelined = async_leg(w, inst, x, y, q, cnt, args.steps)
 
     steps = args.steps
     samples = inst.n * w.samples
@@ -669,6 +710,7 @@ def main():
         "result": {"q": q, "inliers": cnt, "e_R_deg": datagen.rotation_error_deg(q, inst.q_gt),
                    "winner": top["winner"], "true_inliers": int(inst.inlier.sum())},
         "refine": refine,
+        "async": pipelined,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, inst, args.cpu_sample)

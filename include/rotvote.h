@@ -128,6 +128,35 @@ rv_status rot_vote_solve(rv_handle *h, const float *x, const float *y, int64_t n
                          float eps_rad, float q_out[4], int64_t *inlier_count,
                          uint8_t *inlier_mask);
 
+/* Result of rot_vote_solve_async, written to device memory (32 bytes,
+ * 8-byte aligned). */
+typedef struct rv_result {
+    float q[4];     /* the winning cell centre as a unit quaternion (w, x, y, z) */
+    int64_t count;  /* inlier count of q */
+    int32_t winner; /* index of the winning candidate; -1 when nothing voted */
+    int32_t n_cand; /* candidates rescored (at most K) */
+} rv_result;
+
+/* rot_vote_solve without waiting (the same Alg. 1 vote and exact rescoring):
+ * enqueues the whole solve on the handle's stream and returns.
+ *   result_device  device memory, one rv_result, 8-byte aligned.
+ *   inlier_mask    device uint8[n], as for rot_vote_solve.
+ * Both are written when the stream reaches them; the caller synchronises the
+ * stream (or waits on an event recorded after the call) before reading them,
+ * and keeps x, y, the mask and result_device alive until then.  The results
+ * are bit for bit those of rot_vote_solve on the same input.  Calls on one
+ * handle share its scratch and are ordered by its stream; do not rebind the
+ * stream while solves are in flight.  No host synchronisation and no
+ * allocation take place, except on the first solve at a new J (see
+ * rot_vote_get_plan), which synchronises the stream to upload the sample
+ * table: solve once at each J before capturing calls into a HIP graph.
+ * Argument errors are reported at once (nothing is enqueued); device errors
+ * surface at the caller's next synchronisation.  rot_vote_get_topk and
+ * rot_vote_get_histogram synchronise the stream and then describe this solve. */
+rv_status rot_vote_solve_async(rv_handle *h, const float *x, const float *y, int64_t n,
+                               int32_t grid, float eps_rad, rv_result *result_device,
+                               uint8_t *inlier_mask);
+
 /* Vote strategy chosen by measurement: times `reps` solves of this input
  * (after one untimed solve) with each strategy the handle supports at this
  * grid and remembers the faster one for the grid; later solves at that grid

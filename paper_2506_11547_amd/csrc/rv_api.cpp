@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cstddef>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -19,8 +20,9 @@
 namespace {
 
 constexpr int kStages = RV_NUM_STAGES;
-// Below this grid the whole int32 grid (<= 1.4 MiB at 72^3) sits in every
-// XCD's L2 and run-coalesced atomics straight into it beat binning.
+// Below this grid (<= 1.4 MiB of int32 cells at 72^3) the global-atomic vote
+// (one kernel, no queues) measured faster than binning: the solves there are
+// small enough that binning's extra stages cost more than its atomics save.
 constexpr int kBrickMinGrid = 72;
 // Batch queue capacities: a brick's share of the instance's expected runs,
 // times this factor (the heaviest brick of an instance with half inliers
@@ -36,6 +38,13 @@ int64_t runs_per_circle(int G, int J)
 }
 
 std::string g_create_error;  // reason of the last failed create (NULL handle)
+
+// rot_vote_solve_async copies the internal result record to the caller's
+// rv_result: the two layouts are one.
+static_assert(sizeof(rv_result) == sizeof(rv::Result), "result layout");
+static_assert(offsetof(rv_result, count) == offsetof(rv::Result, count), "result layout");
+static_assert(offsetof(rv_result, winner) == offsetof(rv::Result, winner), "result layout");
+static_assert(offsetof(rv_result, n_cand) == offsetof(rv::Result, n_cand), "result layout");
 
 }  // namespace
 
@@ -57,6 +66,7 @@ struct rv_handle {
     uint32_t* d_cand_inl = nullptr;     // 64
     rv::Result* d_result = nullptr;
     rv::Result* h_result = nullptr;     // pinned
+    rv::Result* d_empty = nullptr;      // the result of a solve without votes (q = 1, count 0)
     float2* h_table = nullptr;          // pinned staging for the table
     int32_t table_J = -1;               // J the device table holds
 
@@ -118,6 +128,7 @@ struct rv_handle {
     int32_t last_ncand = 0;
     int32_t last_winner = -1;
     int64_t last_count = 0;
+    bool last_async = false;             // the fields above are read back on demand
     // last batch
     bool batched = false;
     int32_t last_B = 0;
@@ -189,6 +200,7 @@ void release(rv_handle* h)
     (void)hipFree(h->d_cand_idx);
     (void)hipFree(h->d_cand_inl);
     (void)hipFree(h->d_result);
+    (void)hipFree(h->d_empty);
     (void)hipFree(h->bin.pool);
     (void)hipFree(h->bin.fill);
     (void)hipFree(h->bin.qbase);
@@ -338,8 +350,16 @@ RV_API rv_status rot_vote_create(rv_handle** out, const rv_config* cfg)
         (e = dev_alloc(h, &h->d_cand_votes, 64 * sizeof(int32_t))) != hipSuccess ||
         (e = dev_alloc(h, &h->d_cand_idx, 64 * sizeof(int32_t))) != hipSuccess ||
         (e = dev_alloc(h, &h->d_cand_inl, 64 * sizeof(uint32_t))) != hipSuccess ||
-        (e = dev_alloc(h, &h->d_result, sizeof(rv::Result))) != hipSuccess)
+        (e = dev_alloc(h, &h->d_result, sizeof(rv::Result))) != hipSuccess ||
+        (e = dev_alloc(h, &h->d_empty, sizeof(rv::Result))) != hipSuccess)
         return bail(e, "candidate buffers");
+    {
+        rv::Result empty{};
+        empty.q[0] = 1.0f;
+        empty.winner = -1;
+        if ((e = hipMemcpy(h->d_empty, &empty, sizeof(empty), hipMemcpyHostToDevice)) != hipSuccess)
+            return bail(e, "empty result");
+    }
     if ((e = hipHostMalloc(&h->h_result, sizeof(rv::Result), hipHostMallocDefault)) != hipSuccess)
         return bail(e, "pinned result");
     if ((e = hipHostMalloc(&h->h_table, (size_t)h->max_J * sizeof(float2), hipHostMallocDefault)) !=
@@ -542,6 +562,7 @@ rv_status vote_candidates(rv_handle* h, const float* x, const float* y, int64_t 
     const bool tm = h->timing;
     const bool brick = strategy == RV_VOTE_BRICK;
     h->solved = true;
+    h->last_async = false;
     h->last_grid = grid;
     h->last_J = J;
     h->last_strategy = strategy;
@@ -633,6 +654,50 @@ RV_API rv_status rot_vote_solve(rv_handle* h, const float* x, const float* y, in
     h->last_ncand = r.n_cand;
     h->last_winner = r.winner;
     h->last_count = r.count;
+    return RV_OK;
+}
+
+RV_API rv_status rot_vote_solve_async(rv_handle* h, const float* x, const float* y, int64_t n,
+                                      int32_t grid, float eps_rad, rv_result* result_device,
+                                      uint8_t* inlier_mask)
+{
+    if (!h)
+        return RV_EINVAL;
+    h->err.clear();
+    if (!result_device || !is_device_memory(result_device) ||
+        reinterpret_cast<uintptr_t>(result_device) % alignof(rv_result) != 0)
+        return fail(h, RV_EINVAL,
+                    "rot_vote_solve_async: result_device must be aligned device memory");
+    int32_t J = 0;
+    if (rv_status st = check_solve(h, "rot_vote_solve_async", x, y, n, grid, eps_rad, inlier_mask,
+                                   &J))
+        return st;
+    RV_HIP(h, hipSetDevice(h->device), "hipSetDevice");
+    hipStream_t s = h->stream;
+    if (rv_status st = vote_candidates(h, x, y, n, grid, J, "rot_vote_solve_async"))
+        return st;
+    const rv::Result* src = h->d_empty;
+    h->events_recorded = false;
+    if (n > 0) {
+        const bool tm = h->timing;
+        const float T2 = residual_bound(eps_rad);
+        const rv::Candidates c = candidates(h);
+        RV_HIP(h, rv::launch_rescore(x, y, n, T2, c, s), "rescore");
+        if (tm)
+            RV_HIP(h, hipEventRecord(h->ev[5], s), "event");
+        RV_HIP(h, rv::launch_mask(x, y, n, T2, c, inlier_mask, s), "mask");
+        if (tm)
+            RV_HIP(h, hipEventRecord(h->ev[6], s), "event");
+        h->events_recorded = tm;
+        src = h->d_result;
+    }
+    RV_HIP(h, hipMemcpyAsync(result_device, src, sizeof(rv::Result), hipMemcpyDeviceToDevice, s),
+           "result copy");
+    if (n > 0) {
+        h->last_async = true;
+    } else {
+        record_empty(h);
+    }
     return RV_OK;
 }
 
@@ -1206,6 +1271,17 @@ RV_API rv_status rot_vote_get_topk(rv_handle* h, int32_t* n_cand, int32_t* votes
         return fail(h, RV_EINVAL, "rot_vote_get_topk: no solve yet");
     if (!n_cand || !votes || !cell_idx || !inliers || !winner)
         return fail(h, RV_EINVAL, "rot_vote_get_topk: NULL argument");
+    if (h->last_async) {
+        RV_HIP(h, hipSetDevice(h->device), "hipSetDevice");
+        RV_HIP(h, hipMemcpyAsync(h->h_result, h->d_result, sizeof(rv::Result),
+                                 hipMemcpyDeviceToHost, h->stream),
+               "result readback");
+        RV_HIP(h, hipStreamSynchronize(h->stream), "sync");
+        h->last_ncand = h->h_result->n_cand;
+        h->last_winner = h->h_result->winner;
+        h->last_count = h->h_result->count;
+        h->last_async = false;
+    }
     const int m = h->last_ncand;
     if (m > 0) {
         int32_t v[64], ix[64];
@@ -1254,7 +1330,9 @@ RV_API rv_status rot_vote_get_timings(rv_handle* h, float* ms)
         return fail(h, RV_EINVAL, "rot_vote_get_timings: NULL argument");
     if (!h->timing || !h->events_recorded)
         return fail(h, RV_EINVAL, "rot_vote_get_timings: no timed solve (create with RV_FLAG_TIMING)");
-    // stages: prepare, vote, reduce, top-K, rescore, mask
+    // stages: prepare, vote, reduce, top-K, rescore, mask (an asynchronous
+    // solve may still be running)
+    RV_HIP(h, hipEventSynchronize(h->ev[kStages]), "hipEventSynchronize");
     for (int k = 0; k < kStages; ++k)
         RV_HIP(h, hipEventElapsedTime(&ms[k], h->ev[k], h->ev[k + 1]), "hipEventElapsedTime");
     return RV_OK;

@@ -36,7 +36,7 @@ STAGE_NAMES = ("prepare", "vote", "reduce", "topk", "rescore", "mask")
 
 # Names the C header declares; the CPU test suite checks the library exports each.
 EXPORTS = ("rot_vote_default_config", "rot_vote_create", "rot_vote_destroy",
-           "rot_vote_last_error", "rot_vote_set_stream", "rot_vote_solve",
+           "rot_vote_last_error", "rot_vote_set_stream", "rot_vote_solve", "rot_vote_solve_async",
            "rot_vote_get_histogram", "rot_vote_get_topk", "rot_vote_get_plan",
            "rot_vote_get_timings", "rot_vote_solve_batch", "rot_vote_get_batch_histogram",
            "rot_vote_get_batch_topk", "rot_vote_refine", "rot_vote_solve_multi",
@@ -119,6 +119,8 @@ def load_library(path: Path | str = LIB_PATH) -> ct.CDLL:
     L.rot_vote_solve.argtypes = [vp, vp, vp, i64, i32, f32, ct.POINTER(f32 * 4),
                                  ct.POINTER(i64), vp]
     L.rot_vote_solve.restype = i32
+    L.rot_vote_solve_async.argtypes = [vp, vp, vp, i64, i32, f32, vp, vp]
+    L.rot_vote_solve_async.restype = i32
     L.rot_vote_get_histogram.argtypes = [vp, vp]
     L.rot_vote_get_histogram.restype = i32
     L.rot_vote_get_topk.argtypes = [vp, ct.POINTER(i32), ct.POINTER(i32 * MAX_TOPK),
@@ -190,6 +192,23 @@ def _points(x: torch.Tensor, y: torch.Tensor):
 def _offsets(offsets) -> np.ndarray:
     """Batch offsets as a contiguous int64 array (no copy when they already are one)."""
     return np.ascontiguousarray(offsets, dtype=np.int64).reshape(-1)
+
+
+RESULT_BYTES = 32  # sizeof(rv_result): float q[4], int64 count, int32 winner, int32 n_cand
+
+
+def decode_result(result) -> dict:
+    """Reads an rv_result (a uint8 tensor of RESULT_BYTES, device or host).
+    Synchronise the stream the solve ran on first: the copy to the host is
+    ordered only after torch's current stream."""
+    import numpy as np
+    b = result.detach().cpu().numpy().astype(np.uint8, copy=False).tobytes()
+    if len(b) != RESULT_BYTES:
+        raise ValueError(f"an rv_result is {RESULT_BYTES} bytes")
+    q = np.frombuffer(b, np.float32, 4, 0)
+    count = int(np.frombuffer(b, np.int64, 1, 16)[0])
+    winner, n_cand = (int(v) for v in np.frombuffer(b, np.int32, 2, 24))
+    return {"q": [float(v) for v in q], "count": count, "winner": winner, "n_cand": n_cand}
 
 
 def eps_deg_to_rad(eps_deg: float) -> float:
@@ -290,6 +309,38 @@ class Solver:
         q, cnt = self.solve_raw(x.data_ptr(), y.data_ptr(), n, grid, eps_deg_to_rad(eps_deg),
                                 mask.data_ptr() if n else 0)
         return q, cnt, mask
+
+    def solve_async_raw(self, x_ptr: int, y_ptr: int, n: int, grid: int, eps_rad: float,
+                        result_ptr: int, mask_ptr: int):
+        """Direct C-ABI call: enqueues the solve on the handle's stream and
+        returns at once; the rv_result at result_ptr (device) is written later."""
+        self._check(self._lib.rot_vote_solve_async(self._h, ct.c_void_p(x_ptr), ct.c_void_p(y_ptr),
+                                                   n, grid, ct.c_float(eps_rad),
+                                                   ct.c_void_p(result_ptr), ct.c_void_p(mask_ptr)))
+        self._last_grid = grid
+
+    def solve_async(self, x: torch.Tensor, y: torch.Tensor, grid: int, eps_deg: float,
+                    result: torch.Tensor | None = None, mask: torch.Tensor | None = None):
+        """Enqueues a solve on the handle's stream without waiting.  Returns
+        (result, mask): ``result`` is a device uint8 tensor of RESULT_BYTES
+        holding an rv_result once the stream has run (``decode_result``)."""
+        for t, nm in ((x, "x"), (y, "y")):
+            if t.dtype != torch.float32 or t.dim() != 2 or t.shape[0] != 3 or not t.is_cuda:
+                raise ValueError(f"{nm} must be a float32 [3, N] device tensor")
+            if not t.is_contiguous():
+                raise ValueError(f"{nm} must be contiguous (the call does not wait for a copy)")
+        if x.shape != y.shape:
+            raise ValueError("x and y must have the same shape")
+        n = x.shape[1]
+        if result is None:
+            result = torch.empty(RESULT_BYTES, dtype=torch.uint8, device=x.device)
+        if result.dtype != torch.uint8 or result.numel() != RESULT_BYTES or not result.is_cuda:
+            raise ValueError(f"result must be a device uint8 tensor of {RESULT_BYTES} bytes")
+        if mask is None:
+            mask = torch.empty(n, dtype=torch.bool, device=x.device)
+        self.solve_async_raw(x.data_ptr(), y.data_ptr(), n, grid, eps_deg_to_rad(eps_deg),
+                             result.data_ptr(), mask.data_ptr() if n else 0)
+        return result, mask
 
     def tune(self, x: torch.Tensor, y: torch.Tensor, grid: int, eps_deg: float, reps: int = 3):
         """Measures both vote strategies on this input and fixes the faster one
