@@ -1,4 +1,4 @@
-// Brick-binned vote for grids up to 256^3 (the grid is far larger than LDS and
+// Brick-binned vote for grids up to 384^3 (the grid is far larger than LDS and
 // L2, so scattered atomics into it are bound by line traffic).
 //
 // The G^3 grid is cut into 32^3-cell bricks (128 KiB of int32, one brick per
@@ -7,16 +7,18 @@
 // accumulates each brick's queue in LDS and writes the finished brick out once,
 // keeping its K best cells for the top-K stage.
 //
-//   k_bin_estimate  every 32nd circle, runs counted per brick (queue sizing)
+//   k_bin_estimate  every 64th circle, runs counted per brick (queue sizing)
 //   k_bin_plan      queue capacities and offsets in the run pool
 //   k_vote_bin      all circles: sample, bin (LDS staging), append to queues
 //   k_brick_accum   per brick: LDS histogram, write-out, sorted list of its K best
 //
-// Queues are kept per XCD (blockIdx % 8), so the reservation atomics and the
-// partial-line writes of a queue tail stay in one XCD's L2.  A queue that
+// Queues are kept per XCD (blockIdx % 8: workgroups are dispatched to the
+// XCDs in turn), so a queue's tail is appended to from one XCD.  A queue that
 // fills up sends its excess runs straight to a zeroed overflow grid with
 // atomics, and the brick's accumulation adds (and re-zeroes) those cells: the
 // capacities only change speed, never the histogram.
+#include <algorithm>
+
 #include "rv_device.h"
 #include "rv_internal.h"
 #include "rv_topk.h"
@@ -93,16 +95,15 @@ __device__ __forceinline__ uint32_t local_of(uint32_t pc)
 // ------------------------------------------------------------- estimate
 
 // Runs per brick of every kEstimateStride-th correspondence.  One wave per
-// (64 sampled correspondences, chunk of kEstChunk samples), so the table
-// index stays wave-uniform and the work spreads over the whole GPU.
-constexpr int kEstChunk = 256;
+// (64 sampled correspondences, chunk of `chunk` samples, a multiple of 8), so
+// the table index stays wave-uniform and the work spreads over the whole GPU.
 
 template <bool kWide>
 __global__ __launch_bounds__(256) void k_bin_estimate(const float* __restrict__ x,
                                                       const float* __restrict__ y, int64_t n,
                                                       float H, float gm, int J,
                                                       const float2* __restrict__ table, int nba,
-                                                      int ngroups, int nwaves,
+                                                      int chunk, int ngroups, int nwaves,
                                                       uint32_t* __restrict__ est)
 {
     __shared__ uint32_t s_est[Pack<kWide>::kMaxBricksHere];
@@ -118,7 +119,7 @@ __global__ __launch_bounds__(256) void k_bin_estimate(const float* __restrict__ 
         Quat u, v;
         const bool ok = load_circle(x, y, n, i, u, v);
         uint32_t cur = 0xFFFFFFFFu;
-        for_samples<true>(u, v, table, c * kEstChunk, min(J, (c + 1) * kEstChunk), H, gm,
+        for_samples<true>(u, v, table, c * chunk, min(J, (c + 1) * chunk), H, gm,
                           [&](const Cell& cell, int) {
                               const uint32_t pc = packed_coords<kWide>(cell);
                               if (ok && pc != cur)
@@ -142,7 +143,7 @@ constexpr int kPlanThreads = kMaxBricksAll / 2;  // two bricks per thread
 
 __global__ __launch_bounds__(kPlanThreads) void k_bin_plan(BinArgs a, int nb)
 {
-    __shared__ uint64_t s_scan[kPlanThreads];
+    __shared__ uint64_t s_scan[kPlanThreads / kWave];
     __shared__ uint64_t s_total;
     __shared__ uint64_t s_sort[kMaxBricksAll];
     const int t = threadIdx.x;
@@ -157,19 +158,25 @@ __global__ __launch_bounds__(kPlanThreads) void k_bin_plan(BinArgs a, int nb)
         }
     }
     // exclusive offsets of the bricks within one queue set: a scan over pairs
+    // (shuffles within each wave, then over the wave totals)
+    const int lane = t & (kWave - 1), wave = t / kWave;
     auto scan = [&](uint64_t& excl0, uint64_t& excl1) {
-        s_scan[t] = cap[0] + cap[1];
-        __syncthreads();
-        for (int off = 1; off < kPlanThreads; off <<= 1) {  // inclusive (Hillis-Steele)
-            const uint64_t v = t >= off ? s_scan[t - off] : 0;
-            __syncthreads();
-            s_scan[t] += v;
-            __syncthreads();
+        const uint64_t v = cap[0] + cap[1];
+        uint64_t incl = v;
+#pragma unroll
+        for (int off = 1; off < kWave; off <<= 1) {
+            const uint64_t w = __shfl_up(incl, off);
+            incl += lane >= off ? w : 0ull;
         }
-        if (t == kPlanThreads - 1)
-            s_total = s_scan[t];
+        if (lane == kWave - 1)
+            s_scan[wave] = incl;
         __syncthreads();
-        excl0 = s_scan[t] - cap[0] - cap[1];
+        for (int w = 0; w < wave; ++w)
+            incl += s_scan[w];
+        if (t == kPlanThreads - 1)
+            s_total = incl;
+        __syncthreads();
+        excl0 = incl - v;
         excl1 = excl0 + cap[0];
     };
     uint64_t excl0, excl1;
@@ -184,18 +191,24 @@ __global__ __launch_bounds__(kPlanThreads) void k_bin_plan(BinArgs a, int nb)
         scan(excl0, excl1);
     }
     // accumulation order: heaviest bricks first (bitonic sort of cap << 16 | b,
-    // descending, two elements per thread)
+    // descending, two elements per thread, over the next power of two >= nb;
+    // the padding is 0 and sorts last)
     s_sort[b0] = b0 < nb ? ((cap[0] << 16) | (uint64_t)b0) : 0ull;
     s_sort[b1] = b1 < nb ? ((cap[1] << 16) | (uint64_t)b1) : 0ull;
     __syncthreads();
-    for (int k = 2; k <= kMaxBricksAll; k <<= 1) {
+    int np = 2;
+    while (np < nb)
+        np <<= 1;
+    for (int k = 2; k <= np; k <<= 1) {
         for (int j = k >> 1; j > 0; j >>= 1) {
-            const int i = 2 * t - (t & (j - 1));  // the lower index of this thread's pair
-            const uint64_t p = s_sort[i], q = s_sort[i + j];
-            const bool desc = (i & k) == 0;
-            if (desc ? (p < q) : (p > q)) {
-                s_sort[i] = q;
-                s_sort[i + j] = p;
+            if (2 * t < np) {
+                const int i = 2 * t - (t & (j - 1));  // the lower index of this thread's pair
+                const uint64_t p = s_sort[i], q = s_sort[i + j];
+                const bool desc = (i & k) == 0;
+                if (desc ? (p < q) : (p > q)) {
+                    s_sort[i] = q;
+                    s_sort[i + j] = p;
+                }
             }
             __syncthreads();
         }
@@ -220,9 +233,9 @@ __global__ __launch_bounds__(kPlanThreads) void k_bin_plan(BinArgs a, int nb)
 // ------------------------------------------------------------ vote + bin
 
 // Staged runs: cell packed one byte per axis, run length in the top byte.
-// Flush: each run is rewritten as brick << 23 | length << 15 | local cell,
-// counted per brick, one reservation atomic per brick, then written to its
-// queue slot (or, past the queue's capacity, added to the overflow grid).
+// Flush: runs counted per brick, one reservation atomic per brick, then each
+// written to its queue slot as brick-local cell | length << 15 (or, past the
+// queue's capacity, added to the overflow grid).
 template <int kLog, bool kWide>
 __device__ __forceinline__ void bin_flush(uint32_t (*stage)[Pack<kWide>::kStageCap], uint32_t my,
                                           uint32_t* s_cnt, uint2* s_dst, int wave, int lane, int nb,
@@ -680,16 +693,23 @@ hipError_t launch_bin_prepare(const float* x, const float* y, int64_t n, int G, 
     if (n > 0) {
         const int64_t nsamp = (n + kEstimateStride - 1) / kEstimateStride;
         const int64_t ngroups = (nsamp + kWave - 1) / kWave;
-        const int64_t nchunks = (J + kEstChunk - 1) / kEstChunk;
+        // chunks of whole table rows (8 samples) for about 4096 waves
+        const int64_t rows = (J + 7) / 8;
+        const int64_t want = (4096 + ngroups - 1) / ngroups;
+        const int64_t nch = std::min<int64_t>(std::max<int64_t>(want, 1), rows);
+        const int chunk = (int)(((rows + nch - 1) / nch) * 8);
+        const int64_t nchunks = (J + chunk - 1) / chunk;
         const int64_t nwaves = ngroups * nchunks;
         if (nwaves > (int64_t)INT32_MAX - 4)
             return hipErrorInvalidValue;
         if (wide)
             hipLaunchKernelGGL(k_bin_estimate<true>, dim3((unsigned)((nwaves + 3) / 4)), dim3(256),
-                               0, s, x, y, n, H, gm, J, table, nba, (int)ngroups, (int)nwaves, a.est);
+                               0, s, x, y, n, H, gm, J, table, nba, chunk, (int)ngroups,
+                               (int)nwaves, a.est);
         else
             hipLaunchKernelGGL(k_bin_estimate<false>, dim3((unsigned)((nwaves + 3) / 4)), dim3(256),
-                               0, s, x, y, n, H, gm, J, table, nba, (int)ngroups, (int)nwaves, a.est);
+                               0, s, x, y, n, H, gm, J, table, nba, chunk, (int)ngroups,
+                               (int)nwaves, a.est);
         if (hipError_t e = hipGetLastError(); e != hipSuccess)
             return e;
     }

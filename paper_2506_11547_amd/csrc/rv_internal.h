@@ -28,7 +28,8 @@ constexpr int kTopkMaxBlocks = 2048;  // also the largest brick count
 
 hipError_t launch_fill(int32_t* p, int64_t count, int32_t value, hipStream_t s);
 
-// Global-atomic vote: one wave per (64 correspondences, sample chunk).
+// Global-atomic vote: one wave per (64 correspondences, sample chunk); chunk
+// <= 0 picks chunks (whole table rows) for about 8192 waves.
 hipError_t launch_vote_global(const float* x, const float* y, int64_t n, int G, int J,
                               const float2* table, int32_t* hist, int chunk, hipStream_t s);
 

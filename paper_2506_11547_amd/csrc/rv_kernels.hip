@@ -5,6 +5,8 @@
 //   top-K final (+ decode candidates) -> rescore (exact inlier counts) ->
 //   mask (winner, inlier mask, result record).
 // The vote is scatter/count work, not a dense contraction, so no MFMA is used.
+#include <algorithm>
+
 #include "rv_device.h"
 #include "rv_internal.h"
 #include "rv_topk.h"
@@ -88,11 +90,22 @@ hipError_t launch_vote_global(const float* x, const float* y, int64_t n, int G, 
 {
     if (n <= 0 || J <= 0)
         return hipSuccess;
-    if (chunk <= 0 || chunk >= J)
+    const int64_t ngroups = (n + kWave - 1) / kWave;
+    if (chunk <= 0) {
+        // Split J into chunks of whole table rows (8 samples) until there
+        // are about 8192 waves (8 per SIMD): a few thousand correspondences
+        // would otherwise keep a few CUs busy for the whole circle.  A cut
+        // only ends a run early; the counts are the same.
+        constexpr int64_t kTargetWaves = 8192;
+        const int64_t rows = (J + 7) / 8;
+        const int64_t want = (kTargetWaves + ngroups - 1) / ngroups;
+        const int64_t nch = std::min<int64_t>(std::max<int64_t>(want, 1), rows);
+        chunk = (int)(((rows + nch - 1) / nch) * 8);
+    }
+    if (chunk >= J)
         chunk = J;
     else
         chunk = (chunk + 7) & ~7;  // sample chunks start on table rows of 8
-    const int64_t ngroups = (n + kWave - 1) / kWave;
     const int64_t nchunks = (J + chunk - 1) / chunk;
     const int64_t nwaves = ngroups * nchunks;
     if (nwaves > (int64_t)INT32_MAX - 4)
@@ -155,7 +168,7 @@ __global__ __launch_bounds__(kTopkThreads) void k_topk_partial(const int32_t* __
 int topk_blocks(int64_t ncell)
 {
     const int64_t tiles = (ncell + 255) / 256;
-    const int64_t per_block = kTopkWaves * 4;  // about four tiles per wave
+    const int64_t per_block = kTopkWaves;  // about one tile per wave (small grids: more blocks)
     return (int)std::max<int64_t>(1, std::min<int64_t>(kTopkMaxBlocks, (tiles + per_block - 1) / per_block));
 }
 
