@@ -138,9 +138,12 @@ TRAFFIC_RECORDS = {"large": ROOT / "profiles" / "vote_bin__large_traffic.json",
                    "rigid": ROOT / "profiles" / "vote_bin__rigid_traffic.json"}
 
 
-def vote_kernel_name(grid: int, edge: int = 32) -> str:
-    """The vote kernel instance a brick solve launches: brick edge 2^5 or 2^4,
+def vote_kernel_name(grid: int, edge: int = 0) -> str:
+    """The vote kernel instance a brick solve launches: brick edge 2^5 or 2^4
+    (a single solve takes 16 up to grid 128, else 32; a batch its tuned edge),
     wide run layout above grid 256."""
+    if edge == 0:
+        edge = 16 if grid <= 128 else 32
     return f"rv::k_vote_bin<{5 if edge == 32 else 4}, {'true' if grid > 256 else 'false'}>"
 
 

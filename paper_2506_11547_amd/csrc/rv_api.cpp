@@ -568,23 +568,26 @@ rv_status vote_candidates(rv_handle* h, const float* x, const float* y, int64_t 
     h->last_strategy = strategy;
     if (tm)
         RV_HIP(h, hipEventRecord(h->ev[0], s), "event");
+    const int edge = rv::solve_edge_log2(grid);
     if (brick)
-        RV_HIP(h, rv::launch_bin_prepare(x, y, n, grid, J, h->d_table, h->bin, s), "brick plan");
+        RV_HIP(h, rv::launch_bin_prepare(x, y, n, grid, J, edge, h->d_table, h->bin, s),
+               "brick plan");
     else
         RV_HIP(h, rv::launch_fill(h->d_hist, ncell, 0, s), "clear grid");
     if (tm)
         RV_HIP(h, hipEventRecord(h->ev[1], s), "event");
     if (brick)
-        RV_HIP(h, rv::launch_bin_vote(x, y, n, grid, J, h->d_table, h->bin, s), "binned vote");
+        RV_HIP(h, rv::launch_bin_vote(x, y, n, grid, J, edge, h->d_table, h->bin, s),
+               "binned vote");
     else
         RV_HIP(h, rv::launch_vote_global(x, y, n, grid, J, h->d_table, h->d_hist, 0, s), "vote");
     if (tm)
         RV_HIP(h, hipEventRecord(h->ev[2], s), "event");
     int nlists;
     if (brick) {
-        RV_HIP(h, rv::launch_brick_accum(grid, h->K, 5, h->d_hist, h->d_partial, h->bin, s),
+        RV_HIP(h, rv::launch_brick_accum(grid, h->K, edge, h->d_hist, h->d_partial, h->bin, s),
                "brick accumulate");
-        const int nba = rv::brick_axis(grid, 5);
+        const int nba = rv::brick_axis(grid, edge);
         nlists = nba * nba * nba;
     } else {
         nlists = rv::topk_blocks(ncell);

@@ -98,7 +98,7 @@ __device__ __forceinline__ uint32_t local_of(uint32_t pc)
 // (64 sampled correspondences, chunk of `chunk` samples, a multiple of 8), so
 // the table index stays wave-uniform and the work spreads over the whole GPU.
 
-template <bool kWide>
+template <int kLog, bool kWide>
 __global__ __launch_bounds__(256) void k_bin_estimate(const float* __restrict__ x,
                                                       const float* __restrict__ y, int64_t n,
                                                       float H, float gm, int J,
@@ -123,7 +123,7 @@ __global__ __launch_bounds__(256) void k_bin_estimate(const float* __restrict__ 
                           [&](const Cell& cell, int) {
                               const uint32_t pc = packed_coords<kWide>(cell);
                               if (ok && pc != cur)
-                                  atomicAdd(&s_est[brick_of<5, kWide>(pc, nba)], 1u);
+                                  atomicAdd(&s_est[brick_of<kLog, kWide>(pc, nba)], 1u);
                               cur = pc;
                           });
     }
@@ -680,14 +680,18 @@ __global__ __launch_bounds__(Brick<kLog>::kThreads) void k_brick_accum(BinArgs a
 
 int brick_axis(int G, int edge_log2) { return (G + (1 << edge_log2) - 1) >> edge_log2; }
 
+int solve_edge_log2(int G) { return G <= 128 ? 4 : 5; }
+
 hipError_t launch_bin_prepare(const float* x, const float* y, int64_t n, int G, int J,
-                              const float2* table, const BinArgs& a, hipStream_t s)
+                              int edge_log2, const float2* table, const BinArgs& a, hipStream_t s)
 {
-    const int nba = brick_axis(G, 5);
-    const int nb = nba * nba * nba;
-    if (G > kMaxBrickGrid || nb > kMaxBricksAll)
-        return hipErrorInvalidValue;
     const bool wide = G > kNarrowGrid;
+    if ((edge_log2 != 4 && edge_log2 != 5) || (edge_log2 == 4 && wide))
+        return hipErrorInvalidValue;
+    const int nba = brick_axis(G, edge_log2);
+    const int nb = nba * nba * nba;
+    if (G > kMaxBrickGrid || nb > (wide ? kMaxBricksAll : kMaxBricks))
+        return hipErrorInvalidValue;
     const float H = (float)G * 0.5f;
     const float gm = (float)G - 0.5f;
     if (n > 0) {
@@ -702,14 +706,16 @@ hipError_t launch_bin_prepare(const float* x, const float* y, int64_t n, int G, 
         const int64_t nwaves = ngroups * nchunks;
         if (nwaves > (int64_t)INT32_MAX - 4)
             return hipErrorInvalidValue;
+        const dim3 grid((unsigned)((nwaves + 3) / 4));
         if (wide)
-            hipLaunchKernelGGL(k_bin_estimate<true>, dim3((unsigned)((nwaves + 3) / 4)), dim3(256),
-                               0, s, x, y, n, H, gm, J, table, nba, chunk, (int)ngroups,
-                               (int)nwaves, a.est);
+            hipLaunchKernelGGL((k_bin_estimate<5, true>), grid, dim3(256), 0, s, x, y, n, H, gm, J,
+                               table, nba, chunk, (int)ngroups, (int)nwaves, a.est);
+        else if (edge_log2 == 5)
+            hipLaunchKernelGGL((k_bin_estimate<5, false>), grid, dim3(256), 0, s, x, y, n, H, gm, J,
+                               table, nba, chunk, (int)ngroups, (int)nwaves, a.est);
         else
-            hipLaunchKernelGGL(k_bin_estimate<false>, dim3((unsigned)((nwaves + 3) / 4)), dim3(256),
-                               0, s, x, y, n, H, gm, J, table, nba, chunk, (int)ngroups,
-                               (int)nwaves, a.est);
+            hipLaunchKernelGGL((k_bin_estimate<4, false>), grid, dim3(256), 0, s, x, y, n, H, gm, J,
+                               table, nba, chunk, (int)ngroups, (int)nwaves, a.est);
         if (hipError_t e = hipGetLastError(); e != hipSuccess)
             return e;
     }
@@ -717,12 +723,14 @@ hipError_t launch_bin_prepare(const float* x, const float* y, int64_t n, int G, 
     return hipGetLastError();
 }
 
-hipError_t launch_bin_vote(const float* x, const float* y, int64_t n, int G, int J,
+hipError_t launch_bin_vote(const float* x, const float* y, int64_t n, int G, int J, int edge_log2,
                            const float2* table, const BinArgs& a, hipStream_t s)
 {
     if (n <= 0)
         return hipSuccess;
     const bool wide = G > kNarrowGrid;
+    if ((edge_log2 != 4 && edge_log2 != 5) || (edge_log2 == 4 && wide))
+        return hipErrorInvalidValue;
     const int threads = wide ? Pack<true>::kThreads : Pack<false>::kThreads;
     const int64_t ngroups = (n + threads - 1) / threads;
     // at least ~4 rounds of workgroups over the GPU (3 resident per CU, 1 wide),
@@ -741,10 +749,14 @@ hipError_t launch_bin_vote(const float* x, const float* y, int64_t n, int G, int
         hipLaunchKernelGGL((k_vote_bin<5, true>), dim3((unsigned)blocks), dim3(threads), 0, s, x,
                            y, n, G, (float)G * 0.5f, (float)G - 0.5f, J, chunk, (int)ngroups, table,
                            brick_axis(G, 5), a);
-    else
+    else if (edge_log2 == 5)
         hipLaunchKernelGGL((k_vote_bin<5, false>), dim3((unsigned)blocks), dim3(threads), 0, s, x,
                            y, n, G, (float)G * 0.5f, (float)G - 0.5f, J, chunk, (int)ngroups, table,
                            brick_axis(G, 5), a);
+    else
+        hipLaunchKernelGGL((k_vote_bin<4, false>), dim3((unsigned)blocks), dim3(threads), 0, s, x,
+                           y, n, G, (float)G * 0.5f, (float)G - 0.5f, J, chunk, (int)ngroups, table,
+                           brick_axis(G, 4), a);
     return hipGetLastError();
 }
 

@@ -75,14 +75,17 @@ struct BinArgs {
     int32_t batch;       // number of instances (0 for one solve)
 };
 
-// bricks per axis for bricks of 2^edge_log2 cells (5: 32, one solve; 4 or 5 in batches)
+// bricks per axis for bricks of 2^edge_log2 cells (4: 16, 5: 32)
 int brick_axis(int G, int edge_log2);
+// brick edge of a single solve at grid G: 16 up to G = 128 (at most 512
+// bricks, enough workgroups for the accumulation), else 32
+int solve_edge_log2(int G);
 // estimate + plan (queue capacities); then the binned vote; then per-brick
 // accumulation, which writes every cell of the grid and one sorted list per
-// brick that holds the brick's K best cells
+// brick that holds the brick's K best cells.  Edge 16 needs G <= 256.
 hipError_t launch_bin_prepare(const float* x, const float* y, int64_t n, int G, int J,
-                              const float2* table, const BinArgs& a, hipStream_t s);
-hipError_t launch_bin_vote(const float* x, const float* y, int64_t n, int G, int J,
+                              int edge_log2, const float2* table, const BinArgs& a, hipStream_t s);
+hipError_t launch_bin_vote(const float* x, const float* y, int64_t n, int G, int J, int edge_log2,
                            const float2* table, const BinArgs& a, hipStream_t s);
 hipError_t launch_brick_accum(int G, int K, int edge_log2, int32_t* grid, uint64_t* partial,
                               const BinArgs& a, hipStream_t s);
