@@ -151,3 +151,18 @@ def test_async_solve_in_a_graph(rv, G):
                 assert same_q(r["q"], q) and r["count"] == c, rep
                 assert torch.equal(mask, m), rep
         del g
+
+
+def test_async_stage_timings(rv):
+    """With timing events the stage times of an asynchronous solve are read
+    after waiting for its last event (no explicit synchronisation)."""
+    xh, yh = instance(20000, 5)
+    x, y = dev(xh), dev(yh)
+    with rv.Solver(max_n=20000, max_grid=128, topk=16, timing=True) as s:
+        q, c, _ = s.solve(x, y, 128, 1.0)
+        res, _ = s.solve_async(x, y, 128, 1.0)
+        t = s.timings()
+        assert set(t) == set(rv.STAGE_NAMES) and all(v >= 0.0 for v in t.values())
+        assert t["vote"] > 0.0
+        r = rv.decode_result(res)
+        assert same_q(r["q"], q) and r["count"] == c
