@@ -18,6 +18,7 @@
 // atomics, and the brick's accumulation adds (and re-zeroes) those cells: the
 // capacities only change speed, never the histogram.
 #include <algorithm>
+#include <atomic>
 
 #include "rv_device.h"
 #include "rv_internal.h"
@@ -540,145 +541,193 @@ __global__ __launch_bounds__(Brick<kLog>::kThreads) void k_brick_accum(BinArgs a
     __shared__ uint64_t lists[kAccumWaves][kWave];
     __shared__ uint32_t s_floor;
     const int nb = nba * nba * nba;
-    int inst, b;
-    if (a.batch) {
-        inst = blockIdx.x / nb;
-        b = blockIdx.x - inst * nb;
-    } else {
-        inst = 0;
-        b = (int)a.order[blockIdx.x];
-    }
-    const int qoff = inst * nb;
-    const int64_t gofs = (int64_t)inst * G * G * G;  // this instance's grid and overflow grid
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
-    const int bx = b % nba, by = (b / nba) % nba, bz = b / (nba * nba);
-
     uint4* acc4 = reinterpret_cast<uint4*>(acc);
-    for (int k = threadIdx.x; k < kBrickCells / 4; k += kAccumThreads)
-        acc4[k] = make_uint4(0u, 0u, 0u, 0u);
-    if (threadIdx.x == 0)
-        s_floor = 0u;
-    __syncthreads();
-
-    const uint32_t cap = a.cap[qoff + b];
-    // Software-pipelined queue reads: the next 8 KiB per wave are in flight
-    // while the current ones are added into LDS.  Queues start on 64-run
-    // boundaries and their capacity is a multiple of 64, so vector loads of
-    // 4 runs starting below the fill count stay inside the queue.
-    constexpr int kUnroll = 8;
-    constexpr uint32_t kStride = kAccumThreads * 4;
-    for (int xs = 0; xs < a.nsets; ++xs) {
-        const uint32_t cnt = min(a.fill[(int64_t)xs * a.qstride + qoff + b], cap);
-        const uint32_t* q = a.pool + a.qbase[(int64_t)xs * a.qstride + qoff + b];
-        if (cnt == 0)
-            continue;
-        // loads are unconditional (clamped to the queue's last vector) so the
-        // compiler can keep the next batch in flight across the LDS atomics
-        const uint32_t last = (cnt - 1u) & ~3u;
-        uint4 cur[kUnroll], nxt[kUnroll];
-        uint32_t k0 = threadIdx.x * 4;
-        auto load = [&](uint4 (&r)[kUnroll], uint32_t base) {
-#pragma unroll
-            for (int u = 0; u < kUnroll; ++u)
-                r[u] = *reinterpret_cast<const uint4*>(q + min(base + u * kStride, last));
-        };
-        load(cur, k0);
-        while (k0 < cnt) {
-            const uint32_t kn = k0 + kStride * kUnroll;
-            load(nxt, kn);
-#pragma unroll
-            for (int u = 0; u < kUnroll; ++u) {
-                const uint32_t k = k0 + u * kStride;
-                // entries past cnt add nothing
-                if (k < cnt) atomicAdd(&acc[cur[u].x & 0x7FFFu], cur[u].x >> 15);
-                if (k + 1 < cnt) atomicAdd(&acc[cur[u].y & 0x7FFFu], cur[u].y >> 15);
-                if (k + 2 < cnt) atomicAdd(&acc[cur[u].z & 0x7FFFu], cur[u].z >> 15);
-                if (k + 3 < cnt) atomicAdd(&acc[cur[u].w & 0x7FFFu], cur[u].w >> 15);
-            }
-#pragma unroll
-            for (int u = 0; u < kUnroll; ++u)
-                cur[u] = nxt[u];
-            k0 = kn;
+    // A workgroup takes one brick per round of gridDim.x (persistent when the
+    // launch has fewer workgroups than bricks); odd rounds run backwards, so
+    // with bricks ordered heaviest first the workgroup with the heaviest brick
+    // of one round gets the lightest of the next.
+    const int items = a.batch ? a.batch * nb : nb;
+    const int nwg = (int)gridDim.x;
+    int round = 0;
+    for (int base = 0; base < items; base += nwg, ++round) {
+        const int item = base + ((round & 1) ? nwg - 1 - (int)blockIdx.x : (int)blockIdx.x);
+        if (item >= items)
+            continue;  // the whole workgroup: the last round is partial
+        int inst, b;
+        if (a.batch) {
+            inst = item / nb;
+            b = item - inst * nb;
+        } else {
+            inst = 0;
+            b = (int)a.order[item];
         }
-    }
-    __syncthreads();
+        const int qoff = inst * nb;
+        const int64_t gofs = (int64_t)inst * G * G * G;  // this instance's grid and overflow grid
+        const int bx = b % nba, by = (b / nba) % nba, bz = b / (nba * nba);
 
-    // Pass 1: final counts (overflow runs added and written back to LDS), the
-    // grid, and each lane's largest count.
-    const bool overflowed = a.flags[qoff + b] != 0u;
-    const bool vec = (G % 4) == 0;
-    uint32_t lmax = 0;
-    for (int c = threadIdx.x * 4; c < kBrickCells; c += kAccumThreads * 4) {
-        const int lx = c & (kEdge - 1), ly = (c >> kLog) & (kEdge - 1), lz = c >> (2 * kLog);
-        const int gx = bx * kEdge + lx, gy = by * kEdge + ly, gz = bz * kEdge + lz;
-        uint32_t val[4] = {0u, 0u, 0u, 0u};
-        const bool row = gy < G && gz < G;
-        if (row) {
+        for (int k = threadIdx.x; k < kBrickCells / 4; k += kAccumThreads)
+            acc4[k] = make_uint4(0u, 0u, 0u, 0u);
+        if (threadIdx.x == 0)
+            s_floor = 0u;
+        __syncthreads();
+
+        const uint32_t cap = a.cap[qoff + b];
+        // Software-pipelined queue reads: the next 8 KiB per wave are in flight
+        // while the current ones are added into LDS.  Queues start on 64-run
+        // boundaries and their capacity is a multiple of 64, so vector loads of
+        // 4 runs starting below the fill count stay inside the queue.
+        constexpr int kUnroll = 8;
+        constexpr uint32_t kStride = kAccumThreads * 4;
+        for (int xs = 0; xs < a.nsets; ++xs) {
+            const uint32_t cnt = min(a.fill[(int64_t)xs * a.qstride + qoff + b], cap);
+            const uint32_t* q = a.pool + a.qbase[(int64_t)xs * a.qstride + qoff + b];
+            if (cnt == 0)
+                continue;
+            // loads are unconditional (clamped to the queue's last vector) so the
+            // compiler can keep the next batch in flight across the LDS atomics
+            const uint32_t last = (cnt - 1u) & ~3u;
+            uint4 cur[kUnroll], nxt[kUnroll];
+            uint32_t k0 = threadIdx.x * 4;
+            auto load = [&](uint4 (&r)[kUnroll], uint32_t base) {
+    #pragma unroll
+                for (int u = 0; u < kUnroll; ++u)
+                    r[u] = *reinterpret_cast<const uint4*>(q + min(base + u * kStride, last));
+            };
+            load(cur, k0);
+            while (k0 < cnt) {
+                const uint32_t kn = k0 + kStride * kUnroll;
+                load(nxt, kn);
+    #pragma unroll
+                for (int u = 0; u < kUnroll; ++u) {
+                    const uint32_t k = k0 + u * kStride;
+                    // entries past cnt add nothing
+                    if (k < cnt) atomicAdd(&acc[cur[u].x & 0x7FFFu], cur[u].x >> 15);
+                    if (k + 1 < cnt) atomicAdd(&acc[cur[u].y & 0x7FFFu], cur[u].y >> 15);
+                    if (k + 2 < cnt) atomicAdd(&acc[cur[u].z & 0x7FFFu], cur[u].z >> 15);
+                    if (k + 3 < cnt) atomicAdd(&acc[cur[u].w & 0x7FFFu], cur[u].w >> 15);
+                }
+    #pragma unroll
+                for (int u = 0; u < kUnroll; ++u)
+                    cur[u] = nxt[u];
+                k0 = kn;
+            }
+        }
+        __syncthreads();
+
+        // Pass 1: final counts (overflow runs added and written back to LDS), the
+        // grid, and each lane's largest count.
+        const bool overflowed = a.flags[qoff + b] != 0u;
+        const bool vec = (G % 4) == 0;
+        uint32_t lmax = 0;
+        for (int c = threadIdx.x * 4; c < kBrickCells; c += kAccumThreads * 4) {
+            const int lx = c & (kEdge - 1), ly = (c >> kLog) & (kEdge - 1), lz = c >> (2 * kLog);
+            const int gx = bx * kEdge + lx, gy = by * kEdge + ly, gz = bz * kEdge + lz;
+            uint32_t val[4] = {0u, 0u, 0u, 0u};
+            const bool row = gy < G && gz < G;
+            if (row) {
+                const uint4 v4 = acc4[c >> 2];
+                val[0] = v4.x; val[1] = v4.y; val[2] = v4.z; val[3] = v4.w;
+                const int64_t g0 = ((int64_t)gz * G + gy) * G + gx;
+                if (overflowed) {
+    #pragma unroll
+                    for (int s = 0; s < 4; ++s)
+                        if (gx + s < G) {
+                            val[s] += (uint32_t)a.ovf[gofs + g0 + s];
+                            a.ovf[gofs + g0 + s] = 0;
+                        }
+                }
+                if (overflowed)
+                    acc4[c >> 2] = make_uint4(val[0], val[1], val[2], val[3]);
+                if (grid == nullptr) {
+                    // batch without grids: only the brick's list leaves the CU
+                } else if (vec && gx + 3 < G) {
+                    *reinterpret_cast<int4*>(grid + gofs + g0) =
+                        make_int4((int)val[0], (int)val[1], (int)val[2], (int)val[3]);
+                } else {
+    #pragma unroll
+                    for (int s = 0; s < 4; ++s)
+                        if (gx + s < G)
+                            grid[gofs + g0 + s] = (int32_t)val[s];
+                }
+            }
+            // cells past the grid's edge hold 0 and cannot raise the maximum
+            lmax = max(lmax, max(max(val[0], val[1]), max(val[2], val[3])));
+        }
+        // A floor for the top K: the K largest lane maxima of one wave are counts
+        // of K distinct cells, so the brick's K-th largest count is at least the
+        // K-th largest lane maximum of every wave.  Cells below the floor cannot
+        // be among the brick's K best and skip the list.
+        const uint32_t kth = (uint32_t)lane_u64(wave_sort_desc((uint64_t)lmax, lane), K - 1);
+        if (lane == 0)
+            atomicMax(&s_floor, kth);
+        __syncthreads();
+        const uint32_t floor_k = max(s_floor, 1u);
+
+        // Pass 2: the sorted list of the brick's best cells at or above the floor.
+        uint64_t list = 0;
+        for (int c = threadIdx.x * 4; c < kBrickCells; c += kAccumThreads * 4) {
+            const int lx = c & (kEdge - 1), ly = (c >> kLog) & (kEdge - 1), lz = c >> (2 * kLog);
+            const int gx = bx * kEdge + lx, gy = by * kEdge + ly, gz = bz * kEdge + lz;
+            const bool row = gy < G && gz < G;
             const uint4 v4 = acc4[c >> 2];
-            val[0] = v4.x; val[1] = v4.y; val[2] = v4.z; val[3] = v4.w;
-            const int64_t g0 = ((int64_t)gz * G + gy) * G + gx;
-            if (overflowed) {
-#pragma unroll
-                for (int s = 0; s < 4; ++s)
-                    if (gx + s < G) {
-                        val[s] += (uint32_t)a.ovf[gofs + g0 + s];
-                        a.ovf[gofs + g0 + s] = 0;
-                    }
-            }
-            if (overflowed)
-                acc4[c >> 2] = make_uint4(val[0], val[1], val[2], val[3]);
-            if (grid == nullptr) {
-                // batch without grids: only the brick's list leaves the CU
-            } else if (vec && gx + 3 < G) {
-                *reinterpret_cast<int4*>(grid + gofs + g0) =
-                    make_int4((int)val[0], (int)val[1], (int)val[2], (int)val[3]);
-            } else {
-#pragma unroll
-                for (int s = 0; s < 4; ++s)
-                    if (gx + s < G)
-                        grid[gofs + g0 + s] = (int32_t)val[s];
+            const uint32_t val[4] = {v4.x, v4.y, v4.z, v4.w};
+            const bool hit = row && max(max(val[0], val[1]), max(val[2], val[3])) >= floor_k;
+            if (__ballot(hit) == 0)  // the common case: no cell of the wave's 256 qualifies
+                continue;
+            const uint32_t idx0 = (uint32_t)(((int64_t)gz * G + gy) * G + gx);
+    #pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const bool in = row && gx + s < G && val[s] >= floor_k;
+                list = wave_insert_top(list, in ? cell_key(val[s], idx0 + s) : 0ull, lane, K);
             }
         }
-        // cells past the grid's edge hold 0 and cannot raise the maximum
-        lmax = max(lmax, max(max(val[0], val[1]), max(val[2], val[3])));
+        list = block_merge<kAccumWaves>(list, lists, wave, lane);
+        if (wave == 0)
+            partial[(int64_t)(qoff + b) * kWave + lane] = list;
+        __syncthreads();  // the LDS is reused by the next brick
     }
-    // A floor for the top K: the K largest lane maxima of one wave are counts
-    // of K distinct cells, so the brick's K-th largest count is at least the
-    // K-th largest lane maximum of every wave.  Cells below the floor cannot
-    // be among the brick's K best and skip the list.
-    const uint32_t kth = (uint32_t)lane_u64(wave_sort_desc((uint64_t)lmax, lane), K - 1);
-    if (lane == 0)
-        atomicMax(&s_floor, kth);
-    __syncthreads();
-    const uint32_t floor_k = max(s_floor, 1u);
-
-    // Pass 2: the sorted list of the brick's best cells at or above the floor.
-    uint64_t list = 0;
-    for (int c = threadIdx.x * 4; c < kBrickCells; c += kAccumThreads * 4) {
-        const int lx = c & (kEdge - 1), ly = (c >> kLog) & (kEdge - 1), lz = c >> (2 * kLog);
-        const int gx = bx * kEdge + lx, gy = by * kEdge + ly, gz = bz * kEdge + lz;
-        const bool row = gy < G && gz < G;
-        const uint4 v4 = acc4[c >> 2];
-        const uint32_t val[4] = {v4.x, v4.y, v4.z, v4.w};
-        const bool hit = row && max(max(val[0], val[1]), max(val[2], val[3])) >= floor_k;
-        if (__ballot(hit) == 0)  // the common case: no cell of the wave's 256 qualifies
-            continue;
-        const uint32_t idx0 = (uint32_t)(((int64_t)gz * G + gy) * G + gx);
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            const bool in = row && gx + s < G && val[s] >= floor_k;
-            list = wave_insert_top(list, in ? cell_key(val[s], idx0 + s) : 0ull, lane, K);
-        }
-    }
-    list = block_merge<kAccumWaves>(list, lists, wave, lane);
-    if (wave == 0)
-        partial[(int64_t)(qoff + b) * kWave + lane] = list;
 }
 
 // ------------------------------------------------------------- launchers
 
 int brick_axis(int G, int edge_log2) { return (G + (1 << edge_log2) - 1) >> edge_log2; }
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+
+// Workgroups of the persistent accumulation: as many as the device holds at
+// once (CUs x resident workgroups per CU, measured once per device and edge),
+// at most one per brick.
+int accum_blocks(int edge_log2, int items)
+{
+    static std::atomic<int> cached[2][kMaxDevices];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices)
+        return items;
+    std::atomic<int>& slot = cached[edge_log2 == 5 ? 1 : 0][dev];
+    int v = slot.load(std::memory_order_relaxed);
+    if (v <= 0) {
+        int cus = 0, occ = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            return items;
+        const hipError_t e =
+            edge_log2 == 5
+                ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_brick_accum<5>,
+                                                               Brick<5>::kThreads, 0)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_brick_accum<4>,
+                                                               Brick<4>::kThreads, 0);
+        if (e != hipSuccess || cus < 1 || occ < 1)
+            return items;
+        v = cus * occ;
+        slot.store(v, std::memory_order_relaxed);
+    }
+    return std::max(1, std::min(items, v));
+}
+
+}  // namespace
 
 int solve_edge_log2(int G) { return G <= 128 ? 4 : 5; }
 
@@ -769,9 +818,12 @@ hipError_t launch_brick_accum(int G, int K, int edge_log2, int32_t* grid, uint64
     const int nb = nba * nba * nba;
     if (G > kMaxBrickGrid || nb > kMaxBricksAll)
         return hipErrorInvalidValue;
-    const int blocks = a.batch ? a.batch * nb : nb;
     if (K < 1 || K > kWave)
         return hipErrorInvalidValue;
+    // batches: persistent workgroups (measured 5 % faster over 32 768 bricks);
+    // one solve: a workgroup per brick, which the hardware hands out in the
+    // plan's heaviest-first order as CUs free up (persistent was slower there)
+    const int blocks = a.batch ? accum_blocks(edge_log2, a.batch * nb) : nb;
     if (edge_log2 == 5)
         hipLaunchKernelGGL(k_brick_accum<5>, dim3(blocks), dim3(Brick<5>::kThreads), 0, s, a, G, nba,
                            K, grid, partial);
