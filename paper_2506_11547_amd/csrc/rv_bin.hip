@@ -820,10 +820,12 @@ hipError_t launch_brick_accum(int G, int K, int edge_log2, int32_t* grid, uint64
         return hipErrorInvalidValue;
     if (K < 1 || K > kWave)
         return hipErrorInvalidValue;
-    // batches: persistent workgroups (measured 5 % faster over 32 768 bricks);
-    // one solve: a workgroup per brick, which the hardware hands out in the
-    // plan's heaviest-first order as CUs free up (persistent was slower there)
-    const int blocks = a.batch ? accum_blocks(edge_log2, a.batch * nb) : nb;
+    // batches of 32^3 bricks: persistent workgroups (measured 5 % faster over
+    // 32 768 bricks); 16^3 bricks (many small workgroups per CU) and one solve:
+    // a workgroup per brick, which the hardware hands out in order (the plan's
+    // heaviest first) as CUs free up (persistent was slower there)
+    const int blocks = (a.batch && edge_log2 == 5) ? accum_blocks(edge_log2, a.batch * nb)
+                                                   : (a.batch ? a.batch * nb : nb);
     if (edge_log2 == 5)
         hipLaunchKernelGGL(k_brick_accum<5>, dim3(blocks), dim3(Brick<5>::kThreads), 0, s, a, G, nba,
                            K, grid, partial);
