@@ -141,11 +141,13 @@ def test_auto_strategy_choice(rv):
         assert g["plan"]["strategy"] == want, G
 
 
-@pytest.mark.parametrize("G,J", [(128, 1024), (300, 600)])
+@pytest.mark.parametrize("G,J", [(128, 1024), (200, 1600), (300, 600)])
 def test_brick_queue_overflow_is_exact(rv, orc, G, J):
-    """Queue capacities come from every 32nd correspondence; here all the
-    others are one repeated correspondence, so its bricks overflow and their
-    excess runs take the atomic overflow path.  The histogram must not change."""
+    """Queue capacities come from every 64th correspondence, all of them
+    random here; the others (all but every 32nd) are one repeated
+    correspondence, so its bricks overflow and their excess runs take the
+    atomic overflow path.  The histogram must not change.  16^3 bricks at
+    G = 128, 32^3 at 200, the wide layout at 300."""
     n = 64 * 256
     r = np.random.default_rng(9)
     x = r.normal(size=(3, n)).astype(np.float32)
