@@ -14,6 +14,10 @@
 #include <cstdint>
 #include <vector>
 
+#pragma GCC visibility push(default)
+#include "rotvote_probe.h"
+#pragma GCC visibility pop
+
 #define RVP_API extern "C" __attribute__((visibility("default")))
 
 namespace {

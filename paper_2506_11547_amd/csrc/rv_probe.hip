@@ -3,6 +3,10 @@
 // the hardware's rounding of the primitive operations.  Not used by a solve.
 #include "rv_device.h"
 
+#pragma GCC visibility push(default)
+#include "rotvote_probe.h"
+#pragma GCC visibility pop
+
 #define RVP_API extern "C" __attribute__((visibility("default")))
 
 namespace {

@@ -10,6 +10,7 @@ import pytest
 
 ROOT = Path(__file__).resolve().parents[1]
 HEADER = ROOT / "include" / "rotvote.h"
+PROBE_HEADER = ROOT / "include" / "rotvote_probe.h"
 LIB = ROOT / "paper_2506_11547_amd" / "librotvote.so"
 PROBE = ROOT / "paper_2506_11547_amd" / "librotvote_probe.so"
 
@@ -67,11 +68,12 @@ def test_product_library_does_not_reference_the_oracle(lib_path):
             assert "rotvote_oracle" not in text, src
 
 
-def test_probe_library_exports(lib_path):
+def test_probe_library_exports_its_header(lib_path):
+    declared_probe = sorted(set(re.findall(r"\b(rvp_\w+)\s*\(", PROBE_HEADER.read_text())))
+    assert len(declared_probe) == 10, declared_probe
     syms = dynamic_symbols(PROBE)
-    for n in ("rvp_recip", "rvp_div_sqrt", "rvp_basis", "rvp_cells", "rvp_decode", "rvp_residual",
-              "rvp_ceil_valu", "rvp_ceil_lds_atomic", "rvp_ceil_global_atomic", "rvp_ceil_copy"):
-        assert n in syms
+    assert [n for n in declared_probe if n not in syms] == []
+    assert [s for s in syms if s.startswith("rvp_") and s not in declared_probe] == []
 
 
 def test_default_config_and_create_without_gpu(lib_path):
