@@ -60,7 +60,8 @@ def check(q, cnt, lab, top, r):
 
 
 @pytest.mark.parametrize("models,per_model,G,J", [(2, 1000, 64, 540), (3, 1500, 64, 540),
-                                                  (5, 1000, 96, 540), (9, 1000, 128, 540)])
+                                                  (5, 1000, 96, 540), (9, 1000, 128, 540),
+                                                  (4, 1000, 200, 540), (3, 1000, 300, 540)])
 def test_scene_with_several_rotations(rv, orc, models, per_model, G, J):
     inst = datagen.make_multi_instance(models, per_model, per_model, 0.01, 200 + models)
     q, cnt, lab, top, r = run_both(rv, orc, inst.x, inst.y, G, J, 2.0, 64, models + 3, 10.0, 50)
