@@ -218,3 +218,31 @@ def test_batch_error_conventions(rv):
         with pytest.raises(rv.RotVoteError) as e:
             s.solve_batch(x, x, [0, 10], 16, 1.0)
         assert e.value.status == rv.RV_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("grids", [True, False])
+def test_persistent_accumulation_with_overflow(rv, orc, grids):
+    """40 instances (320 bricks of 32^3, more than the GPU's resident
+    accumulation workgroups, so each workgroup takes bricks in rounds), every
+    fifth one a single repeated correspondence whose bricks overflow their
+    queues: every instance against the oracle."""
+    r = np.random.default_rng(31)
+    inst = []
+    for k in range(40):
+        n = int(r.integers(200, 2500))
+        if k % 5 == 2:
+            xr = np.tile(np.float32([[0.3], [-0.5], [0.8]]), (1, n))
+            yr = np.tile(np.float32([[0.9], [0.1], [-0.2]]), (1, n))
+            inst.append((xr, yr))
+        else:
+            d = datagen.make_instance(n, float(r.uniform(0.3, 0.95)), 0.5, 500 + k)
+            inst.append((d.x, d.y))
+    x, y, offs = concat(inst)
+    with rv.Solver(max_n=int(offs[-1]), max_grid=64, topk=16, max_batch=len(inst),
+                   batch_grids=grids, batch_brick_edge=32) as s:
+        for _ in range(2):  # overflow grids left zeroed for the next batch
+            q, cnt, mask = s.solve_batch(dev(x), dev(y), offs, 64, 1.0)
+            m = mask.cpu().numpy()
+            for b, (xb, yb) in enumerate(inst):
+                check_instance(rv, s, b, q[b], cnt[b], m[offs[b]:offs[b + 1]], xb, yb, 64, 512,
+                               1.0, 16, orc, grids=grids)
