@@ -296,3 +296,22 @@ def test_tuned_strategy_changes_speed_only(rv, orc, G):
     o = orc.solve(inst.x, inst.y, G, 8 * G, eps_rad(rv, 1.0), 16)
     assert np.array_equal(np.float32(q1).view(np.uint32), o["q"].view(np.uint32))
     assert c1 == o["count"]
+
+
+@pytest.mark.parametrize("wl", ["large", "paper_default"])
+def test_permutation_invariance_at_full_size(rv, wl):
+    """A property that holds at any size, checked at the benchmark's sizes
+    without the oracle: permuting the correspondences changes which
+    workgroups vote which circles and the order of runs in every queue, but
+    not the histogram, the candidates, the rotation or the count; the mask
+    is permuted with them."""
+    w, inst = datagen.make_workload(wl)
+    g = run_gpu(rv, inst.x, inst.y, w.grid, w.samples, w.eps_deg, w.topk)
+    p = np.random.default_rng(11).permutation(inst.n)
+    h = run_gpu(rv, inst.x[:, p], inst.y[:, p], w.grid, w.samples, w.eps_deg, w.topk)
+    assert np.array_equal(g["hist"], h["hist"])
+    assert g["top"]["votes"] == h["top"]["votes"] and g["top"]["idx"] == h["top"]["idx"]
+    assert g["top"]["inliers"] == h["top"]["inliers"]
+    assert np.array_equal(g["q"].view(np.uint32), h["q"].view(np.uint32))
+    assert g["count"] == h["count"]
+    assert np.array_equal(g["mask"][p], h["mask"])
