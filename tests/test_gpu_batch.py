@@ -246,3 +246,26 @@ def test_persistent_accumulation_with_overflow(rv, orc, grids):
             for b, (xb, yb) in enumerate(inst):
                 check_instance(rv, s, b, q[b], cnt[b], m[offs[b]:offs[b + 1]], xb, yb, 64, 512,
                                1.0, 16, orc, grids=grids)
+
+
+def test_full_batch_instance_order_invariance(rv):
+    """A property at the benchmark's size (4096 instances) without the oracle:
+    reversing the order of the instances in the batch changes which work
+    units and bricks run where, not any instance's rotation, count or mask."""
+    w = datagen.BATCH_WORKLOADS["batch"]
+    bt = w.batch()
+    inst = [bt.instance(b) for b in range(bt.B)]
+    x1, y1, o1 = concat(inst)
+    x2, y2, o2 = concat(inst[::-1])
+    with rv.Solver(max_n=int(o1[-1]), max_grid=w.grid, topk=w.topk, samples_per_circle=w.samples,
+                   max_batch=bt.B) as s:
+        q1, c1, m1 = s.solve_batch(dev(x1), dev(y1), o1, w.grid, w.eps_deg)
+        m1 = m1.cpu().numpy()
+        q2, c2, m2 = s.solve_batch(dev(x2), dev(y2), o2, w.grid, w.eps_deg)
+        m2 = m2.cpu().numpy()
+    B = bt.B
+    for b in range(B):
+        r = B - 1 - b
+        assert np.array_equal(np.float32(q1[b]).view(np.uint32), np.float32(q2[r]).view(np.uint32)), b
+        assert c1[b] == c2[r], b
+        assert np.array_equal(m1[o1[b]:o1[b + 1]], m2[o2[r]:o2[r + 1]]), b
