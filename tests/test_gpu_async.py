@@ -114,8 +114,9 @@ def test_async_argument_errors(rv):
         assert int(buf.sum()) == 0   # nothing was written
 
 
+@pytest.mark.parametrize("mode", ["relaxed", "global"])
 @pytest.mark.parametrize("G", [64, 256])
-def test_async_solve_in_a_graph(rv, G):
+def test_async_solve_in_a_graph(rv, G, mode):
     """Captured once, replayed on three new inputs copied into the captured
     buffers; eager solves and synchronisations between the replays."""
     n = 4000
@@ -135,7 +136,7 @@ def test_async_solve_in_a_graph(rv, G):
             s.solve_async(xb, yb, G, eps, result=res, mask=mask)   # uploads the table
         stream.synchronize()
         g = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(g, stream=stream, capture_error_mode="relaxed"):
+        with torch.cuda.graph(g, stream=stream, capture_error_mode=mode):
             s.solve_async(xb, yb, G, eps, result=res, mask=mask)
         torch.cuda.synchronize()
         for rep in range(2):
