@@ -71,7 +71,9 @@ enum {
     RV_MAX_BATCH_GRID = 64,
     RV_MAX_REFINE_ROUNDS = 64,
     RV_MAX_T_CELLS = 1024,
-    RV_MAX_RIGID_N = 1 << 18  /* point correspondences of the quadratic rigid stages */
+    RV_MAX_RIGID_N = 1 << 18, /* point correspondences of the quadratic rigid stages */
+    RV_NOALLOC_MAX_GRID = 64,       /* rot_vote_solve_noalloc: largest G */
+    RV_NOALLOC_MAX_SAMPLES = 4096   /* rot_vote_solve_noalloc: largest J */
 };
 
 typedef struct rv_config {
@@ -107,7 +109,8 @@ rv_status rot_vote_create(rv_handle **out, const rv_config *cfg);
 rv_status rot_vote_destroy(rv_handle *h);
 
 /* Reason for the handle's last error ("" if none); valid until the next call
- * on h.  A NULL handle yields the reason of the last failed create. */
+ * on h.  A NULL handle yields the reason of the last failed call made without
+ * a handle (rot_vote_create or rot_vote_solve_noalloc). */
 const char *rot_vote_last_error(const rv_handle *h);
 
 /* Rebinds the handle to another HIP stream (e.g. the caller's current one). */
@@ -156,6 +159,37 @@ typedef struct rv_result {
 rv_status rot_vote_solve_async(rv_handle *h, const float *x, const float *y, int64_t n,
                                int32_t grid, float eps_rad, rv_result *result_device,
                                uint8_t *inlier_mask);
+
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  One solve
+ * as rot_vote_solve_async gives it (the same results bit for bit, for the
+ * same x, y, n, grid, J, K and eps), with no handle and no allocation of any
+ * kind: no hipMalloc, hipFree or allocating library call.
+ *   x, y, n, grid, eps_rad, inlier_mask   as rot_vote_solve.
+ *   samples_per_circle  J; 0 means 8 * grid.
+ *   topk          K candidates rescored, 1..RV_MAX_TOPK.
+ *   stream        hipStream_t of the calling thread's current device (NULL:
+ *                 the null stream); the call enqueues its kernels there and
+ *                 returns without waiting.
+ *   result_device device memory, one rv_result, 8-byte aligned; written
+ *                 when the stream reaches it, as for rot_vote_solve_async.
+ * Scratch: the vote grid, sample table, top-K lists and candidates live in
+ * one fixed device array inside the library (about 1.1 MiB), which each GPU
+ * the library runs on holds from the library's load until the process ends.
+ * Every call on a GPU uses that GPU's array and leaves the last call's
+ * contents in it (each call clears what it needs), so calls whose work
+ * overlaps on one GPU (two streams, or two threads) race and give wrong
+ * results: order them (one stream, or events).  Limits of the fixed array:
+ * grid 1..RV_NOALLOC_MAX_GRID (64^3 int32 cells, 1 MiB) and J up to
+ * RV_NOALLOC_MAX_SAMPLES; beyond them the call returns RV_EUNSUPPORTED.
+ * The first call on a device looks the array's address up on that device
+ * (hipGetSymbolAddress): make it before capturing calls into a graph.
+ * Errors: a negative rv_status with nothing enqueued, the reason in
+ * rot_vote_last_error(NULL); device errors surface at the caller's next
+ * synchronisation. */
+rv_status rot_vote_solve_noalloc(const float *x, const float *y, int64_t n, int32_t grid,
+                                 int32_t samples_per_circle, int32_t topk, float eps_rad,
+                                 void *stream, rv_result *result_device, uint8_t *inlier_mask);
 
 /* Vote strategy chosen by measurement: times `reps` solves of this input
  * (after one untimed solve) with each strategy the handle supports at this

@@ -49,6 +49,12 @@ int rvp_decode(const int *idx, int64_t n, int G, float *q);
  * x, y: float32 SoA [3][n]; out: float32 [n]. */
 int rvp_residual(const float *x, const float *y, int64_t n, const float *q, float *out);
 
+/* The sample table of rot_vote_solve_noalloc, computed on the device: out[2j]
+ * = cos(theta_j), out[2j + 1] = sin(theta_j), theta_j = ((2j + 1 - J) / J)
+ * (pi / 2) in binary64 rounded to binary32 (Alg. 1's circle samples).
+ * out: float32 [2 J]. */
+int rvp_table(int J, float *out);
+
 /* Ceiling micro-benchmarks.  Each allocates its own buffers, runs one untimed
  * and one timed launch (HIP events), checks what it can of the result, frees
  * everything and writes the rate to the host double.

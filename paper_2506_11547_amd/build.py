@@ -41,7 +41,7 @@ def build(verbose: bool = False) -> list[Path]:
     jobs = [
         (LIB, [CSRC / "rv_kernels.hip", CSRC / "rv_bin.hip", CSRC / "rv_batch.hip",
                CSRC / "rv_refine.hip", CSRC / "rv_multi.hip", CSRC / "rv_rigid.hip",
-               CSRC / "rv_api.cpp",
+               CSRC / "rv_static.hip", CSRC / "rv_api.cpp",
                CSRC / "rv_serve.cpp"]),
         (PROBE_LIB, [CSRC / "rv_probe.hip", CSRC / "rv_ceil.hip"]),
     ]

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cstddef>
 #include <cmath>
@@ -16,6 +17,30 @@
 #include "rv_internal.h"
 
 #define RV_API extern "C" __attribute__((visibility("default")))
+
+namespace rv {
+
+bool is_device_memory(const void* p)
+{
+    hipPointerAttribute_t attr;
+    if (hipPointerGetAttributes(&attr, p) != hipSuccess) {
+        (void)hipGetLastError();  // clear the sticky "invalid value" for host pointers
+        return false;
+    }
+    return attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged;
+}
+
+// |L q|^2 = 4 sin^2(psi / 2) for the angle psi between R(q) a and b.
+float residual_bound(float eps)
+{
+    const double s = std::sin(0.5 * (double)eps);
+    return (float)(4.0 * s * s);
+}
+
+}  // namespace rv
+
+using rv::is_device_memory;
+using rv::residual_bound;
 
 namespace {
 
@@ -38,6 +63,9 @@ int64_t runs_per_circle(int G, int J)
 }
 
 std::string g_create_error;  // reason of the last failed create (NULL handle)
+// The last failed handle-free call's reason when it was not a create: a
+// string literal, or null when the create's message is the latest.
+std::atomic<const char*> g_null_reason{nullptr};
 
 // rot_vote_solve_async copies the internal result record to the caller's
 // rv_result: the two layouts are one.
@@ -47,6 +75,8 @@ static_assert(offsetof(rv_result, winner) == offsetof(rv::Result, winner), "resu
 static_assert(offsetof(rv_result, n_cand) == offsetof(rv::Result, n_cand), "result layout");
 
 }  // namespace
+
+void rv::set_null_error(const char* msg) { g_null_reason.store(msg); }
 
 struct rv_handle {
     rv_config cfg{};
@@ -158,8 +188,10 @@ rv_status fail(rv_handle* h, rv_status st, const std::string& msg)
 {
     if (h)
         h->err = msg;
-    else
+    else {
         g_create_error = msg;
+        g_null_reason.store(nullptr);
+    }
     return st;
 }
 
@@ -175,16 +207,6 @@ rv_status hip_fail(rv_handle* h, hipError_t e, const char* what)
         if (e_ != hipSuccess)                  \
             return hip_fail((h), e_, (what));  \
     } while (0)
-
-bool is_device_memory(const void* p)
-{
-    hipPointerAttribute_t attr;
-    if (hipPointerGetAttributes(&attr, p) != hipSuccess) {
-        (void)hipGetLastError();  // clear the sticky "invalid value" for host pointers
-        return false;
-    }
-    return attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged;
-}
 
 void release(rv_handle* h)
 {
@@ -253,13 +275,6 @@ void fill_table(float2* t, int J)
         t[j].x = (float)std::cos(th);
         t[j].y = (float)std::sin(th);
     }
-}
-
-// |L q|^2 = 4 sin^2(psi / 2) for the angle psi between R(q) a and b.
-float residual_bound(float eps)
-{
-    const double s = std::sin(0.5 * (double)eps);
-    return (float)(4.0 * s * s);
 }
 
 rv::Candidates candidates(rv_handle* h)
@@ -490,7 +505,10 @@ RV_API rv_status rot_vote_destroy(rv_handle* h)
 
 RV_API const char* rot_vote_last_error(const rv_handle* h)
 {
-    return h ? h->err.c_str() : g_create_error.c_str();
+    if (h)
+        return h->err.c_str();
+    const char* r = g_null_reason.load();
+    return r ? r : g_create_error.c_str();
 }
 
 RV_API rv_status rot_vote_set_stream(rv_handle* h, void* stream)

@@ -28,6 +28,15 @@ constexpr int kTopkMaxBlocks = 2048;  // also the largest brick count
 
 hipError_t launch_fill(int32_t* p, int64_t count, int32_t value, hipStream_t s);
 
+// Host helpers of the C-ABI layer: whether p is device (or managed) memory,
+// and the rescoring bound 4 sin^2(eps / 2) rounded once to binary32.
+bool is_device_memory(const void* p);
+float residual_bound(float eps);
+// Reason of the last failed call made without a handle (a create or the
+// no-allocation solve), read by rot_vote_last_error(NULL); msg is a string
+// literal (setting it allocates nothing).
+void set_null_error(const char* msg);
+
 // Global-atomic vote: one wave per (64 correspondences, sample chunk); chunk
 // <= 0 picks chunks (whole table rows) for about 8192 waves.
 hipError_t launch_vote_global(const float* x, const float* y, int64_t n, int G, int J,

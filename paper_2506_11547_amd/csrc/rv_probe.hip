@@ -2,6 +2,7 @@
 // test suite can compare each step with the CPU oracle bit for bit and check
 // the hardware's rounding of the primitive operations.  Not used by a solve.
 #include "rv_device.h"
+#include "rv_table.h"
 
 #pragma GCC visibility push(default)
 #include "rotvote_probe.h"
@@ -77,6 +78,13 @@ __global__ void k_residual(const float* x, const float* y, int64_t n, const floa
     out[i] = (oka && okb) ? rv::residual2(D, P, qq) : -1.0f;
 }
 
+__global__ void k_table(int J, float2* out)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < J)
+        out[j] = rv::table_entry(j, J);
+}
+
 int blocks(int64_t n) { return (int)((n + 255) / 256); }
 
 int finish()
@@ -132,5 +140,12 @@ RVP_API int rvp_residual(const float* x, const float* y, int64_t n, const float*
 {
     if (n <= 0) return 0;
     hipLaunchKernelGGL(k_residual, dim3(blocks(n)), dim3(256), 0, 0, x, y, n, q, out);
+    return finish();
+}
+
+RVP_API int rvp_table(int J, float* out)
+{
+    if (J <= 0) return 0;
+    hipLaunchKernelGGL(k_table, dim3(blocks(J)), dim3(256), 0, 0, J, reinterpret_cast<float2*>(out));
     return finish();
 }

@@ -29,6 +29,8 @@ STRATEGY_NAMES = {v: k for k, v in STRATEGIES.items()}
 FLAG_TIMING = 1
 FLAG_BATCH_GRIDS = 2
 MAX_TOPK = 64
+NOALLOC_MAX_GRID = 64
+NOALLOC_MAX_SAMPLES = 4096
 MAX_BATCH_GRID = 64
 MAX_REFINE_ROUNDS = 64
 NUM_STAGES = 6
@@ -45,7 +47,7 @@ EXPORTS = ("rot_vote_default_config", "rot_vote_create", "rot_vote_destroy",
            "rot_vote_server_default_config",
            "rot_vote_server_create",
            "rot_vote_server_destroy", "rot_vote_server_submit", "rot_vote_server_wait",
-           "rot_vote_server_stats", "rot_vote_server_last_error")
+           "rot_vote_server_stats", "rot_vote_server_last_error", "rot_vote_solve_noalloc")
 
 
 class RvConfig(ct.Structure):
@@ -121,6 +123,8 @@ def load_library(path: Path | str = LIB_PATH) -> ct.CDLL:
     L.rot_vote_solve.restype = i32
     L.rot_vote_solve_async.argtypes = [vp, vp, vp, i64, i32, f32, vp, vp]
     L.rot_vote_solve_async.restype = i32
+    L.rot_vote_solve_noalloc.argtypes = [vp, vp, i64, i32, i32, i32, f32, vp, vp, vp]
+    L.rot_vote_solve_noalloc.restype = i32
     L.rot_vote_get_histogram.argtypes = [vp, vp]
     L.rot_vote_get_histogram.restype = i32
     L.rot_vote_get_topk.argtypes = [vp, ct.POINTER(i32), ct.POINTER(i32 * MAX_TOPK),
@@ -214,6 +218,43 @@ def decode_result(result) -> dict:
 def eps_deg_to_rad(eps_deg: float) -> float:
     """Degrees to the float32 radians the C-ABI takes (converted in float64)."""
     return float(ct.c_float(eps_deg * math.pi / 180.0).value)
+
+
+def solve_noalloc_raw(x_ptr: int, y_ptr: int, n: int, grid: int, eps_rad: float, result_ptr: int,
+                      mask_ptr: int, samples_per_circle: int = 0, topk: int = 16,
+                      stream: int = 0) -> None:
+    """Direct C-ABI call of the handle-free solve that allocates nothing: enqueues
+    it on the raw stream and returns; the rv_result at result_ptr is written later."""
+    L = load_library()
+    st = L.rot_vote_solve_noalloc(ct.c_void_p(x_ptr), ct.c_void_p(y_ptr), n, grid,
+                                  samples_per_circle, topk, ct.c_float(eps_rad),
+                                  ct.c_void_p(stream), ct.c_void_p(result_ptr),
+                                  ct.c_void_p(mask_ptr))
+    if st != RV_OK:
+        raise RotVoteError(st, L.rot_vote_last_error(None).decode())
+
+
+def solve_noalloc(x: torch.Tensor, y: torch.Tensor, grid: int, eps_deg: float,
+                  result: torch.Tensor, mask: torch.Tensor, samples_per_circle: int = 0,
+                  topk: int = 16, stream: torch.cuda.Stream | None = None) -> None:
+    """The handle-free solve into caller-owned ``result`` (device uint8 of
+    RESULT_BYTES) and ``mask`` (device bool [N]) on ``stream`` (default: torch's
+    current stream); nothing is allocated, nothing waited for."""
+    for t, nm in ((x, "x"), (y, "y")):
+        if t.dtype != torch.float32 or t.dim() != 2 or t.shape[0] != 3 or not t.is_cuda \
+                or not t.is_contiguous():
+            raise ValueError(f"{nm} must be a contiguous float32 [3, N] device tensor")
+    if x.shape != y.shape:
+        raise ValueError("x and y must have the same shape")
+    if result.dtype != torch.uint8 or result.numel() != RESULT_BYTES or not result.is_cuda:
+        raise ValueError(f"result must be a device uint8 tensor of {RESULT_BYTES} bytes")
+    n = x.shape[1]
+    if mask.numel() != n or mask.element_size() != 1 or not mask.is_cuda:
+        raise ValueError("mask must be a 1-byte [N] device tensor")
+    s = stream if stream is not None else torch.cuda.current_stream(x.device)
+    solve_noalloc_raw(x.data_ptr(), y.data_ptr(), n, grid, eps_deg_to_rad(eps_deg),
+                      result.data_ptr(), mask.data_ptr() if n else 0, samples_per_circle, topk,
+                      s.cuda_stream)
 
 
 class Solver:
@@ -714,13 +755,14 @@ class Probe:
         L.rvp_cells.argtypes = [vp, i64, i32, vp, i32]
         L.rvp_decode.argtypes = [vp, i64, i32, vp]
         L.rvp_residual.argtypes = [vp, vp, i64, vp, vp]
+        L.rvp_table.argtypes = [i32, vp]
         d = ct.POINTER(ct.c_double)
         L.rvp_ceil_valu.argtypes = [i32, i32, d]
         L.rvp_ceil_lds_atomic.argtypes = [i32, i32, i32, d]
         L.rvp_ceil_global_atomic.argtypes = [i64, i32, i32, i32, d]
         L.rvp_ceil_copy.argtypes = [i64, d]
         for f in (L.rvp_recip, L.rvp_div_sqrt, L.rvp_basis, L.rvp_cells, L.rvp_decode,
-                  L.rvp_residual, L.rvp_ceil_valu, L.rvp_ceil_lds_atomic,
+                  L.rvp_residual, L.rvp_table, L.rvp_ceil_valu, L.rvp_ceil_lds_atomic,
                   L.rvp_ceil_global_atomic, L.rvp_ceil_copy):
             f.restype = i32
 
@@ -796,4 +838,11 @@ class Probe:
         out = torch.empty(x.shape[1], dtype=torch.float32, device=x.device)
         self._run(self.lib.rvp_residual(self._p(x), self._p(y), x.shape[1], self._p(q),
                                         self._p(out)))
+        return out
+
+    def table(self, J: int) -> torch.Tensor:
+        """The device-computed sample table of the handle-free solve, float32 [J, 2]."""
+        torch.cuda.synchronize()
+        out = torch.empty(J, 2, dtype=torch.float32, device="cuda")
+        self._run(self.lib.rvp_table(J, self._p(out)))
         return out
