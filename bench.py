@@ -61,14 +61,23 @@ def parse():
     ap.add_argument("--workload", default="large")
     ap.add_argument("--strategy", default="auto")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=150_000,
-                    help="correspondences of the workload the CPU oracle times")
+    ap.add_argument("--cpu-runs", type=int, default=5,
+                    help="whole-workload oracle solves on all host threads (median reported)")
+    ap.add_argument("--cpu-single-fraction", type=int, default=64,
+                    help="the one-thread oracle leg times this fraction 1/F of the workload")
+    ap.add_argument("--cpu-single-runs", type=int, default=3,
+                    help="one-thread oracle solves (median reported)")
     ap.add_argument("--cpu-instances", type=int, default=1000,
                     help="batch workload: instances the CPU oracle times")
-    ap.add_argument("--duration", type=float, default=10.0,
+    ap.add_argument("--duration", type=float, default=60.0,
                     help="serve workload: seconds of arrivals")
     ap.add_argument("--rate", type=float, default=2000.0, help="serve workload: requests/s")
-    ap.add_argument("--workers", type=int, default=4, help="serve workload: server workers")
+    ap.add_argument("--workers", type=int, default=8, help="serve workload: server lanes")
+    ap.add_argument("--hbm-budget-gib", type=float, default=8.0,
+                    help="serve workload: the server's scratch arena (admission by footprint)")
+    ap.add_argument("--tuning-cache", default=os.environ.get(
+        "ROTVOTE_TUNING", str(Path.home() / ".cache" / "rotvote" / "tuning.json")),
+                    help="batch workload: tuning file (JSON) read if present, else written")
     ap.add_argument("--no-loop", action="store_true",
                     help="batch workload: skip the one-solve-per-call comparison")
     ap.add_argument("--ceilings", action="store_true",
@@ -168,31 +177,63 @@ def measured_traffic(workload: str, kernel: str):
     return float(rec["traffic_bytes_per_launch"])
 
 
-def cpu_baseline(w, inst, n_sample: int) -> dict:
-    """The oracle, as it is, on the first n_sample correspondences."""
+def host_cpu() -> dict:
+    """The host the CPU baseline ran on: processors online (nproc), the ones
+    this process may use, and the CPU model."""
+    model = "unknown"
+    try:
+        for line in Path("/proc/cpuinfo").read_text().splitlines():
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    return {"nproc": os.cpu_count(), "usable": usable, "cpu_model": model}
+
+
+def cpu_baseline(w, inst, runs: int, single_fraction: int, single_runs: int) -> dict:
+    """The oracle, as it is, on the whole workload: the median wall time of
+    ``runs`` whole solves on every usable host thread (OpenMP vote loop; the
+    top-K scan and the rescoring are single-threaded in the oracle), and the
+    median of ``single_runs`` whole solves on one thread over the first
+    1/single_fraction of the correspondences.  Data generation is outside
+    every timing."""
+    import statistics
+
     import oracle
     o = oracle.get()
     threads = oracle.threads()
-    n_sample = min(n_sample, inst.n)
-    x = inst.x[:, :n_sample].copy()
-    y = inst.y[:, :n_sample].copy()
+    x, y = inst.x, inst.y
     eps = float(__import__("ctypes").c_float(w.eps_deg * math.pi / 180.0).value)
-    t0 = time.perf_counter()
-    o.solve(x, y, w.grid, w.samples, eps, w.topk, nthreads=threads)
-    dt = time.perf_counter() - t0
-    # the same solve on one thread, on a fifteenth of the sample
-    n1 = max(1, n_sample // 15)
-    t1 = time.perf_counter()
-    o.solve(x[:, :n1].copy(), y[:, :n1].copy(), w.grid, w.samples, eps, w.topk, nthreads=1)
-    dt1 = time.perf_counter() - t1
-    return {"value": n_sample * w.samples / dt, "unit": "votes/s", "cores": threads,
-            "kind": "oracle",
-            "sample": f"first {n_sample} of the {inst.n} correspondences, whole solve "
-                      f"(G={w.grid}, J={w.samples}, K={w.topk}); vote loop on {threads} "
-                      f"OpenMP threads, top-K and rescoring single-threaded; {dt:.2f} s",
-            "single_thread": {"value": n1 * w.samples / dt1, "unit": "votes/s", "cores": 1,
-                              "sample": f"first {n1} correspondences, whole solve on one "
-                                        f"thread; {dt1:.2f} s"}}
+    times = []
+    for _ in range(runs):
+        t0 = time.perf_counter()
+        o.solve(x, y, w.grid, w.samples, eps, w.topk, nthreads=threads)
+        times.append(time.perf_counter() - t0)
+    med = statistics.median(times)
+    n1 = max(1, inst.n // single_fraction)
+    x1, y1 = x[:, :n1].copy(), y[:, :n1].copy()
+    times1 = []
+    for _ in range(single_runs):
+        t1 = time.perf_counter()
+        o.solve(x1, y1, w.grid, w.samples, eps, w.topk, nthreads=1)
+        times1.append(time.perf_counter() - t1)
+    med1 = statistics.median(times1)
+    return {"value": inst.n * w.samples / med, "unit": "votes/s", "cores": threads,
+            "kind": "oracle", "n": inst.n, "runs": runs, "median_s": med,
+            "times_s": times, **host_cpu(),
+            "sample": f"the whole workload ({inst.n} correspondences; G={w.grid}, J={w.samples}, "
+                      f"K={w.topk}), median of {runs} whole solves; vote loop on {threads} "
+                      f"OpenMP threads, top-K and rescoring single-threaded",
+            "single_thread": {"value": n1 * w.samples / med1, "unit": "votes/s", "cores": 1,
+                              "n": n1, "runs": single_runs, "median_s": med1,
+                              "sample": f"first {n1} correspondences (1/{single_fraction} of "
+                                        f"the workload), whole solve on one thread, median of "
+                                        f"{single_runs}"}}
 
 
 def cpu_baseline_batch(w, bt, max_instances: int) -> dict:
@@ -283,7 +324,8 @@ def run_serve(args):
     arrivals = np.sort(rng.uniform(0.0, args.duration, n_req))
     picks = rng.integers(0, len(res), n_req)
     srv = rotvote.Server(workers=args.workers, max_n=1_000_000, max_grid=256, topk=16,
-                         max_batch=64, batch_max_n=65536, max_queue=1 << 22)
+                         max_batch=64, batch_max_n=65536, max_queue=1 << 22,
+                         hbm_budget=int(args.hbm_budget_gib * (1 << 30)))
     # warm-up: one request of every pool entry
     for k, (G, n, x, y, masks) in enumerate(res):
         srv.wait(srv.submit(x, y, G, eps_deg, masks[0]))
@@ -291,6 +333,7 @@ def run_serve(args):
     tickets = [None] * n_req
     use = [0] * len(res)
     t0 = time.monotonic() + 0.05
+    next_note = 10.0
     for i in range(n_req):
         k = int(picks[i])
         G, n, x, y, masks = res[k]
@@ -304,9 +347,14 @@ def run_serve(args):
             if d > 2e-4:
                 time.sleep(d - 1e-4)
         tickets[i] = srv.submit(x, y, G, eps_deg, m)
+        if arrivals[i] >= next_note:
+            print(f"serve: {i + 1} of {n_req} requests submitted at {arrivals[i]:.0f} s",
+                  file=sys.stderr, flush=True)
+            next_note += 10.0
     replies = [srv.wait(t) for t in tickets]
     torch.cuda.synchronize()
     st = srv.stats()
+    mem = srv.memory()
     srv.close()
     lat = np.array([r["t_end"] - (t0 + a) for r, a in zip(replies, arrivals)])
     wait = np.array([r["t_start"] - r["t_submit"] for r in replies])
@@ -332,7 +380,8 @@ def run_serve(args):
         "config": {"workload": "serve", "rate_rps": args.rate, "duration_s": args.duration,
                    "n_range": [1_000, 1_000_000], "grids": [64, 128, 256], "outlier_ratio": [0.8, 0.99],
                    "sigma_deg": 1.0, "eps_deg": eps_deg, "topk": 16, "seed": seed,
-                   "pool_per_tier": 24, "workers": st["workers"], "max_batch": 64},
+                   "pool_per_tier": 24, "workers": st["workers"], "max_batch": 64,
+                   "hbm_budget_bytes": mem["arena_bytes"]},
         "serving": {
             "requests": n_req, "offered_rps": n_req / args.duration, "achieved_rps": n_req / span,
             "offered_votes_per_s": offered, "achieved_votes_per_s": achieved,
@@ -346,6 +395,13 @@ def run_serve(args):
             "batched_fraction": float(np.mean([r["batched"] > 1 for r in replies])),
             "mean_batch": float(np.mean([r["batched"] for r in replies])),
             "server_device_bytes": st["device_bytes"],
+            "arena_peak_in_use_bytes": mem["peak_in_use"],
+            "peak_in_flight": mem["peak_in_flight"],
+            "scratch_mib_p50_by_grid": {
+                int(g): float(np.percentile([r["scratch_bytes"] for r, t in zip(replies, tier)
+                                             if t == g and r["batched"] == 1], 50) / (1 << 20))
+                for g in (64, 128, 256)
+                if any(t == g and r["batched"] == 1 for r, t in zip(replies, tier))},
         },
     }
     print(json.dumps(out), flush=True)
@@ -499,7 +555,24 @@ def run_batch(args):
     solver = rotvote.Solver(device=0, max_n=n, max_grid=w.grid, topk=w.topk,
                             samples_per_circle=w.samples, timing=True, stream=stream,
                             max_batch=bt.B)
-    edge, edge_ms = solver.tune_batch(x, y, offs, w.grid, w.eps_deg, reps=2)
+    # the batch schedule (brick edge per instance-size bucket): from the tuning
+    # file when it holds one for this GPU, grid and J, else by measurement
+    cache = Path(args.tuning_cache)
+    tuning = {"file": str(cache)}
+    if cache.exists() and solver.load_tuning(cache) > 0:
+        tuning["source"] = "loaded"
+    else:
+        edges, ms = solver.tune_batch(x, y, offs, w.grid, w.eps_deg, reps=2)
+        tuning.update(source="measured", ms_all32=ms[0],
+                      ms_bucket_at16=[ms[k + 1] for k in range(rotvote.BATCH_BUCKETS)])
+        cache.parent.mkdir(parents=True, exist_ok=True)
+        solver.save_tuning(cache)
+    sched = solver.batch_schedule(w.grid)
+    tuning["schedule"] = dict(zip(["n<512", "512<=n<2048", "2048<=n<8192", "n>=8192"], sched))
+    # the brick edge that votes most of the samples (its vote kernel is the profiled one)
+    sizes = np.diff(offs)
+    bucket = np.searchsorted(np.array(rotvote.BATCH_BUCKET_BOUNDS), sizes, side="right")
+    edge = sched[int(np.argmax(np.bincount(bucket, weights=sizes, minlength=4)))]
     for _ in range(args.warmup):
         solver.solve_batch(x, y, offs, w.grid, w.eps_deg, mask=mask)
     stage = {k: 0.0 for k in rotvote.STAGE_NAMES}
@@ -512,6 +585,7 @@ def run_batch(args):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
 
+    graph = graph_batch_leg(sched, x, y, offs, w, bt.B, args.steps, q, cnt)
     loop = None
     if not args.no_loop:
         loop = loop_baseline(args, w, bt, x, y, mask, stream, q, cnt)
@@ -541,7 +615,8 @@ def run_batch(args):
                    "sigma_deg": w.sigma_deg, "grid": w.grid, "samples_per_circle": w.samples,
                    "eps_deg": w.eps_deg, "topk": w.topk, "seed": w.seed,
                    "vote_strategy": "brick (batched)", "brick_edge": edge},
-        "brick_edge_tuning": {"chosen": edge, "ms_edge32": edge_ms[32], "ms_edge16": edge_ms[16]},
+        "batch_schedule": tuning,
+        "graph": graph,
         "solves_per_s": bt.B * steps / dt,
         "stage_ms": stage_ms,
         "loop": loop if loop is None else dict(loop, speedup_of_batch=(bt.B * steps / dt) /
@@ -556,6 +631,49 @@ def run_batch(args):
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_batch(w, bt, args.cpu_instances)
     print(json.dumps(out), flush=True)
+
+
+def graph_batch_leg(sched, x, y, offs, w, B: int, reps: int, q, cnt) -> dict:
+    """The device-planned batch (offsets in device memory) captured once into
+    a HIP graph on a side stream (a handle without timing events, with the
+    same batch schedule) and replayed ``reps`` times; wall time per replay,
+    and whether every instance's rotation and count equal the synchronous
+    batch's."""
+    import numpy as np
+    import torch
+
+    from paper_2506_11547_amd import rotvote
+    side = torch.cuda.Stream()
+    ob = torch.from_numpy(np.ascontiguousarray(offs, np.int64)).cuda()
+    res = torch.zeros(B, rotvote.RESULT_BYTES, dtype=torch.uint8, device="cuda")
+    mask = torch.empty(x.shape[1], dtype=torch.bool, device="cuda")
+    solver = rotvote.Solver(device=0, max_n=x.shape[1], max_grid=w.grid, topk=w.topk,
+                            samples_per_circle=w.samples, stream=side, max_batch=B)
+    solver.set_batch_schedule(w.grid, sched)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(side):
+        solver.solve_batch_async(x, y, ob, w.grid, w.eps_deg, results=res, mask=mask)
+    side.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=side):
+        solver.solve_batch_async(x, y, ob, w.grid, w.eps_deg, results=res, mask=mask)
+    torch.cuda.synchronize()
+    g.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        g.replay()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    raw = res.cpu().numpy()
+    gq = raw[:, :16].copy().view(np.float32).reshape(B, 4)
+    gc = raw[:, 16:24].copy().view(np.int64).reshape(B)
+    same = bool(np.array_equal(gq.view(np.uint32), np.float32(q).view(np.uint32)) and
+                np.array_equal(gc, cnt))
+    del g
+    solver.close()
+    return {"replays": reps, "ms_per_batch": dt * 1e3, "solves_per_s": B / dt,
+            "identical_to_sync": same}
 
 
 def refine_leg(solver, x, y, q, mask, w, inst, reps: int = 5) -> dict:
@@ -661,7 +779,8 @@ def main():
     tuned = None
     if args.strategy == "auto":
         best, ms = solver.tune(x, y, w.grid, w.eps_deg, reps=3)
-        tuned = {"chosen": best, "ms_global": ms["global"], "ms_brick": ms["brick"]}
+        tuned = {"chosen": best, "ms_global": ms["global"], "ms_brick": ms["brick"],
+                 "ms_keys": ms["keys"]}
     for _ in range(args.warmup):
         solver.solve(x, y, w.grid, w.eps_deg, mask=mask)
     stage = {k: 0.0 for k in rotvote.STAGE_NAMES}
@@ -716,7 +835,8 @@ def main():
         "async": pipelined,
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, inst, args.cpu_sample)
+        out["cpu_baseline"] = cpu_baseline(w, inst, args.cpu_runs, args.cpu_single_fraction,
+                                           args.cpu_single_runs)
     print(json.dumps(out), flush=True)
 
 

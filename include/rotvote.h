@@ -56,7 +56,10 @@ typedef enum rv_status {
 typedef enum rv_vote_strategy {
     RV_VOTE_AUTO = 0,      /* chosen per (G, n) from measurements */
     RV_VOTE_GLOBAL = 1,    /* run-coalesced atomics straight into the grid */
-    RV_VOTE_BRICK = 2      /* runs binned by brick, bricks accumulated in LDS (grid <= 384) */
+    RV_VOTE_BRICK = 2,     /* runs binned by brick, bricks accumulated in LDS (grid <= 384) */
+    RV_VOTE_KEYS = 3       /* every sample a key, keys sorted by brick in LDS and stored in
+                              brick order, bricks accumulated in LDS (grid <= 384); automatic
+                              for J <= 2 G, where nearly every sample starts a new cell */
 } rv_vote_strategy;
 
 enum {
@@ -72,6 +75,8 @@ enum {
     RV_MAX_REFINE_ROUNDS = 64,
     RV_MAX_T_CELLS = 1024,
     RV_MAX_RIGID_N = 1 << 18, /* point correspondences of the quadratic rigid stages */
+    RV_BATCH_BUCKETS = 4,     /* instance-size buckets of a batch schedule: n < 512,
+                                 512 <= n < 2048, 2048 <= n < 8192, n >= 8192 */
     RV_NOALLOC_MAX_GRID = 64,       /* rot_vote_solve_noalloc: largest G */
     RV_NOALLOC_MAX_SAMPLES = 4096   /* rot_vote_solve_noalloc: largest J */
 };
@@ -113,7 +118,10 @@ rv_status rot_vote_destroy(rv_handle *h);
  * a handle (rot_vote_create or rot_vote_solve_noalloc). */
 const char *rot_vote_last_error(const rv_handle *h);
 
-/* Rebinds the handle to another HIP stream (e.g. the caller's current one). */
+/* Rebinds the handle to another HIP stream (e.g. the caller's current one).
+ * Work already enqueued on the old stream is ordered before the handle's
+ * next work on the new one (an event recorded on the old stream, waited on
+ * by the new), so the two never use the handle's scratch at once. */
 rv_status rot_vote_set_stream(rv_handle *h, void *stream);
 
 /* One robust solve (Alg. 1 voting, then exact rescoring of the top K cells).
@@ -193,17 +201,18 @@ rv_status rot_vote_solve_noalloc(const float *x, const float *y, int64_t n, int3
 
 /* Vote strategy chosen by measurement: times `reps` solves of this input
  * (after one untimed solve) with each strategy the handle supports at this
- * grid and remembers the faster one for the grid; later solves at that grid
- * with vote_strategy AUTO use it.  Both strategies give the same histogram
- * and results bit for bit, so tuning changes speed only.
+ * grid and remembers the fastest for the grid; later solves at that grid
+ * with vote_strategy AUTO use it.  Every strategy gives the same histogram
+ * and results bit for bit (Alg. 1's vote is a sum of integer counts), so
+ * tuning changes speed only.
  *   mask_scratch   device uint8[n] written by the timed solves.
- *   strategy_out   host (may be NULL): RV_VOTE_GLOBAL or RV_VOTE_BRICK.
- *   ms_out         host float[2] (may be NULL): mean wall time per solve of
- *                  {global, brick} in ms; -1 for a strategy not available.
+ *   strategy_out   host (may be NULL): RV_VOTE_GLOBAL, RV_VOTE_BRICK or RV_VOTE_KEYS.
+ *   ms_out         host float[3] (may be NULL): mean wall time per solve of
+ *                  {global, brick, keys} in ms; -1 for a strategy not available.
  * Needs n >= 1; reps in 1..1000. */
 rv_status rot_vote_tune(rv_handle *h, const float *x, const float *y, int64_t n, int32_t grid,
                         float eps_rad, int32_t reps, uint8_t *mask_scratch, int32_t *strategy_out,
-                        float ms_out[2]);
+                        float ms_out[3]);
 
 /* Several rotations from one vote (Alg. 1 returning several high peaks; one
  * cluster point per rotation motion in the scene).  The vote, top-K and decode
@@ -328,7 +337,9 @@ rv_status rot_vote_solve_rigid(rv_handle *h, const float *x, const float *y, int
  * instance; the instances share grid, J, K and eps).  Instance b is the
  * column range [offsets[b], offsets[b+1]) of the SoA arrays x and y, which
  * hold n = offsets[B] columns; each instance gets exactly the result a
- * separate rot_vote_solve on its columns would give.
+ * separate rot_vote_solve on its columns would give.  The batch is planned on
+ * the device (rot_vote_solve_batch_async); this call uploads the offsets,
+ * runs it and reads the results back.
  *   offsets       host int64[B+1], offsets[0] = 0, nondecreasing, offsets[B] <= max_n.
  *   B             0..max_batch instances (0 is a no-op).
  *   grid          1..min(max_grid, RV_MAX_BATCH_GRID).
@@ -341,15 +352,64 @@ rv_status rot_vote_solve_batch(rv_handle *h, const float *x, const float *y, con
                                int32_t B, int32_t grid, float eps_rad, float *q_out,
                                int64_t *inlier_count, uint8_t *inlier_mask);
 
-/* Brick size chosen by measurement for batches: times `reps` batched solves
- * of this batch (after one untimed) with 32^3 and with 16^3 bricks and keeps
- * the faster for this grid (results are the same either way).  Arguments as
- * rot_vote_solve_batch; mask_scratch is its inlier_mask.  edge_out (host, may
- * be NULL): 16 or 32; ms_out (host float[2], may be NULL): mean wall time per
- * batch of {32, 16}.  RV_EINVAL when the config fixes batch_brick_edge. */
+/* rot_vote_solve_batch without a host round trip (Sec. 4.3: every
+ * correspondence's circle is voted independently, so the instances are data
+ * parallel): the offsets are read on the device, where one kernel plans the
+ * whole batch (each instance's brick size from its size bucket and the
+ * handle's batch schedule, its work units of up to 512 correspondences, its
+ * queue capacities and pool offsets), and every later kernel is launched for
+ * upper bounds and skips what the plan left empty.  Nothing waits for the
+ * host and nothing is allocated, so a batch can be captured into a HIP graph
+ * and replayed on new offsets and new columns of the same arrays.
+ *   x, y            device float32 SoA [3][n_cols]; n_cols 0..max_n.
+ *   offsets_device  device int64[B+1]: offsets[0] = 0, nondecreasing,
+ *                   offsets[B] <= n_cols, every instance's n*J <= 2^31-1.
+ *   B               1..max_batch (0 is a no-op); grid as rot_vote_solve_batch.
+ *   results_device  device rv_result[B], 8-byte aligned: instance b's q,
+ *                   count, winner and candidates rescored.
+ *   inlier_mask     device uint8[n_cols]; entries past offsets[B] are untouched.
+ * Offsets that break their rules are detected on the device: every result
+ * then has winner -2, count 0, q = (1,0,0,0), and no mask entry is written.
+ * The first batch at a new J synchronises the stream to upload the sample
+ * table (as rot_vote_solve_async does): run one before capturing.  The
+ * handle's batch scratch is shared by its calls, which its stream orders;
+ * rot_vote_get_batch_topk synchronises and then describes this batch. */
+rv_status rot_vote_solve_batch_async(rv_handle *h, const float *x, const float *y, int64_t n_cols,
+                                     const int64_t *offsets_device, int32_t B, int32_t grid,
+                                     float eps_rad, rv_result *results_device,
+                                     uint8_t *inlier_mask);
+
+/* The batch schedule at a grid: the brick edge (16 or 32 cells) of the
+ * instances in each size bucket (RV_BATCH_BUCKETS entries).  Results are the
+ * same under every schedule; only the speed changes.  Set: RV_EINVAL when the
+ * config fixes batch_brick_edge or an edge is not 16 or 32.  Get: the edges
+ * in force (the config's, the schedule set, tuned or loaded, else 32). */
+rv_status rot_vote_set_batch_schedule(rv_handle *h, int32_t grid, const int32_t *edges);
+rv_status rot_vote_get_batch_schedule(rv_handle *h, int32_t grid, int32_t *edges);
+
+/* The batch schedule chosen by measurement on this batch: starting from 32^3
+ * bricks for every size bucket, each bucket that has instances here in turn
+ * takes 16^3 bricks if the whole batch then runs faster (`reps` timed
+ * batches after one untimed, per trial); the faster schedule is kept for
+ * this grid.  Arguments as rot_vote_solve_batch; mask_scratch is its
+ * inlier_mask.  edges_out (host int32[RV_BATCH_BUCKETS], may be NULL): the
+ * schedule kept; ms_out (host float[RV_BATCH_BUCKETS + 1], may be NULL): the
+ * mean batch time with 32^3 everywhere, then after trying each bucket at
+ * 16^3 (-1 for a bucket without instances).  RV_EINVAL when the config fixes
+ * batch_brick_edge. */
 rv_status rot_vote_tune_batch(rv_handle *h, const float *x, const float *y, const int64_t *offsets,
                               int32_t B, int32_t grid, float eps_rad, int32_t reps,
-                              uint8_t *mask_scratch, int32_t *edge_out, float ms_out[2]);
+                              uint8_t *mask_scratch, int32_t *edges_out, float *ms_out);
+
+/* The choices made by measurement (rot_vote_tune's vote strategy per grid,
+ * the batch schedules) in a JSON file keyed by (GPU architecture, grid, J,
+ * instance-size bucket).  Save merges the handle's choices into the file
+ * (entries of other keys are kept; written to path.tmp, then renamed).  Load
+ * applies the file's entries for this GPU's architecture and the handle's J
+ * at each grid; *applied (may be NULL) counts them.  RV_EINVAL for a file
+ * that cannot be read or written or is not a tuning file. */
+rv_status rot_vote_save_tuning(rv_handle *h, const char *path);
+rv_status rot_vote_load_tuning(rv_handle *h, const char *path, int32_t *applied);
 
 /* Test hook (RV_FLAG_BATCH_GRIDS): copies instance b's vote grid of the last
  * batch to the device buffer dst (grid^3 int32). */
@@ -390,25 +450,33 @@ rv_status rot_vote_get_timings(rv_handle *h, float *ms);
 rv_status rot_vote_get_footprint(const rv_handle *h, int64_t *device_bytes);
 
 /* ---------------------------------------------------------------- serving
- * A request server: worker threads, each with its own HIP stream (default
- * priority) and its own handle, take requests from one FIFO queue.  A worker
- * that takes a request with grid <= RV_MAX_BATCH_GRID and n <= batch_max_n
- * also takes the queued requests of the same grid and eps (oldest first, up to
- * max_batch of them and max_n columns in all), gathers their columns and runs
- * them as one rot_vote_solve_batch; any other request runs alone
- * (rot_vote_solve, then rot_vote_refine if asked).  A request's result does
- * not depend on what it was batched with: every path gives exactly
- * rot_vote_solve's result.  Admission: each worker's handle holds the whole
- * scratch of one request (or batch) in flight, so requests in flight never
- * exceed `workers`; with hbm_budget > 0 the server starts only as many workers
- * as fit in that many device bytes (RV_ENOMEM if not even one does); beyond
- * max_queue waiting requests a submission returns RV_EAGAIN.  Times are
- * seconds of the host's monotonic clock (CLOCK_MONOTONIC). */
+ * A request server with admission by device-memory footprint.  A request's
+ * footprint is the scratch its solve needs: the G^3 int32 vote grid (1, 8 or
+ * 64 MiB at G = 64, 128, 256) and, for grids solved by the brick strategy,
+ * a run pool sized for its n (rot_vote_server_request_bytes).  All of it
+ * comes from one device arena of hbm_budget bytes allocated at create.  The
+ * server admits the oldest queued request as soon as one of its `workers`
+ * lanes (a thread with its own HIP stream, default priority, and handle) is
+ * free and the footprint fits in the arena's free bytes; the lane runs it
+ * (rot_vote_solve, then rot_vote_refine if asked) while the next requests
+ * are admitted on other lanes, so work in flight is bounded by memory, and
+ * many small requests run on the device beside a large one.  A finished
+ * request returns its bytes to the arena at once.  Requests are admitted in
+ * arrival order: one that does not fit yet holds back the ones behind it.
+ * Continuous batching: an admitted request with grid <= RV_MAX_BATCH_GRID
+ * and n <= batch_max_n (and no refinement) takes the queued requests of the
+ * same grid and eps with it (oldest first, up to max_batch of them and max_n
+ * columns in all), gathered into one rot_vote_solve_batch whose run pool and
+ * gathered columns are its footprint.  A request's result does not depend on
+ * where or with what it ran: every path gives exactly rot_vote_solve's
+ * result.  Beyond max_queue waiting requests a submission returns
+ * RV_EAGAIN; a request whose footprint exceeds the arena is refused with
+ * RV_ENOMEM.  Times are seconds of the host's monotonic clock. */
 typedef struct rv_server rv_server;
 
 typedef struct rv_server_config {
     int32_t device;
-    int32_t workers;             /* 1..16 */
+    int32_t workers;             /* lanes: requests (or fused batches) run at once, 1..64 */
     int64_t max_n;               /* largest request (and largest batch, in columns) */
     int32_t max_grid;
     int32_t topk;                /* K of every solve */
@@ -416,9 +484,16 @@ typedef struct rv_server_config {
     int32_t max_batch;           /* requests fused into one batched solve; 0 or 1: never */
     int64_t batch_max_n;         /* requests with n up to this (and grid <= 64) may be fused */
     int64_t max_queue;           /* waiting requests before RV_EAGAIN */
-    int64_t hbm_budget;          /* device bytes for all workers' scratch; 0: no limit */
+    int64_t hbm_budget;          /* bytes of the scratch arena shared by the requests in
+                                    flight; 0: room for `workers` requests of the largest size */
     int32_t reserved[4];         /* must be 0 */
 } rv_server_config;
+
+enum {
+    RV_REQ_AFTER_STREAM = 1u  /* the request's kernels start after the work enqueued on
+                                 rv_request.stream before the submission (the producer of
+                                 x and y), through an event recorded at submit */
+};
 
 typedef struct rv_request {
     const float *x;              /* device float32 [3][n] SoA, as rot_vote_solve */
@@ -428,7 +503,8 @@ typedef struct rv_request {
     float eps_rad;
     uint8_t *inlier_mask;        /* device uint8[n], written by the request */
     int32_t refine_rounds;       /* 0: none; else rot_vote_refine after the solve */
-    int32_t reserved;
+    uint32_t flags;              /* RV_REQ_* */
+    void *stream;                /* hipStream_t for RV_REQ_AFTER_STREAM (NULL: null stream) */
 } rv_request;
 
 typedef struct rv_reply {
@@ -436,28 +512,40 @@ typedef struct rv_reply {
     int64_t inlier_count;
     int32_t status;              /* the solve's rv_status */
     int32_t batched;             /* requests in its solve (1: alone) */
-    int32_t worker;
+    int32_t worker;              /* the lane that ran it */
     int32_t refine_rounds_run;
     double t_submit, t_start, t_end;
+    int64_t scratch_bytes;       /* arena bytes its solve held (shared when batched) */
 } rv_reply;
 
-/* Fills *cfg: device 0, 2 workers, max_n 1<<20, max_grid 256, K 16, J = 8G,
- * max_batch 64, batch_max_n 65536, max_queue 1<<20, no budget. */
+/* Fills *cfg: device 0, 4 lanes, max_n 1<<20, max_grid 256, K 16, J = 8G,
+ * max_batch 64, batch_max_n 65536, max_queue 1<<20, hbm_budget 0. */
 void rot_vote_server_default_config(rv_server_config *cfg);
+/* Creates the lanes and the arena; RV_ENOMEM if they do not fit. */
 rv_status rot_vote_server_create(rv_server **out, const rv_server_config *cfg);
-/* Waits for the queue to drain, stops the workers, frees everything.  NULL is
- * a no-op.  Replies not collected are dropped. */
+/* Serves the queued requests (admission resumes if paused), stops the lanes,
+ * frees everything.  NULL is a no-op.  Replies not collected are dropped. */
 rv_status rot_vote_server_destroy(rv_server *s);
 /* Validates the request (as rot_vote_solve would) and queues it; *ticket
  * identifies it for rot_vote_server_wait.  The buffers must stay valid until
- * the reply is collected. */
+ * the reply is collected; the mask is complete when the reply is. */
 rv_status rot_vote_server_submit(rv_server *s, const rv_request *req, uint64_t *ticket);
 /* Waits up to timeout_ms (< 0: forever) for the request and collects its reply
  * (once).  RV_ETIMEDOUT leaves it pending. */
 rv_status rot_vote_server_wait(rv_server *s, uint64_t ticket, int32_t timeout_ms, rv_reply *out);
-/* Workers started and their device bytes; requests queued and in flight. */
+/* Lanes and device bytes (lanes' own scratch plus the arena); requests queued
+ * and in flight. */
 rv_status rot_vote_server_stats(rv_server *s, int32_t *workers, int64_t *device_bytes,
                                 int64_t *queued, int64_t *in_flight);
+/* The arena's size, bytes held by requests in flight now and at most so far,
+ * and the most requests in flight at once so far (any pointer may be NULL). */
+rv_status rot_vote_server_memory(rv_server *s, int64_t *arena_bytes, int64_t *in_use,
+                                 int64_t *peak_in_use, int64_t *peak_in_flight);
+/* paused != 0 stops admitting (submissions still queue); 0 resumes. */
+rv_status rot_vote_server_pause(rv_server *s, int32_t paused);
+/* The footprint a request of n correspondences at this grid is admitted with
+ * when it runs alone. */
+rv_status rot_vote_server_request_bytes(rv_server *s, int64_t n, int32_t grid, int64_t *bytes);
 const char *rot_vote_server_last_error(const rv_server *s);
 
 #ifdef __cplusplus

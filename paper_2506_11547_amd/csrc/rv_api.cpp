@@ -49,6 +49,10 @@ constexpr int kStages = RV_NUM_STAGES;
 // (one kernel, no queues) measured faster than binning: the solves there are
 // small enough that binning's extra stages cost more than its atomics save.
 constexpr int kBrickMinGrid = 72;
+// At and below this many samples per grid step (J <= kKeysMaxRatio * G) the
+// automatic choice among the binned strategies takes keys: the circle then
+// crosses a new cell at nearly every sample, so run merging saves nothing.
+constexpr int kKeysMaxRatio = 2;
 // Batch queue capacities: a brick's share of the instance's expected runs,
 // times this factor (the heaviest brick of an instance with half inliers
 // holds about 1.75 shares at G = 64), plus a fixed slack.
@@ -110,15 +114,17 @@ struct rv_handle {
     int32_t batch_grid = 0;             // largest grid of a batch
     int64_t max_units = 0;
     bool batch_grids = false;           // RV_FLAG_BATCH_GRIDS
-    rv::Unit* d_units = nullptr;        // max_units
-    rv::Unit* h_units = nullptr;        // pinned staging
-    uint32_t* d_bplan = nullptr;        // [cap | qbase], 2 * max_batch * 8
-    uint32_t* h_bplan = nullptr;        // pinned staging
     int64_t* d_offsets = nullptr;       // max_batch + 1
     int64_t* h_offsets = nullptr;       // pinned staging
-    uint32_t* d_bfill = nullptr;        // max_batch * 8
-    uint32_t* d_bflags = nullptr;       // max_batch * 8
-    uint64_t* d_bpartial = nullptr;     // max_batch * 8 * 64
+    rv::InstPlan* d_iplan = nullptr;    // max_batch
+    int32_t* d_bcounts = nullptr;       // the plan's counts (8)
+    rv::Unit* d_units_all = nullptr;    // max_units
+    // per brick-size class (0: 16^3 bricks, 1: 32^3)
+    int32_t cls_nb[2] = {0, 0};         // largest bricks per instance of the class
+    rv::Unit* d_cunits[2] = {};         // max_units each
+    int32_t* d_inst_of[2] = {};         // max_batch each
+    uint32_t* d_cq[2] = {};             // cap | qbase | fill | flags, 4 * max_batch * cls_nb
+    uint64_t* d_cpartial[2] = {};       // max_batch * cls_nb * 64
     float4* d_bcand_q = nullptr;        // max_batch * 64
     int32_t* d_bcand_votes = nullptr;
     int32_t* d_bcand_idx = nullptr;
@@ -147,6 +153,7 @@ struct rv_handle {
     double* d_rpartial = nullptr;         // kRefineMaxBlocks * kRefineSums
 
     hipEvent_t ev[kStages + 1] = {};
+    hipEvent_t ev_switch = nullptr;      // orders a stream change (rot_vote_set_stream)
     bool timing = false;
     bool events_recorded = false;
 
@@ -162,12 +169,18 @@ struct rv_handle {
     // last batch
     bool batched = false;
     int32_t last_B = 0;
-    int32_t last_batch_edge = 0;
+    bool last_batch_async = false;      // h_bresult is read back on demand
     int32_t last_bgrid = 0;
 
     int64_t device_bytes = 0;           // sum of the handle's device allocations
+    // A server lane: the grid and the run pool are not the handle's but bound
+    // per solve from the server's arena (rv::lane_bind); never freed here.
+    bool lane = false;
     int8_t tuned[RV_MAX_GRID + 1] = {};  // per grid: strategy chosen by rot_vote_tune (0: none)
-    int8_t batch_edge_log2[RV_MAX_BATCH_GRID + 1] = {};  // per grid: by rot_vote_tune_batch (0: none)
+    // per grid and instance-size bucket: brick edge (log2) of a batch's
+    // instances, set by rot_vote_tune_batch, rot_vote_set_batch_schedule or a
+    // loaded tuning file (0: not set)
+    int8_t sched[RV_MAX_BATCH_GRID + 1][rv::kBatchBuckets] = {};
     int32_t forced_strategy = 0;         // while tuning
 
     std::string err;
@@ -214,7 +227,8 @@ void release(rv_handle* h)
         return;
     (void)hipSetDevice(h->device);
     (void)hipStreamSynchronize(h->stream);  // scratch may still be in use by queued work
-    (void)hipFree(h->d_hist);
+    if (!h->lane)
+        (void)hipFree(h->d_hist);
     (void)hipFree(h->d_table);
     (void)hipFree(h->d_partial);
     (void)hipFree(h->d_cand_q);
@@ -223,7 +237,8 @@ void release(rv_handle* h)
     (void)hipFree(h->d_cand_inl);
     (void)hipFree(h->d_result);
     (void)hipFree(h->d_empty);
-    (void)hipFree(h->bin.pool);
+    if (!h->lane)
+        (void)hipFree(h->bin.pool);
     (void)hipFree(h->bin.fill);
     (void)hipFree(h->bin.qbase);
     (void)hipFree(h->bin.cap);
@@ -231,12 +246,16 @@ void release(rv_handle* h)
     (void)hipFree(h->bin.flags);
     (void)hipFree(h->bin.order);
     (void)hipFree(h->d_ovf);
-    (void)hipFree(h->d_units);
-    (void)hipFree(h->d_bplan);
     (void)hipFree(h->d_offsets);
-    (void)hipFree(h->d_bfill);
-    (void)hipFree(h->d_bflags);
-    (void)hipFree(h->d_bpartial);
+    (void)hipFree(h->d_iplan);
+    (void)hipFree(h->d_bcounts);
+    (void)hipFree(h->d_units_all);
+    for (int c = 0; c < 2; ++c) {
+        (void)hipFree(h->d_cunits[c]);
+        (void)hipFree(h->d_inst_of[c]);
+        (void)hipFree(h->d_cq[c]);
+        (void)hipFree(h->d_cpartial[c]);
+    }
     (void)hipFree(h->d_bcand_q);
     (void)hipFree(h->d_bcand_votes);
     (void)hipFree(h->d_bcand_idx);
@@ -255,8 +274,6 @@ void release(rv_handle* h)
     (void)hipFree(h->d_rstate);
     (void)hipFree(h->d_rpartial);
     (void)hipHostFree(h->h_rstate);
-    (void)hipHostFree(h->h_units);
-    (void)hipHostFree(h->h_bplan);
     (void)hipHostFree(h->h_offsets);
     (void)hipHostFree(h->h_bresult);
     (void)hipHostFree(h->h_result);
@@ -264,6 +281,8 @@ void release(rv_handle* h)
     for (auto& e : h->ev)
         if (e)
             (void)hipEventDestroy(e);
+    if (h->ev_switch)
+        (void)hipEventDestroy(h->ev_switch);
 }
 
 // Step 0 of the rule: theta_j = ((2j + 1 - J) / J) * (pi / 2) in binary64,
@@ -301,7 +320,9 @@ RV_API void rot_vote_default_config(rv_config* cfg)
     cfg->batch_brick_edge = 0;
 }
 
-RV_API rv_status rot_vote_create(rv_handle** out, const rv_config* cfg)
+namespace {
+
+rv_status create_impl(rv_handle** out, const rv_config* cfg, bool lane)
 {
     if (!out || !cfg)
         return fail(nullptr, RV_EINVAL, "rot_vote_create: NULL argument");
@@ -313,7 +334,7 @@ RV_API rv_status rot_vote_create(rv_handle** out, const rv_config* cfg)
         return fail(nullptr, RV_EINVAL, "rot_vote_create: samples_per_circle < 0");
     if (cfg->topk < 1 || cfg->topk > RV_MAX_TOPK)
         return fail(nullptr, RV_EINVAL, "rot_vote_create: topk outside 1..64");
-    if (cfg->vote_strategy < RV_VOTE_AUTO || cfg->vote_strategy > RV_VOTE_BRICK)
+    if (cfg->vote_strategy < RV_VOTE_AUTO || cfg->vote_strategy > RV_VOTE_KEYS)
         return fail(nullptr, RV_EINVAL, "rot_vote_create: unknown vote_strategy");
     if (cfg->flags & ~(uint32_t)(RV_FLAG_TIMING | RV_FLAG_BATCH_GRIDS))
         return fail(nullptr, RV_EINVAL, "rot_vote_create: unknown flags");
@@ -336,6 +357,7 @@ RV_API rv_status rot_vote_create(rv_handle** out, const rv_config* cfg)
     if (!h)
         return fail(nullptr, RV_ENOMEM, "rot_vote_create: out of host memory");
     h->cfg = *cfg;
+    h->lane = lane;
     h->device = cfg->device;
     h->stream = static_cast<hipStream_t>(cfg->stream);
     h->max_n = cfg->max_n;
@@ -354,7 +376,7 @@ RV_API rv_status rot_vote_create(rv_handle** out, const rv_config* cfg)
     if ((e = hipSetDevice(h->device)) != hipSuccess)
         return bail(e, "hipSetDevice");
     const size_t ncell = (size_t)h->max_grid * h->max_grid * h->max_grid;
-    if ((e = dev_alloc(h, &h->d_hist, ncell * sizeof(int32_t))) != hipSuccess)
+    if (!lane && (e = dev_alloc(h, &h->d_hist, ncell * sizeof(int32_t))) != hipSuccess)
         return bail(e, "vote grid");
     if ((e = dev_alloc(h, &h->d_table, (size_t)h->max_J * sizeof(float2))) != hipSuccess)
         return bail(e, "sample table");
@@ -383,13 +405,16 @@ RV_API rv_status rot_vote_create(rv_handle** out, const rv_config* cfg)
     for (auto& ev : h->ev)
         if ((e = hipEventCreate(&ev)) != hipSuccess)
             return bail(e, "events");
+    if ((e = hipEventCreateWithFlags(&h->ev_switch, hipEventDisableTiming)) != hipSuccess)
+        return bail(e, "events");
     if ((e = dev_alloc(h, &h->d_rstate, sizeof(rv::RefineState))) != hipSuccess ||
         (e = dev_alloc(h, &h->d_rpartial,
                        (size_t)rv::kRefineMaxBlocks * rv::kRefineSums * sizeof(double))) != hipSuccess)
         return bail(e, "refinement scratch");
     if ((e = hipHostMalloc(&h->h_rstate, sizeof(rv::RefineState), hipHostMallocDefault)) != hipSuccess)
         return bail(e, "pinned refinement state");
-    if ((e = dev_alloc(h, &h->d_mbits, (size_t)std::max<int64_t>(1, h->max_n) * sizeof(uint64_t))) !=
+    if ((e = dev_alloc(h, &h->d_mbits,
+                       (size_t)std::max<int64_t>(1, lane ? 1 : h->max_n) * sizeof(uint64_t))) !=
             hipSuccess ||
         (e = dev_alloc(h, &h->d_mstate, sizeof(rv::MultiState))) != hipSuccess)
         return bail(e, "model scratch");
@@ -432,6 +457,8 @@ RV_API rv_status rot_vote_create(rv_handle** out, const rv_config* cfg)
         runs = std::max(runs, b);
     }
     runs = std::min<uint64_t>(runs, 0xFFFFFFFFull - 64);
+    if (lane)
+        runs = 0;  // bound per solve
     h->bin.pool_runs = runs;
     if (runs > 0 && (e = dev_alloc(h, &h->bin.pool, runs * sizeof(uint32_t))) != hipSuccess)
         return bail(e, "brick run pool");
@@ -458,16 +485,24 @@ RV_API rv_status rot_vote_create(rv_handle** out, const rv_config* cfg)
     }
     if (h->max_batch > 0) {
         const int64_t B = h->max_batch;
-        const int64_t nq = B * rv::kMaxBatchBricks;
         const int64_t bg = h->batch_grid;
         const size_t gcells = (size_t)B * (size_t)(bg * bg * bg);
         h->max_units = (h->max_n + rv::kUnitSize - 1) / rv::kUnitSize + B;
-        if ((e = dev_alloc(h, &h->d_units, (size_t)h->max_units * sizeof(rv::Unit))) != hipSuccess ||
-            (e = dev_alloc(h, &h->d_bplan, (size_t)(2 * nq) * sizeof(uint32_t))) != hipSuccess ||
+        for (int c = 0; c < 2; ++c) {
+            const int nba = rv::brick_axis((int)bg, c == 0 ? 4 : 5);
+            h->cls_nb[c] = nba * nba * nba;
+            const size_t q = (size_t)B * h->cls_nb[c];
+            if ((e = dev_alloc(h, &h->d_cunits[c], (size_t)h->max_units * sizeof(rv::Unit))) !=
+                    hipSuccess ||
+                (e = dev_alloc(h, &h->d_inst_of[c], (size_t)B * sizeof(int32_t))) != hipSuccess ||
+                (e = dev_alloc(h, &h->d_cq[c], 4 * q * sizeof(uint32_t))) != hipSuccess ||
+                (e = dev_alloc(h, &h->d_cpartial[c], q * 64 * sizeof(uint64_t))) != hipSuccess)
+                return bail(e, "batch class scratch");
+        }
+        if ((e = dev_alloc(h, &h->d_units_all, (size_t)h->max_units * sizeof(rv::Unit))) != hipSuccess ||
             (e = dev_alloc(h, &h->d_offsets, (size_t)(B + 1) * sizeof(int64_t))) != hipSuccess ||
-            (e = dev_alloc(h, &h->d_bfill, (size_t)nq * sizeof(uint32_t))) != hipSuccess ||
-            (e = dev_alloc(h, &h->d_bflags, (size_t)nq * sizeof(uint32_t))) != hipSuccess ||
-            (e = dev_alloc(h, &h->d_bpartial, (size_t)nq * 64 * sizeof(uint64_t))) != hipSuccess ||
+            (e = dev_alloc(h, &h->d_iplan, (size_t)B * sizeof(rv::InstPlan))) != hipSuccess ||
+            (e = dev_alloc(h, &h->d_bcounts, 8 * sizeof(int32_t))) != hipSuccess ||
             (e = dev_alloc(h, &h->d_bcand_q, (size_t)B * 64 * sizeof(float4))) != hipSuccess ||
             (e = dev_alloc(h, &h->d_bcand_votes, (size_t)B * 64 * sizeof(int32_t))) != hipSuccess ||
             (e = dev_alloc(h, &h->d_bcand_idx, (size_t)B * 64 * sizeof(int32_t))) != hipSuccess ||
@@ -477,11 +512,7 @@ RV_API rv_status rot_vote_create(rv_handle** out, const rv_config* cfg)
             return bail(e, "batch scratch");
         if (h->batch_grids && (e = dev_alloc(h, &h->d_bgrids, gcells * sizeof(int32_t))) != hipSuccess)
             return bail(e, "batch grids");
-        if ((e = hipHostMalloc(&h->h_units, (size_t)h->max_units * sizeof(rv::Unit),
-                               hipHostMallocDefault)) != hipSuccess ||
-            (e = hipHostMalloc(&h->h_bplan, (size_t)(2 * nq) * sizeof(uint32_t),
-                               hipHostMallocDefault)) != hipSuccess ||
-            (e = hipHostMalloc(&h->h_offsets, (size_t)(B + 1) * sizeof(int64_t),
+        if ((e = hipHostMalloc(&h->h_offsets, (size_t)(B + 1) * sizeof(int64_t),
                                hipHostMallocDefault)) != hipSuccess ||
             (e = hipHostMalloc(&h->h_bresult, (size_t)B * sizeof(rv::Result),
                                hipHostMallocDefault)) != hipSuccess)
@@ -492,6 +523,94 @@ RV_API rv_status rot_vote_create(rv_handle** out, const rv_config* cfg)
     }
     *out = h;
     return RV_OK;
+}
+
+// The vote strategy a solve at this grid uses.
+int pick_strategy(const rv_handle* h, int grid)
+{
+    int strategy = h->forced_strategy ? h->forced_strategy : h->cfg.vote_strategy;
+    if (strategy == RV_VOTE_AUTO && h->tuned[grid] != 0)
+        strategy = h->tuned[grid];  // measured by rot_vote_tune
+    if (strategy == RV_VOTE_AUTO) {
+        const int J = h->cfg.samples_per_circle > 0 ? h->cfg.samples_per_circle : 8 * grid;
+        strategy = !(h->brick_ok && grid >= kBrickMinGrid && grid <= rv::kMaxBrickGrid)
+                       ? RV_VOTE_GLOBAL
+                       : (J <= kKeysMaxRatio * grid ? RV_VOTE_KEYS : RV_VOTE_BRICK);
+    }
+    return strategy;
+}
+
+int64_t align256(int64_t b) { return (b + 255) & ~(int64_t)255; }
+
+// Brick edge (log2) of a batch instance in size bucket k at this grid: fixed
+// by the config, else the schedule (tuned, set or loaded), else 32.
+int batch_edge_log2(const rv_handle* h, int grid, int k)
+{
+    return h->cfg.batch_brick_edge == 16   ? 4
+           : h->cfg.batch_brick_edge == 32 ? 5
+           : h->sched[grid][k]             ? h->sched[grid][k]
+                                           : 5;
+}
+
+}  // namespace
+
+RV_API rv_status rot_vote_create(rv_handle** out, const rv_config* cfg)
+{
+    return create_impl(out, cfg, false);
+}
+
+rv_status rv::create_lane(rv_handle** out, const rv_config* cfg)
+{
+    if (cfg && cfg->max_pairs != 0)
+        return fail(nullptr, RV_EINVAL, "server lane: no pair buffers");
+    if (cfg && (cfg->flags & RV_FLAG_BATCH_GRIDS))
+        return fail(nullptr, RV_EINVAL, "server lane: no kept batch grids");
+    return create_impl(out, cfg, true);
+}
+
+int64_t rv::lane_solve_bytes(const rv_handle* h, int64_t n, int32_t grid)
+{
+    if (grid < 1 || grid > h->max_grid || n < 0)
+        return -1;
+    const int64_t G = grid;
+    const int64_t gbytes = align256(G * G * G * (int64_t)sizeof(int32_t));
+    const int strategy = pick_strategy(h, grid);
+    if (n == 0 || strategy == RV_VOTE_GLOBAL)
+        return gbytes;
+    const int J = h->cfg.samples_per_circle > 0 ? h->cfg.samples_per_circle : 8 * grid;
+    const bool keys = strategy == RV_VOTE_KEYS;
+    const int nba = rv::brick_axis(grid, keys ? 5 : rv::solve_edge_log2(grid));
+    const int64_t nb = (int64_t)nba * nba * nba;
+    // the plan asks for 1.15 x the estimated runs (keys: samples) plus 256..319
+    // per queue
+    const int64_t per_circle =
+        (int64_t)std::ceil(1.25 * (double)(keys ? J : runs_per_circle(grid, J)));
+    const int64_t runs = std::min<int64_t>(n * per_circle + rv::kQueueSets * nb * 320,
+                                           (int64_t)0xFFFFFFFFll - 64);
+    return gbytes + align256(runs * (int64_t)sizeof(uint32_t));
+}
+
+int64_t rv::lane_batch_bytes(const rv_handle* h, int64_t cols, int32_t B, int32_t grid)
+{
+    if (grid < 1 || grid > h->batch_grid || B < 1 || B > h->max_batch || cols < 0)
+        return -1;
+    const int J = h->cfg.samples_per_circle > 0 ? h->cfg.samples_per_circle : 8 * grid;
+    // the batch plan: ceil(share * n_b) + slack, rounded up to 64, per (instance,
+    // brick), with the more queues of the two brick sizes
+    const int nba = rv::brick_axis(grid, 4);
+    const int64_t nb = (int64_t)nba * nba * nba;
+    const int64_t runs = std::min<int64_t>(
+        (int64_t)std::ceil(kBatchCapFactor * (double)runs_per_circle(grid, J) * (double)cols) +
+            (int64_t)B * nb * (256 + 64 + 1),
+        (int64_t)0xFFFFFFFFll - 64);
+    return align256(runs * (int64_t)sizeof(uint32_t));
+}
+
+void rv::lane_bind(rv_handle* h, int32_t* grid, uint32_t* pool, uint64_t pool_runs)
+{
+    h->d_hist = grid;
+    h->bin.pool = pool;
+    h->bin.pool_runs = std::min<uint64_t>(pool_runs, 0xFFFFFFFFull - 64);
 }
 
 RV_API rv_status rot_vote_destroy(rv_handle* h)
@@ -515,8 +634,15 @@ RV_API rv_status rot_vote_set_stream(rv_handle* h, void* stream)
 {
     if (!h)
         return RV_EINVAL;
-    h->stream = static_cast<hipStream_t>(stream);
     h->err.clear();
+    hipStream_t next = static_cast<hipStream_t>(stream);
+    if (next != h->stream) {
+        // the handle's scratch may still be in use by work on the old stream
+        RV_HIP(h, hipSetDevice(h->device), "hipSetDevice");
+        RV_HIP(h, hipEventRecord(h->ev_switch, h->stream), "event on the old stream");
+        RV_HIP(h, hipStreamWaitEvent(next, h->ev_switch, 0), "wait on the new stream");
+        h->stream = next;
+    }
     return RV_OK;
 }
 
@@ -558,15 +684,11 @@ rv_status vote_candidates(rv_handle* h, const float* x, const float* y, int64_t 
     const std::string f(fn);
     hipStream_t s = h->stream;
     const int64_t ncell = (int64_t)grid * grid * grid;
-    int strategy = h->forced_strategy ? h->forced_strategy : h->cfg.vote_strategy;
-    if (strategy == RV_VOTE_AUTO && h->tuned[grid] != 0)
-        strategy = h->tuned[grid];  // measured by rot_vote_tune
-    if (strategy == RV_VOTE_AUTO)
-        strategy = (h->brick_ok && grid >= kBrickMinGrid && grid <= rv::kMaxBrickGrid)
-                       ? RV_VOTE_BRICK : RV_VOTE_GLOBAL;
-    if (strategy == RV_VOTE_BRICK && !(h->brick_ok && grid <= rv::kMaxBrickGrid))
+    const int strategy = pick_strategy(h, grid);
+    if (strategy != RV_VOTE_GLOBAL && !(h->brick_ok && grid <= rv::kMaxBrickGrid))
         return fail(h, RV_EUNSUPPORTED,
-                    f + ": the brick strategy needs grid <= 384 and a handle created for it");
+                    f + ": the brick and key strategies need grid <= 384 and a handle created "
+                        "for them");
 
     if (h->table_J != J) {
         RV_HIP(h, hipStreamSynchronize(s), "sync before table upload");
@@ -578,7 +700,8 @@ rv_status vote_candidates(rv_handle* h, const float* x, const float* y, int64_t 
     }
 
     const bool tm = h->timing;
-    const bool brick = strategy == RV_VOTE_BRICK;
+    const bool keys = strategy == RV_VOTE_KEYS;
+    const bool brick = strategy == RV_VOTE_BRICK || keys;
     h->solved = true;
     h->last_async = false;
     h->last_grid = grid;
@@ -586,15 +709,17 @@ rv_status vote_candidates(rv_handle* h, const float* x, const float* y, int64_t 
     h->last_strategy = strategy;
     if (tm)
         RV_HIP(h, hipEventRecord(h->ev[0], s), "event");
-    const int edge = rv::solve_edge_log2(grid);
+    const int edge = keys ? 5 : rv::solve_edge_log2(grid);
     if (brick)
-        RV_HIP(h, rv::launch_bin_prepare(x, y, n, grid, J, edge, h->d_table, h->bin, s),
+        RV_HIP(h, rv::launch_bin_prepare(x, y, n, grid, J, edge, h->d_table, h->bin, s, keys),
                "brick plan");
     else
         RV_HIP(h, rv::launch_fill(h->d_hist, ncell, 0, s), "clear grid");
     if (tm)
         RV_HIP(h, hipEventRecord(h->ev[1], s), "event");
-    if (brick)
+    if (keys)
+        RV_HIP(h, rv::launch_key_vote(x, y, n, grid, J, h->d_table, h->bin, s), "key vote");
+    else if (brick)
         RV_HIP(h, rv::launch_bin_vote(x, y, n, grid, J, edge, h->d_table, h->bin, s),
                "binned vote");
     else
@@ -724,7 +849,7 @@ RV_API rv_status rot_vote_solve_async(rv_handle* h, const float* x, const float*
 
 RV_API rv_status rot_vote_tune(rv_handle* h, const float* x, const float* y, int64_t n,
                                int32_t grid, float eps_rad, int32_t reps, uint8_t* mask_scratch,
-                               int32_t* strategy_out, float ms_out[2])
+                               int32_t* strategy_out, float ms_out[3])
 {
     if (!h)
         return RV_EINVAL;
@@ -737,12 +862,12 @@ RV_API rv_status rot_vote_tune(rv_handle* h, const float* x, const float* y, int
     if (rv_status st = check_solve(h, "rot_vote_tune", x, y, n, grid, eps_rad, mask_scratch, &J))
         return st;
     const bool brick_ok = h->brick_ok && grid <= rv::kMaxBrickGrid;
-    const int cand[2] = {RV_VOTE_GLOBAL, RV_VOTE_BRICK};
-    float ms[2] = {-1.0f, -1.0f};
+    const int cand[3] = {RV_VOTE_GLOBAL, RV_VOTE_BRICK, RV_VOTE_KEYS};
+    float ms[3] = {-1.0f, -1.0f, -1.0f};
     float q[4];
     int64_t cnt = 0;
-    for (int c = 0; c < 2; ++c) {
-        if (cand[c] == RV_VOTE_BRICK && !brick_ok)
+    for (int c = 0; c < 3; ++c) {
+        if (cand[c] != RV_VOTE_GLOBAL && !brick_ok)
             continue;
         h->forced_strategy = cand[c];
         rv_status st = rot_vote_solve(h, x, y, n, grid, eps_rad, q, &cnt, mask_scratch);  // warm-up
@@ -755,14 +880,15 @@ RV_API rv_status rot_vote_tune(rv_handle* h, const float* x, const float* y, int
             return st;
         ms[c] = (float)(std::chrono::duration<double, std::milli>(t1 - t0).count() / reps);
     }
-    const int best = (ms[1] >= 0.0f && ms[1] < ms[0]) ? RV_VOTE_BRICK : RV_VOTE_GLOBAL;
+    int best = RV_VOTE_GLOBAL;
+    for (int c = 1; c < 3; ++c)
+        if (ms[c] >= 0.0f && ms[c] < ms[best - 1])
+            best = cand[c];
     h->tuned[grid] = (int8_t)best;
     if (strategy_out)
         *strategy_out = best;
-    if (ms_out) {
-        ms_out[0] = ms[0];
-        ms_out[1] = ms[1];
-    }
+    if (ms_out)
+        std::memcpy(ms_out, ms, sizeof(ms));
     return RV_OK;
 }
 
@@ -1009,28 +1135,157 @@ RV_API rv_status rot_vote_solve_rigid(rv_handle* h, const float* x, const float*
     return RV_OK;
 }
 
+namespace {
+
+// Argument checks shared by the batch entry points (offsets are checked by
+// the caller where they live on the host).
+rv_status check_batch(rv_handle* h, const char* fn, int32_t B, int32_t grid, float eps_rad,
+                      int32_t* J)
+{
+    const std::string f(fn);
+    if (h->max_batch == 0)
+        return fail(h, RV_EUNSUPPORTED, f + ": handle created with max_batch = 0");
+    if (B < 0 || B > h->max_batch)
+        return fail(h, RV_EINVAL, f + ": B outside 0..max_batch");
+    if (grid < 1 || grid > h->batch_grid)
+        return fail(h, RV_EINVAL, f + ": grid outside 1..min(max_grid, 64)");
+    if (!(eps_rad > 0.0f) || !(eps_rad <= (float)M_PI))
+        return fail(h, RV_EINVAL, f + ": eps_rad outside (0, pi]");
+    *J = h->cfg.samples_per_circle > 0 ? h->cfg.samples_per_circle : 8 * grid;
+    if (*J > h->max_J)
+        return fail(h, RV_EINVAL, f + ": J = 8*grid exceeds the table sized at create");
+    return RV_OK;
+}
+
+// The whole batch on the handle's stream, from offsets in device memory:
+// plan, then per brick-size class the binned vote and the accumulation, then
+// the per-instance top-K, rescoring and masks.  Results go to `results`
+// (device, B records).  No host synchronisation (except a sample-table upload
+// at a new J).
+rv_status enqueue_batch(rv_handle* h, const float* x, const float* y, int64_t n_cols,
+                        const int64_t* d_offsets, int32_t B, int32_t grid, int32_t J, float T2,
+                        rv::Result* results, uint8_t* mask, const char* fn)
+{
+    hipStream_t s = h->stream;
+    if (h->table_J != J) {
+        RV_HIP(h, hipStreamSynchronize(s), "sync before table upload");
+        fill_table(h->h_table, J);
+        RV_HIP(h, hipMemcpyAsync(h->d_table, h->h_table, (size_t)J * sizeof(float2),
+                                 hipMemcpyHostToDevice, s),
+               "table upload");
+        h->table_J = J;
+    }
+    rv::BatchPlanArgs p{};
+    p.offsets = d_offsets;
+    p.B = B;
+    p.J = J;
+    p.n_cols = n_cols;
+    bool use[2] = {false, false};
+    for (int k = 0; k < rv::kBatchBuckets; ++k) {
+        p.bucket_edge[k] = (int8_t)batch_edge_log2(h, grid, k);
+        use[p.bucket_edge[k] == 4 ? 0 : 1] = true;
+    }
+    const int edge[2] = {4, 5};
+    int nb[2];
+    for (int c = 0; c < 2; ++c) {
+        const int nba = rv::brick_axis(grid, edge[c]);
+        nb[c] = nba * nba * nba;
+        p.nb[c] = nb[c];
+        p.share[c] = kBatchCapFactor * (double)runs_per_circle(grid, J) / (double)nb[c];
+        // slack per queue: smaller bricks, more queues per instance, less slack each
+        p.slack[c] = (uint32_t)std::min(256, std::max(64, 2048 / nb[c]));
+        const size_t q = (size_t)h->max_batch * h->cls_nb[c];
+        p.cap[c] = h->d_cq[c];
+        p.qbase[c] = h->d_cq[c] + q;
+        p.fill[c] = h->d_cq[c] + 2 * q;
+        p.flags[c] = h->d_cq[c] + 3 * q;
+        p.inst_of[c] = h->d_inst_of[c];
+        p.units[c] = h->d_cunits[c];
+    }
+    p.pool_runs = h->bin.pool_runs;
+    p.inst = h->d_iplan;
+    p.counts = h->d_bcounts;
+    p.units_all = h->d_units_all;
+    p.results = results;
+
+    const bool tm = h->timing;
+    h->batched = true;
+    h->last_B = B;
+    h->last_bgrid = grid;
+    h->last_J = J;
+    h->last_strategy = RV_VOTE_BRICK;
+    if (tm)
+        RV_HIP(h, hipEventRecord(h->ev[0], s), "event");
+    RV_HIP(h, rv::launch_batch_plan(p, s), (std::string(fn) + ": plan").c_str());
+    if (tm)
+        RV_HIP(h, hipEventRecord(h->ev[1], s), "event");
+    // launched for upper bounds: sum over instances of ceil(n_b / 512) units
+    const int64_t max_units = n_cols / rv::kUnitSize + B;
+    rv::BinArgs a[2];
+    for (int c = 0; c < 2; ++c) {
+        a[c] = h->bin;
+        a[c].fill = p.fill[c];
+        a[c].qbase = p.qbase[c];
+        a[c].cap = p.cap[c];
+        a[c].flags = p.flags[c];
+        a[c].ovf = h->d_bovf;
+        a[c].units = h->d_cunits[c];
+        a[c].counts = h->d_bcounts + 2 * c;
+        a[c].inst_of = h->d_inst_of[c];
+        a[c].nsets = 1;
+        a[c].qstride = B * nb[c];
+        a[c].batch = B;
+    }
+    for (int c = 1; c >= 0; --c)
+        if (use[c])
+            RV_HIP(h, rv::launch_bin_vote_batch(x, y, n_cols, grid, J, edge[c], h->d_table, a[c],
+                                                (int)max_units, s),
+                   "batch vote");
+    if (tm)
+        RV_HIP(h, hipEventRecord(h->ev[2], s), "event");
+    for (int c = 1; c >= 0; --c)
+        if (use[c])
+            RV_HIP(h, rv::launch_brick_accum(grid, h->K, edge[c],
+                                             h->batch_grids ? h->d_bgrids : nullptr,
+                                             h->d_cpartial[c], a[c], s),
+                   "batch brick accumulate");
+    if (tm)
+        RV_HIP(h, hipEventRecord(h->ev[3], s), "event");
+    const rv::Candidates cand{h->d_bcand_q, h->d_bcand_votes, h->d_bcand_idx, h->d_bcand_inl,
+                              results};
+    for (int c = 1; c >= 0; --c)
+        if (use[c])
+            RV_HIP(h, rv::launch_batch_topk(h->d_cpartial[c], B, nb[c], h->K, grid,
+                                            h->d_bcounts + 2 * c, h->d_inst_of[c], cand, s),
+                   "batch top-K");
+    if (tm)
+        RV_HIP(h, hipEventRecord(h->ev[4], s), "event");
+    RV_HIP(h, rv::launch_batch_rescore_mask(x, y, n_cols, T2, h->d_units_all, (int)max_units,
+                                            h->d_bcounts + 4, d_offsets, cand, mask, s,
+                                            tm ? h->ev[5] : nullptr),
+           "batch rescore and mask");
+    if (tm)
+        RV_HIP(h, hipEventRecord(h->ev[6], s), "event");
+    return RV_OK;
+}
+
+}  // namespace
+
 RV_API rv_status rot_vote_solve_batch(rv_handle* h, const float* x, const float* y,
-                                      const int64_t* offsets, int32_t B, int32_t grid, float eps_rad,
-                                      float* q_out, int64_t* inlier_count, uint8_t* inlier_mask)
+                                      const int64_t* offsets, int32_t B, int32_t grid,
+                                      float eps_rad, float* q_out, int64_t* inlier_count,
+                                      uint8_t* inlier_mask)
 {
     if (!h)
         return RV_EINVAL;
     h->err.clear();
-    if (h->max_batch == 0)
-        return fail(h, RV_EUNSUPPORTED, "rot_vote_solve_batch: handle created with max_batch = 0");
-    if (B < 0 || B > h->max_batch)
-        return fail(h, RV_EINVAL, "rot_vote_solve_batch: B outside 0..max_batch");
+    int32_t J = 0;
+    if (rv_status st = check_batch(h, "rot_vote_solve_batch", B, grid, eps_rad, &J))
+        return st;
     if (B == 0)
         return RV_OK;
     if (!offsets || !q_out || !inlier_count)
         return fail(h, RV_EINVAL, "rot_vote_solve_batch: offsets, q_out and inlier_count must not be NULL");
-    if (grid < 1 || grid > h->batch_grid)
-        return fail(h, RV_EINVAL, "rot_vote_solve_batch: grid outside 1..min(max_grid, 64)");
-    if (!(eps_rad > 0.0f) || !(eps_rad <= (float)M_PI))
-        return fail(h, RV_EINVAL, "rot_vote_solve_batch: eps_rad outside (0, pi]");
-    const int32_t J = h->cfg.samples_per_circle > 0 ? h->cfg.samples_per_circle : 8 * grid;
-    if (J > h->max_J)
-        return fail(h, RV_EINVAL, "rot_vote_solve_batch: J = 8*grid exceeds the table sized at create");
     if (offsets[0] != 0)
         return fail(h, RV_EINVAL, "rot_vote_solve_batch: offsets[0] must be 0");
     for (int32_t b = 0; b < B; ++b) {
@@ -1051,113 +1306,21 @@ RV_API rv_status rot_vote_solve_batch(rv_handle* h, const float* x, const float*
     }
     RV_HIP(h, hipSetDevice(h->device), "hipSetDevice");
     hipStream_t s = h->stream;
-    const float T2 = residual_bound(eps_rad);
-    // brick edge: fixed by the config, else measured by rot_vote_tune_batch, else 32
-    const int edge_log2 = h->cfg.batch_brick_edge == 16   ? 4
-                          : h->cfg.batch_brick_edge == 32 ? 5
-                          : h->batch_edge_log2[grid]      ? h->batch_edge_log2[grid]
-                                                          : 5;
-    const int nba = rv::brick_axis(grid, edge_log2);
-    const int nb = nba * nba * nba;
-    const int64_t nq = (int64_t)B * nb;
-    // slack per queue: smaller bricks, more queues per instance, less slack each
-    const uint64_t slack = (uint64_t)std::min(256, std::max(64, 2048 / nb));
-
-    // The staging buffers are reused: nothing of an earlier call may still read them.
-    RV_HIP(h, hipStreamSynchronize(s), "sync before batch plan");
-    if (h->table_J != J) {
-        fill_table(h->h_table, J);
-        RV_HIP(h, hipMemcpyAsync(h->d_table, h->h_table, (size_t)J * sizeof(float2),
-                                 hipMemcpyHostToDevice, s),
-               "table upload");
-        h->table_J = J;
-    }
-    // Host plan: work units of up to kUnitSize correspondences, and queue
-    // capacities from each instance's expected runs (overflowing runs go to
-    // the instance's overflow grid, so the plan bounds speed, not results).
-    const double share = kBatchCapFactor * (double)runs_per_circle(grid, J) / (double)nb;
-    uint32_t* cap = h->h_bplan;
-    uint32_t* qbase = h->h_bplan + nq;
-    uint64_t total = 0;
-    int64_t nunits = 0;
-    for (int32_t b = 0; b < B; ++b) {
-        const int64_t lo = offsets[b], hi = offsets[b + 1];
-        for (int64_t f = lo; f < hi; f += rv::kUnitSize)
-            h->h_units[nunits++] = rv::Unit{b, (int32_t)std::min<int64_t>(rv::kUnitSize, hi - f), f};
-        const uint64_t c = hi > lo ? (((uint64_t)std::ceil(share * (double)(hi - lo)) + slack + 63u) & ~63ull)
-                                   : 0u;
-        for (int k = 0; k < nb; ++k)
-            cap[(int64_t)b * nb + k] = (uint32_t)std::min<uint64_t>(c, 0x7FFFFFC0u);
-        total += c * (uint64_t)nb;
-    }
-    if (total > h->bin.pool_runs) {  // cannot happen within max_n; keep every queue inside the pool
-        const double f = (double)h->bin.pool_runs / (double)total;
-        for (int64_t k = 0; k < nq; ++k)
-            cap[k] = (uint32_t)((uint64_t)((double)cap[k] * f) & ~63ull);
-    }
-    uint64_t at = 0;
-    for (int64_t k = 0; k < nq; ++k) {
-        qbase[k] = (uint32_t)at;
-        at += cap[k];
-    }
-    for (int32_t b = 0; b <= B; ++b)
-        h->h_offsets[b] = offsets[b];
-
-    const bool tm = h->timing;
-    h->batched = true;
-    h->last_batch_edge = 1 << edge_log2;
-    h->last_B = B;
-    h->last_bgrid = grid;
-    h->last_J = J;
-    h->last_strategy = RV_VOTE_BRICK;
-    if (tm)
-        RV_HIP(h, hipEventRecord(h->ev[0], s), "event");
-    if (nunits > 0)
-        RV_HIP(h, hipMemcpyAsync(h->d_units, h->h_units, (size_t)nunits * sizeof(rv::Unit),
-                                 hipMemcpyHostToDevice, s),
-               "unit upload");
-    RV_HIP(h, hipMemcpyAsync(h->d_bplan, h->h_bplan, (size_t)(2 * nq) * sizeof(uint32_t),
-                             hipMemcpyHostToDevice, s),
-           "plan upload");
+    // the pinned staging of the offsets is reused: nothing earlier may still read it
+    RV_HIP(h, hipStreamSynchronize(s), "sync before batch");
+    std::memcpy(h->h_offsets, offsets, (size_t)(B + 1) * sizeof(int64_t));
     RV_HIP(h, hipMemcpyAsync(h->d_offsets, h->h_offsets, (size_t)(B + 1) * sizeof(int64_t),
                              hipMemcpyHostToDevice, s),
            "offsets upload");
-    RV_HIP(h, rv::launch_fill((int32_t*)h->d_bfill, nq, 0, s), "clear queue fills");
-    RV_HIP(h, rv::launch_fill((int32_t*)h->d_bflags, nq, 0, s), "clear overflow flags");
-    if (tm)
-        RV_HIP(h, hipEventRecord(h->ev[1], s), "event");
-
-    rv::BinArgs a = h->bin;
-    a.fill = h->d_bfill;
-    a.qbase = h->d_bplan + nq;
-    a.cap = h->d_bplan;
-    a.flags = h->d_bflags;
-    a.ovf = h->d_bovf;
-    a.units = h->d_units;
-    a.nsets = 1;
-    a.qstride = (int32_t)nq;
-    a.batch = B;
-    RV_HIP(h, rv::launch_bin_vote_batch(x, y, n, grid, J, edge_log2, h->d_table, a, (int)nunits, s),
-           "batch vote");
-    if (tm)
-        RV_HIP(h, hipEventRecord(h->ev[2], s), "event");
-    RV_HIP(h, rv::launch_brick_accum(grid, h->K, edge_log2, h->batch_grids ? h->d_bgrids : nullptr,
-                                     h->d_bpartial, a, s),
-           "batch brick accumulate");
-    if (tm)
-        RV_HIP(h, hipEventRecord(h->ev[3], s), "event");
-    const rv::Candidates c{h->d_bcand_q, h->d_bcand_votes, h->d_bcand_idx, h->d_bcand_inl, h->d_bresult};
-    RV_HIP(h, rv::launch_batch_finish(x, y, n, T2, B, nb, h->K, grid, h->d_bpartial, h->d_units,
-                                      (int)nunits, h->d_offsets, c, inlier_mask, s,
-                                      tm ? h->ev[4] : nullptr, tm ? h->ev[5] : nullptr),
-           "batch top-K, rescore and mask");
-    if (tm)
-        RV_HIP(h, hipEventRecord(h->ev[6], s), "event");
+    if (rv_status st = enqueue_batch(h, x, y, n, h->d_offsets, B, grid, J, residual_bound(eps_rad),
+                                     h->d_bresult, inlier_mask, "rot_vote_solve_batch"))
+        return st;
     RV_HIP(h, hipMemcpyAsync(h->h_bresult, h->d_bresult, (size_t)B * sizeof(rv::Result),
                              hipMemcpyDeviceToHost, s),
            "result readback");
     RV_HIP(h, hipStreamSynchronize(s), "sync");
-    h->events_recorded = tm;
+    h->events_recorded = h->timing;
+    h->last_batch_async = false;
     for (int32_t b = 0; b < B; ++b) {
         const rv::Result& r = h->h_bresult[b];
         std::memcpy(q_out + 4 * (int64_t)b, r.q, sizeof(r.q));
@@ -1166,10 +1329,80 @@ RV_API rv_status rot_vote_solve_batch(rv_handle* h, const float* x, const float*
     return RV_OK;
 }
 
+RV_API rv_status rot_vote_solve_batch_async(rv_handle* h, const float* x, const float* y,
+                                            int64_t n_cols, const int64_t* offsets_device,
+                                            int32_t B, int32_t grid, float eps_rad,
+                                            rv_result* results_device, uint8_t* inlier_mask)
+{
+    if (!h)
+        return RV_EINVAL;
+    h->err.clear();
+    int32_t J = 0;
+    if (rv_status st = check_batch(h, "rot_vote_solve_batch_async", B, grid, eps_rad, &J))
+        return st;
+    if (B == 0)
+        return RV_OK;
+    if (n_cols < 0 || n_cols > h->max_n)
+        return fail(h, RV_EINVAL, "rot_vote_solve_batch_async: n_cols outside 0..max_n");
+    if (!offsets_device || !is_device_memory(offsets_device) ||
+        reinterpret_cast<uintptr_t>(offsets_device) % alignof(int64_t) != 0)
+        return fail(h, RV_EINVAL, "rot_vote_solve_batch_async: offsets must be aligned device memory");
+    if (!results_device || !is_device_memory(results_device) ||
+        reinterpret_cast<uintptr_t>(results_device) % alignof(rv_result) != 0)
+        return fail(h, RV_EINVAL, "rot_vote_solve_batch_async: results must be aligned device memory");
+    if (n_cols > 0 && (!x || !y || !inlier_mask || !is_device_memory(x) || !is_device_memory(y) ||
+                       !is_device_memory(inlier_mask)))
+        return fail(h, RV_EINVAL, "rot_vote_solve_batch_async: x, y and inlier_mask must be device memory");
+    RV_HIP(h, hipSetDevice(h->device), "hipSetDevice");
+    if (rv_status st = enqueue_batch(h, x, y, n_cols, offsets_device, B, grid, J,
+                                     residual_bound(eps_rad), h->d_bresult, inlier_mask,
+                                     "rot_vote_solve_batch_async"))
+        return st;
+    RV_HIP(h, hipMemcpyAsync(results_device, h->d_bresult, (size_t)B * sizeof(rv::Result),
+                             hipMemcpyDeviceToDevice, h->stream),
+           "result copy");
+    h->events_recorded = h->timing;
+    h->last_batch_async = true;
+    return RV_OK;
+}
+
+RV_API rv_status rot_vote_set_batch_schedule(rv_handle* h, int32_t grid, const int32_t* edges)
+{
+    if (!h)
+        return RV_EINVAL;
+    h->err.clear();
+    if (h->max_batch == 0)
+        return fail(h, RV_EUNSUPPORTED, "rot_vote_set_batch_schedule: handle created with max_batch = 0");
+    if (grid < 1 || grid > h->batch_grid)
+        return fail(h, RV_EINVAL, "rot_vote_set_batch_schedule: grid outside 1..min(max_grid, 64)");
+    if (h->cfg.batch_brick_edge != 0)
+        return fail(h, RV_EINVAL, "rot_vote_set_batch_schedule: the config fixes batch_brick_edge");
+    if (!edges)
+        return fail(h, RV_EINVAL, "rot_vote_set_batch_schedule: NULL edges");
+    for (int k = 0; k < rv::kBatchBuckets; ++k)
+        if (edges[k] != 16 && edges[k] != 32)
+            return fail(h, RV_EINVAL, "rot_vote_set_batch_schedule: every edge must be 16 or 32");
+    for (int k = 0; k < rv::kBatchBuckets; ++k)
+        h->sched[grid][k] = (int8_t)(edges[k] == 16 ? 4 : 5);
+    return RV_OK;
+}
+
+RV_API rv_status rot_vote_get_batch_schedule(rv_handle* h, int32_t grid, int32_t* edges)
+{
+    if (!h)
+        return RV_EINVAL;
+    h->err.clear();
+    if (grid < 1 || grid > RV_MAX_BATCH_GRID || !edges)
+        return fail(h, RV_EINVAL, "rot_vote_get_batch_schedule: grid outside 1..64 or NULL edges");
+    for (int k = 0; k < rv::kBatchBuckets; ++k)
+        edges[k] = 1 << batch_edge_log2(h, grid, k);
+    return RV_OK;
+}
+
 RV_API rv_status rot_vote_tune_batch(rv_handle* h, const float* x, const float* y,
                                      const int64_t* offsets, int32_t B, int32_t grid, float eps_rad,
-                                     int32_t reps, uint8_t* mask_scratch, int32_t* edge_out,
-                                     float ms_out[2])
+                                     int32_t reps, uint8_t* mask_scratch, int32_t* edges_out,
+                                     float* ms_out)
 {
     if (!h)
         return RV_EINVAL;
@@ -1184,11 +1417,9 @@ RV_API rv_status rot_vote_tune_batch(rv_handle* h, const float* x, const float* 
         return fail(h, RV_EINVAL, "rot_vote_tune_batch: grid outside 1..min(max_grid, 64)");
     std::vector<float> q(4 * (size_t)B);
     std::vector<int64_t> cnt(B);
-    const int edges[2] = {5, 4};
-    float ms[2] = {-1.0f, -1.0f};
-    const int8_t saved = h->batch_edge_log2[grid];
-    for (int c = 0; c < 2; ++c) {
-        h->batch_edge_log2[grid] = (int8_t)edges[c];
+    int8_t saved[rv::kBatchBuckets];
+    std::memcpy(saved, h->sched[grid], sizeof(saved));
+    auto timed = [&](float* ms) -> rv_status {
         rv_status st = rot_vote_solve_batch(h, x, y, offsets, B, grid, eps_rad, q.data(), cnt.data(),
                                             mask_scratch);  // warm-up (and argument checks)
         const auto t0 = std::chrono::steady_clock::now();
@@ -1196,20 +1427,48 @@ RV_API rv_status rot_vote_tune_batch(rv_handle* h, const float* x, const float* 
             st = rot_vote_solve_batch(h, x, y, offsets, B, grid, eps_rad, q.data(), cnt.data(),
                                       mask_scratch);
         const auto t1 = std::chrono::steady_clock::now();
-        if (st != RV_OK) {
-            h->batch_edge_log2[grid] = saved;
+        *ms = (float)(std::chrono::duration<double, std::milli>(t1 - t0).count() / reps);
+        return st;
+    };
+    // coordinate descent over the size buckets: from 32^3 bricks everywhere,
+    // each bucket (with instances in this batch) in turn takes 16^3 bricks if
+    // that times faster; results are the same whatever the schedule
+    bool present[rv::kBatchBuckets] = {};
+    for (int32_t b = 0; b < B; ++b) {
+        const int64_t n = offsets[b + 1] - offsets[b];
+        int k = 0;
+        for (int i = 0; i < rv::kBatchBuckets - 1; ++i)
+            k += n >= rv::kBucketBound[i] ? 1 : 0;
+        present[k] = true;
+    }
+    float ms[rv::kBatchBuckets + 1];
+    for (auto& v : ms)
+        v = -1.0f;
+    for (int k = 0; k < rv::kBatchBuckets; ++k)
+        h->sched[grid][k] = 5;
+    if (rv_status st = timed(&ms[0])) {
+        std::memcpy(h->sched[grid], saved, sizeof(saved));
+        return st;
+    }
+    float best = ms[0];
+    for (int k = 0; k < rv::kBatchBuckets; ++k) {
+        if (!present[k])
+            continue;
+        h->sched[grid][k] = 4;
+        if (rv_status st = timed(&ms[k + 1])) {
+            std::memcpy(h->sched[grid], saved, sizeof(saved));
             return st;
         }
-        ms[c] = (float)(std::chrono::duration<double, std::milli>(t1 - t0).count() / reps);
+        if (ms[k + 1] < best)
+            best = ms[k + 1];
+        else
+            h->sched[grid][k] = 5;
     }
-    const int best = ms[1] < ms[0] ? 4 : 5;
-    h->batch_edge_log2[grid] = (int8_t)best;
-    if (edge_out)
-        *edge_out = 1 << best;
-    if (ms_out) {
-        ms_out[0] = ms[0];
-        ms_out[1] = ms[1];
-    }
+    if (edges_out)
+        for (int k = 0; k < rv::kBatchBuckets; ++k)
+            edges_out[k] = 1 << h->sched[grid][k];
+    if (ms_out)
+        std::memcpy(ms_out, ms, sizeof(ms));
     return RV_OK;
 }
 
@@ -1246,13 +1505,20 @@ RV_API rv_status rot_vote_get_batch_topk(rv_handle* h, int32_t b, int32_t* n_can
         return fail(h, RV_EINVAL, "rot_vote_get_batch_topk: b outside the last batch");
     if (!n_cand || !votes || !cell_idx || !inliers || !winner)
         return fail(h, RV_EINVAL, "rot_vote_get_batch_topk: NULL argument");
+    RV_HIP(h, hipSetDevice(h->device), "hipSetDevice");
+    if (h->last_batch_async) {
+        RV_HIP(h, hipMemcpyAsync(h->h_bresult, h->d_bresult, (size_t)h->last_B * sizeof(rv::Result),
+                                 hipMemcpyDeviceToHost, h->stream),
+               "result readback");
+        RV_HIP(h, hipStreamSynchronize(h->stream), "sync");
+        h->last_batch_async = false;
+    }
     const rv::Result& r = h->h_bresult[b];
     const int m = r.n_cand;
     if (m > 0) {
         int32_t v[64], ix[64];
         uint32_t in[64];
         const size_t o = (size_t)b * 64;
-        RV_HIP(h, hipSetDevice(h->device), "hipSetDevice");
         RV_HIP(h, hipMemcpy(v, h->d_bcand_votes + o, m * sizeof(int32_t), hipMemcpyDeviceToHost), "copy");
         RV_HIP(h, hipMemcpy(ix, h->d_bcand_idx + o, m * sizeof(int32_t), hipMemcpyDeviceToHost), "copy");
         RV_HIP(h, hipMemcpy(in, h->d_bcand_inl + o, m * sizeof(uint32_t), hipMemcpyDeviceToHost), "copy");
@@ -1264,6 +1530,216 @@ RV_API rv_status rot_vote_get_batch_topk(rv_handle* h, int32_t b, int32_t* n_can
     }
     *n_cand = m;
     *winner = r.winner;
+    return RV_OK;
+}
+
+// ------------------------------------------------------------ tuning file
+//
+// The choices made by measurement (rot_vote_tune's vote strategy per grid,
+// rot_vote_tune_batch's brick edge per grid and instance-size bucket) kept
+// in a small JSON file, keyed by (GPU architecture, grid, J, size bucket):
+//   {"format": "rotvote-tuning", "version": 1, "entries": [
+//     {"arch": "gfx950", "kind": "solve", "grid": 256, "J": 2048, "n_lo": 0, "n_hi": -1,
+//      "strategy": 2},
+//     {"arch": "gfx950", "kind": "batch", "grid": 64, "J": 512, "n_lo": 0, "n_hi": 512,
+//      "edge": 16}, ...]}
+// n_hi = -1 means no upper bound.
+
+namespace {
+
+struct TuneEntry {
+    std::string arch, kind;
+    int64_t grid = 0, J = 0, n_lo = 0, n_hi = -1, value = 0;  // strategy or edge
+};
+
+std::string device_arch(int device)
+{
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess)
+        return "unknown";
+    std::string a = prop.gcnArchName;
+    const size_t c = a.find(':');
+    return c == std::string::npos ? a : a.substr(0, c);
+}
+
+// Parses the entries of a tuning file (objects of string and integer
+// fields); false if the text is not one.
+bool parse_tuning(const std::string& t, std::vector<TuneEntry>* out)
+{
+    if (t.find("\"rotvote-tuning\"") == std::string::npos)
+        return false;
+    size_t at = t.find("\"entries\"");
+    if (at == std::string::npos)
+        return false;
+    at = t.find('[', at);
+    if (at == std::string::npos)
+        return false;
+    for (;;) {
+        const size_t open = t.find_first_of("{]", at);
+        if (open == std::string::npos)
+            return false;
+        if (t[open] == ']')
+            return true;
+        const size_t close = t.find('}', open);
+        if (close == std::string::npos)
+            return false;
+        TuneEntry e;
+        size_t k = open + 1;
+        while (k < close) {
+            const size_t q0 = t.find('"', k);
+            if (q0 == std::string::npos || q0 >= close)
+                break;
+            const size_t q1 = t.find('"', q0 + 1);
+            const size_t colon = t.find(':', q1);
+            if (q1 == std::string::npos || colon == std::string::npos || colon >= close)
+                return false;
+            const std::string key = t.substr(q0 + 1, q1 - q0 - 1);
+            size_t v = t.find_first_not_of(" \t\r\n", colon + 1);
+            if (v == std::string::npos || v >= close)
+                return false;
+            std::string sval;
+            int64_t ival = 0;
+            if (t[v] == '"') {
+                const size_t v1 = t.find('"', v + 1);
+                if (v1 == std::string::npos || v1 >= close)
+                    return false;
+                sval = t.substr(v + 1, v1 - v - 1);
+                k = v1 + 1;
+            } else {
+                char* end = nullptr;
+                ival = std::strtoll(t.c_str() + v, &end, 10);
+                if (end == t.c_str() + v)
+                    return false;
+                k = (size_t)(end - t.c_str());
+            }
+            if (key == "arch") e.arch = sval;
+            else if (key == "kind") e.kind = sval;
+            else if (key == "grid") e.grid = ival;
+            else if (key == "J") e.J = ival;
+            else if (key == "n_lo") e.n_lo = ival;
+            else if (key == "n_hi") e.n_hi = ival;
+            else if (key == "strategy" || key == "edge") e.value = ival;
+        }
+        out->push_back(e);
+        at = close + 1;
+    }
+}
+
+bool read_file(const char* path, std::string* text)
+{
+    FILE* f = std::fopen(path, "rb");
+    if (!f)
+        return false;
+    char buf[4096];
+    size_t r;
+    while ((r = std::fread(buf, 1, sizeof(buf), f)) > 0)
+        text->append(buf, r);
+    std::fclose(f);
+    return true;
+}
+
+int handle_J(const rv_handle* h, int grid)
+{
+    return h->cfg.samples_per_circle > 0 ? h->cfg.samples_per_circle : 8 * grid;
+}
+
+}  // namespace
+
+RV_API rv_status rot_vote_save_tuning(rv_handle* h, const char* path)
+{
+    if (!h)
+        return RV_EINVAL;
+    h->err.clear();
+    if (!path)
+        return fail(h, RV_EINVAL, "rot_vote_save_tuning: NULL path");
+    const std::string arch = device_arch(h->device);
+    std::vector<TuneEntry> mine;
+    for (int g = 1; g <= h->max_grid && g <= RV_MAX_GRID; ++g)
+        if (h->tuned[g])
+            mine.push_back({arch, "solve", g, handle_J(h, g), 0, -1, h->tuned[g]});
+    for (int g = 1; g <= RV_MAX_BATCH_GRID; ++g) {
+        if (!h->sched[g][0])
+            continue;
+        for (int k = 0; k < rv::kBatchBuckets; ++k)
+            mine.push_back({arch, "batch", g, handle_J(h, g), k ? rv::kBucketBound[k - 1] : 0,
+                            k < rv::kBatchBuckets - 1 ? rv::kBucketBound[k] : -1,
+                            (int64_t)1 << h->sched[g][k]});
+    }
+    // keep the file's other entries (other GPUs, grids, J or kinds)
+    std::vector<TuneEntry> all;
+    std::string text;
+    if (read_file(path, &text) && !parse_tuning(text, &all))
+        return fail(h, RV_EINVAL, "rot_vote_save_tuning: the file exists and is not a tuning file");
+    std::vector<TuneEntry> keep;
+    for (const TuneEntry& e : all) {
+        bool replaced = false;
+        for (const TuneEntry& m : mine)
+            replaced |= e.arch == m.arch && e.kind == m.kind && e.grid == m.grid && e.J == m.J &&
+                        e.n_lo == m.n_lo;
+        if (!replaced)
+            keep.push_back(e);
+    }
+    keep.insert(keep.end(), mine.begin(), mine.end());
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE* f = std::fopen(tmp.c_str(), "wb");
+    if (!f)
+        return fail(h, RV_EINVAL, "rot_vote_save_tuning: cannot write " + tmp);
+    std::fprintf(f, "{\"format\": \"rotvote-tuning\", \"version\": 1, \"entries\": [\n");
+    for (size_t i = 0; i < keep.size(); ++i) {
+        const TuneEntry& e = keep[i];
+        std::fprintf(f,
+                     "  {\"arch\": \"%s\", \"kind\": \"%s\", \"grid\": %lld, \"J\": %lld, "
+                     "\"n_lo\": %lld, \"n_hi\": %lld, \"%s\": %lld}%s\n",
+                     e.arch.c_str(), e.kind.c_str(), (long long)e.grid, (long long)e.J,
+                     (long long)e.n_lo, (long long)e.n_hi, e.kind == "solve" ? "strategy" : "edge",
+                     (long long)e.value, i + 1 < keep.size() ? "," : "");
+    }
+    std::fprintf(f, "]}\n");
+    const bool ok = std::fclose(f) == 0;
+    if (!ok || std::rename(tmp.c_str(), path) != 0)
+        return fail(h, RV_EINVAL, std::string("rot_vote_save_tuning: cannot write ") + path);
+    return RV_OK;
+}
+
+RV_API rv_status rot_vote_load_tuning(rv_handle* h, const char* path, int32_t* applied)
+{
+    if (!h)
+        return RV_EINVAL;
+    h->err.clear();
+    if (!path)
+        return fail(h, RV_EINVAL, "rot_vote_load_tuning: NULL path");
+    std::string text;
+    if (!read_file(path, &text))
+        return fail(h, RV_EINVAL, std::string("rot_vote_load_tuning: cannot read ") + path);
+    std::vector<TuneEntry> all;
+    if (!parse_tuning(text, &all))
+        return fail(h, RV_EINVAL, "rot_vote_load_tuning: not a tuning file");
+    const std::string arch = device_arch(h->device);
+    int32_t n = 0;
+    for (const TuneEntry& e : all) {
+        if (e.arch != arch || e.grid < 1 || e.grid > h->max_grid || e.J != handle_J(h, (int)e.grid))
+            continue;
+        if (e.kind == "solve" && (e.value == RV_VOTE_GLOBAL ||
+                                  ((e.value == RV_VOTE_BRICK || e.value == RV_VOTE_KEYS) &&
+                                   h->brick_ok &&
+                                   e.grid <= rv::kMaxBrickGrid))) {
+            h->tuned[e.grid] = (int8_t)e.value;
+            ++n;
+        } else if (e.kind == "batch" && e.grid <= RV_MAX_BATCH_GRID && h->max_batch > 0 &&
+                   h->cfg.batch_brick_edge == 0 && (e.value == 16 || e.value == 32)) {
+            for (int k = 0; k < rv::kBatchBuckets; ++k)
+                if ((k ? rv::kBucketBound[k - 1] : 0) == e.n_lo) {
+                    // a schedule entry sets its bucket; the others keep 32 until set
+                    for (int j = 0; j < rv::kBatchBuckets; ++j)
+                        if (!h->sched[e.grid][j])
+                            h->sched[e.grid][j] = 5;
+                    h->sched[e.grid][k] = (int8_t)(e.value == 16 ? 4 : 5);
+                    ++n;
+                }
+        }
+    }
+    if (applied)
+        *applied = n;
     return RV_OK;
 }
 

@@ -1,27 +1,220 @@
 // Batched solves: many independent instances (same G, J, K, eps), each a
-// contiguous column range of one SoA input.  The binned vote and the brick
-// accumulation are the one-solve kernels run over (instance, unit) and
-// (instance, brick); these kernels finish each instance: merge its bricks'
-// sorted lists, rescore its candidates on its own correspondences, pick its
-// winner and write its mask and result record.
+// contiguous column range of one SoA input.  A plan kernel sizes everything
+// on the device from the instances' offsets (so a batch needs no host round
+// trip and can be captured in a HIP graph): each instance's brick-size class
+// (from its size bucket), its work units, its queues' capacities and pool
+// offsets.  The binned vote and the brick accumulation are the one-solve
+// kernels run over (instance, unit) and (instance, brick) of each class;
+// these kernels finish each instance: merge its bricks' sorted lists, rescore
+// its candidates on its own correspondences, pick its winner and write its
+// mask and result record.
+#include <cmath>
+
 #include "rv_device.h"
 #include "rv_internal.h"
 #include "rv_topk.h"
 
 namespace rv {
 
-// One wave per instance: merge the nb brick lists, decode the K best cells,
-// clear the inlier counters and write a default result record (identity,
-// count 0), which the mask kernel overwrites for instances with
+// ------------------------------------------------------------------ plan
+
+constexpr int kPlanThreads = 1024;
+constexpr int kPlanWaves = kPlanThreads / 64;
+constexpr int kScanVals = 5;  // class-0 instances, class-0 units, class-1 units, units, runs
+
+// Inclusive scans of kScanVals 64-bit values across the workgroup: per wave
+// with shuffles, then over the wave totals; returns the exclusive prefix of
+// this thread plus the carry, and adds the block's totals to the carry.
+__device__ __forceinline__ void block_scan(uint64_t (&v)[kScanVals], uint64_t (&carry)[kScanVals],
+                                           uint64_t (*s_w)[kScanVals], int wave, int lane)
+{
+    uint64_t incl[kScanVals];
+#pragma unroll
+    for (int k = 0; k < kScanVals; ++k) {
+        incl[k] = v[k];
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t lo = __shfl_up((uint32_t)incl[k], off);
+            const uint32_t hi = __shfl_up((uint32_t)(incl[k] >> 32), off);
+            const uint64_t w = ((uint64_t)hi << 32) | lo;
+            incl[k] += lane >= off ? w : 0ull;
+        }
+        if (lane == 63)
+            s_w[wave][k] = incl[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kScanVals; ++k) {
+        uint64_t pre = 0, tot = 0;
+        for (int w = 0; w < kPlanWaves; ++w) {
+            pre += w < wave ? s_w[w][k] : 0ull;
+            tot += s_w[w][k];
+        }
+        v[k] = carry[k] + pre + incl[k] - v[k];  // exclusive
+        carry[k] += tot;
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ int bucket_of(int64_t n)
+{
+    int k = 0;
+#pragma unroll
+    for (int i = 0; i < kBatchBuckets - 1; ++i)
+        k += n >= kBucketBound[i] ? 1 : 0;
+    return k;
+}
+
+// Queue capacity of every brick of an instance of n correspondences: its
+// planned share of the runs plus slack, in multiples of 64 (queues start on
+// 256-byte boundaries), optionally scaled down to fit the pool.
+__device__ __forceinline__ uint64_t inst_cap(const BatchPlanArgs& p, int cls, int64_t n, double f)
+{
+    if (n <= 0)
+        return 0;
+    uint64_t c = ((uint64_t)ceil(p.share[cls] * (double)n) + p.slack[cls] + 63u) & ~63ull;
+    if (f < 1.0)
+        c = (uint64_t)((double)c * f) & ~63ull;
+    return c;
+}
+
+// One workgroup: checks the offsets, then two passes over the instances in
+// chunks of 1024 (pass 1: total runs, for the pool; pass 2: the scans and the
+// per-instance plan).
+__global__ __launch_bounds__(kPlanThreads) void k_batch_plan(BatchPlanArgs p)
+{
+    __shared__ uint64_t s_w[kPlanWaves][kScanVals];
+    __shared__ int s_bad;
+    __shared__ uint64_t s_runs;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int B = p.B;
+    if (t == 0) {
+        s_bad = (p.offsets[0] != 0 || p.offsets[B] > p.n_cols) ? 1 : 0;
+        s_runs = 0;
+    }
+    __syncthreads();
+    uint64_t runs = 0;
+    for (int b = t; b < B; b += kPlanThreads) {
+        const int64_t n = p.offsets[b + 1] - p.offsets[b];
+        if (n < 0 || n * (int64_t)p.J > (int64_t)INT32_MAX)
+            atomicOr(&s_bad, 1);
+        const int cls = p.bucket_edge[bucket_of(n)] == 4 ? 0 : 1;
+        runs += inst_cap(p, cls, n, 1.0) * (uint64_t)p.nb[cls];
+    }
+    atomicAdd((unsigned long long*)&s_runs, (unsigned long long)runs);
+    __syncthreads();
+    if (s_bad) {
+        for (int b = t; b < B; b += kPlanThreads) {
+            Result* r = p.results + b;
+            r->q[0] = 1.0f;
+            r->q[1] = r->q[2] = r->q[3] = 0.0f;
+            r->count = 0;
+            r->winner = -2;
+            r->n_cand = 0;
+        }
+        if (t < 6)
+            p.counts[t] = 0;
+        return;
+    }
+    const double f = s_runs > p.pool_runs ? (double)p.pool_runs / (double)s_runs : 1.0;
+    uint64_t carry[kScanVals] = {0, 0, 0, 0, 0};
+    for (int base = 0; base < B; base += kPlanThreads) {
+        const int b = base + t;
+        int64_t n = 0;
+        int cls = 0;
+        uint64_t cap = 0;
+        if (b < B) {
+            n = p.offsets[b + 1] - p.offsets[b];
+            cls = p.bucket_edge[bucket_of(n)] == 4 ? 0 : 1;
+            cap = inst_cap(p, cls, n, f);
+        }
+        const uint64_t units = (uint64_t)((n + kUnitSize - 1) / kUnitSize);
+        uint64_t v[kScanVals] = {(b < B && cls == 0) ? 1ull : 0ull, cls == 0 ? units : 0ull,
+                                 cls == 1 ? units : 0ull, units,
+                                 b < B ? cap * (uint64_t)p.nb[cls] : 0ull};
+        block_scan(v, carry, s_w, wave, lane);
+        if (b < B) {
+            InstPlan ip;
+            ip.cls = cls;
+            ip.ci = cls == 0 ? (int32_t)v[0] : (int32_t)((uint64_t)b - v[0]);
+            ip.unit0 = (int32_t)(cls == 0 ? v[1] : v[2]);
+            ip.gunit0 = (int32_t)v[3];
+            ip.nunits = (int32_t)units;
+            ip.cap = (uint32_t)cap;
+            ip.rbase = (uint32_t)v[4];
+            ip.reserved = 0;
+            p.inst[b] = ip;
+        }
+    }
+    if (t == 0) {
+        p.counts[0] = (int32_t)carry[1];
+        p.counts[1] = (int32_t)carry[0];
+        p.counts[2] = (int32_t)carry[2];
+        p.counts[3] = B - (int32_t)carry[0];
+        p.counts[4] = (int32_t)carry[3];
+        p.counts[5] = 1;
+    }
+}
+
+// One wave per instance: its class-local index, its queues (capacity, pool
+// offset, cleared fill count and overflow flag) and its work units.
+__global__ __launch_bounds__(256) void k_batch_expand(BatchPlanArgs p)
+{
+    const int b = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (b >= p.B || p.counts[5] == 0)
+        return;
+    const InstPlan ip = p.inst[b];
+    const int cls = ip.cls;
+    const int nb = p.nb[cls];
+    if (lane == 0)
+        p.inst_of[cls][ip.ci] = b;
+    for (int k = lane; k < nb; k += 64) {
+        const int64_t q = (int64_t)ip.ci * nb + k;
+        p.cap[cls][q] = ip.cap;
+        p.qbase[cls][q] = ip.rbase + (uint32_t)k * ip.cap;
+        p.fill[cls][q] = 0u;
+        p.flags[cls][q] = 0u;
+    }
+    const int64_t first = p.offsets[b];
+    const int64_t n = p.offsets[b + 1] - first;
+    for (int j = lane; j < ip.nunits; j += 64) {
+        const int64_t f = first + (int64_t)j * kUnitSize;
+        const int32_t cnt = (int32_t)min<int64_t>(kUnitSize, n - (int64_t)j * kUnitSize);
+        p.units[cls][ip.unit0 + j] = Unit{ip.ci, cnt, f};
+        p.units_all[ip.gunit0 + j] = Unit{b, cnt, f};
+    }
+}
+
+hipError_t launch_batch_plan(const BatchPlanArgs& p, hipStream_t s)
+{
+    if (p.B <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_batch_plan, dim3(1), dim3(kPlanThreads), 0, s, p);
+    if (hipError_t e = hipGetLastError(); e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(k_batch_expand, dim3((unsigned)((p.B + 3) / 4)), dim3(256), 0, s, p);
+    return hipGetLastError();
+}
+
+// --------------------------------------------------------------- finish
+
+// One wave per instance of a class: merge the nb brick lists, decode the K
+// best cells, clear the inlier counters and write a default result record
+// (identity, count 0), which the mask kernel overwrites for instances with
 // correspondences.
 __global__ __launch_bounds__(64) void k_topk_final_batch(const uint64_t* __restrict__ partial, int nb,
-                                                         int K, int G, Candidates c)
+                                                         int K, int G, const int32_t* counts,
+                                                         const int32_t* inst_of, Candidates c)
 {
-    const int inst = blockIdx.x;
+    const int ci = blockIdx.x;
+    if (counts && ci >= counts[1])
+        return;
+    const int inst = inst_of ? inst_of[ci] : ci;
     const int lane = threadIdx.x;
     uint64_t list = 0;
     for (int b = 0; b < nb; ++b)
-        list = wave_insert_sorted(list, partial[((int64_t)inst * nb + b) * 64 + lane], lane);
+        list = wave_insert_sorted(list, partial[((int64_t)ci * nb + b) * 64 + lane], lane);
     const bool valid = lane < K && list != 0;
     const int ncand = __popcll(__ballot(valid));
     const int64_t o = (int64_t)inst * kMaxTopK + lane;
@@ -53,9 +246,12 @@ __global__ __launch_bounds__(kUnitThreads) void k_rescore_batch(const float* __r
                                                                 const float* __restrict__ y,
                                                                 int64_t n, float T2,
                                                                 const Unit* __restrict__ units,
+                                                                const int32_t* nunits,
                                                                 Candidates c)
 {
     __shared__ uint32_t part[kUnitWaves][64];
+    if (nunits && (int)blockIdx.x >= *nunits)
+        return;
     const Unit un = units[blockIdx.x];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
@@ -104,10 +300,13 @@ __global__ __launch_bounds__(kUnitThreads) void k_rescore_batch(const float* __r
 __global__ __launch_bounds__(kUnitThreads) void k_mask_batch(const float* __restrict__ x,
                                                              const float* __restrict__ y, int64_t n,
                                                              float T2, const Unit* __restrict__ units,
+                                                             const int32_t* nunits,
                                                              const int64_t* __restrict__ offsets,
                                                              Candidates c, uint8_t* __restrict__ mask)
 {
     __shared__ int s_win;
+    if (nunits && (int)blockIdx.x >= *nunits)
+        return;
     const Unit un = units[blockIdx.x];
     const int lane = threadIdx.x & 63;
     if (threadIdx.x < 64) {
@@ -207,27 +406,33 @@ hipError_t launch_scatter_masks(const GatherItem* items, const Unit* units, int 
     return hipGetLastError();
 }
 
-hipError_t launch_batch_finish(const float* x, const float* y, int64_t n, float T2, int B, int nb,
-                               int K, int G, const uint64_t* partial, const Unit* units, int nunits,
-                               const int64_t* offsets, const Candidates& c, uint8_t* mask,
-                               hipStream_t s, hipEvent_t after_topk, hipEvent_t after_rescore)
+hipError_t launch_batch_topk(const uint64_t* partial, int B, int nb, int K, int G,
+                             const int32_t* counts, const int32_t* inst_of, const Candidates& c,
+                             hipStream_t s)
 {
-    hipLaunchKernelGGL(k_topk_final_batch, dim3(B), dim3(64), 0, s, partial, nb, K, G, c);
-    if (hipError_t e = hipGetLastError(); e != hipSuccess)
-        return e;
-    if (after_topk)
-        (void)hipEventRecord(after_topk, s);
-    if (nunits > 0) {
-        hipLaunchKernelGGL(k_rescore_batch, dim3(nunits), dim3(kUnitThreads), 0, s, x, y, n, T2,
-                           units, c);
+    if (B <= 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_topk_final_batch, dim3(B), dim3(64), 0, s, partial, nb, K, G, counts,
+                       inst_of, c);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_rescore_mask(const float* x, const float* y, int64_t n, float T2,
+                                     const Unit* units, int max_units, const int32_t* nunits,
+                                     const int64_t* offsets, const Candidates& c, uint8_t* mask,
+                                     hipStream_t s, hipEvent_t after_rescore)
+{
+    if (max_units > 0) {
+        hipLaunchKernelGGL(k_rescore_batch, dim3(max_units), dim3(kUnitThreads), 0, s, x, y, n, T2,
+                           units, nunits, c);
         if (hipError_t e = hipGetLastError(); e != hipSuccess)
             return e;
     }
     if (after_rescore)
         (void)hipEventRecord(after_rescore, s);
-    if (nunits > 0) {
-        hipLaunchKernelGGL(k_mask_batch, dim3(nunits), dim3(kUnitThreads), 0, s, x, y, n, T2, units,
-                           offsets, c, mask);
+    if (max_units > 0) {
+        hipLaunchKernelGGL(k_mask_batch, dim3(max_units), dim3(kUnitThreads), 0, s, x, y, n, T2,
+                           units, nunits, offsets, c, mask);
         return hipGetLastError();
     }
     return hipSuccess;

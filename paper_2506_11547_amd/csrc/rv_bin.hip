@@ -99,7 +99,7 @@ __device__ __forceinline__ uint32_t local_of(uint32_t pc)
 // (64 sampled correspondences, chunk of `chunk` samples, a multiple of 8), so
 // the table index stays wave-uniform and the work spreads over the whole GPU.
 
-template <int kLog, bool kWide>
+template <int kLog, bool kWide, bool kKeys>
 __global__ __launch_bounds__(256) void k_bin_estimate(const float* __restrict__ x,
                                                       const float* __restrict__ y, int64_t n,
                                                       float H, float gm, int J,
@@ -123,7 +123,8 @@ __global__ __launch_bounds__(256) void k_bin_estimate(const float* __restrict__ 
         for_samples<true>(u, v, table, c * chunk, min(J, (c + 1) * chunk), H, gm,
                           [&](const Cell& cell, int) {
                               const uint32_t pc = packed_coords<kWide>(cell);
-                              if (ok && pc != cur)
+                              // runs, or (keys) every sample
+                              if (ok && (kKeys || pc != cur))
                                   atomicAdd(&s_est[brick_of<kLog, kWide>(pc, nba)], 1u);
                               cur = pc;
                           });
@@ -429,6 +430,9 @@ __global__ __launch_bounds__(Pack<kWide>::kThreads, Pack<kWide>::kBlocksPerCU) v
     __shared__ uint16_t s_idx[kWide ? P::kWaves * P::kStageCap : 1];
     __shared__ uint32_t s_total;
     const int nb = nba * nba * nba;
+    // a batch launched for an upper bound of its units: the rest return at once
+    if (a.units && a.counts && (int)blockIdx.x >= a.counts[0])
+        return;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
     const int xs = a.nsets > 1 ? (int)(blockIdx.x & (kSets - 1)) : 0;
@@ -450,7 +454,7 @@ __global__ __launch_bounds__(Pack<kWide>::kThreads, Pack<kWide>::kBlocksPerCU) v
         j1 = min(J, j0 + chunk);
     }
     const int qoff = inst * nb;
-    const int64_t ovf_off = (int64_t)inst * G * G * G;
+    const int64_t ovf_off = (int64_t)(a.inst_of ? a.inst_of[inst] : inst) * G * G * G;
     for (int b = threadIdx.x; b < nb; b += P::kThreads) {
         s_cnt[b] = 0;
     }
@@ -525,6 +529,178 @@ __global__ __launch_bounds__(Pack<kWide>::kThreads, Pack<kWide>::kBlocksPerCU) v
         flush(fill);
 }
 
+// ------------------------------------------------------- vote by keys
+//
+// The key strategy, for circles sampled more sparsely than the grid's cells
+// (J below about 2 G: nearly every sample lands in a new cell, so merging
+// runs saves nothing and the run bookkeeping and the flush checks cost more
+// than the samples).  Every sample is a key, brick index << 15 | cell within
+// its 32^3 brick, written by every lane at a fixed slot (sample, lane) of its
+// wave's staging, with no ballot or compaction; an unusable correspondence
+// writes a dropped marker.  Every kWindow samples (the same sample index in
+// every wave, so no flush check) the workgroup sorts its keys by brick (a
+// counting sort in LDS: counts, one reservation per brick, positions) and
+// stores them position by position into the bricks' queues as single votes
+// (cell | 1 << 15), so one store instruction writes consecutive slots of a
+// few bricks' queues.  The brick accumulation is the run strategy's.
+template <int kWaves_, int kWindow_, int kBlocks_>
+struct KeyPack {
+    static constexpr int kWaves = kWaves_;
+    static constexpr int kThreads = kWaves * kWave;
+    static constexpr int kWindow = kWindow_;  // samples per flush, a multiple of 8
+    static constexpr int kStageCap = kWindow * kWave;
+    static constexpr int kBlocksPerCU = kBlocks_;
+    static constexpr int kSplit = kWindow;    // chunks of J for few circles
+    static_assert(kWindow % 8 == 0, "the sample loop reads the table eight entries at a time");
+    static_assert(kWaves * kStageCap <= 65536, "16-bit sort index");
+};
+// 16 waves in one workgroup per CU, flushing every 16 samples (1024 keys per
+// wave; 120 KiB of LDS): measured at G = 360, J = 180 against 8 waves in two
+// workgroups per CU with 16-sample (5 % slower) and 8-sample windows (29 %
+// slower): larger flushes write longer stretches of each brick's queue.
+using Keys = KeyPack<16, 16, 1>;
+
+constexpr uint32_t kKeyLocalBits = 15;  // cell within a 32^3 brick
+constexpr uint32_t kKeyLocalMask = (1u << kKeyLocalBits) - 1u;
+
+__device__ __forceinline__ uint32_t key_of(const Cell& c, uint32_t nba)
+{
+    const uint32_t brick = __umul24(__umul24(c.z >> 5, nba) + (c.y >> 5), nba) + (c.x >> 5);
+    const uint32_t local = ((c.z & 31u) << 10) | ((c.y & 31u) << 5) | (c.x & 31u);
+    return (brick << kKeyLocalBits) | local;
+}
+
+template <class KP>
+__device__ __forceinline__ void keys_flush(uint32_t (*stage)[KP::kStageCap], uint32_t my,
+                                           uint32_t* s_cnt, uint2* s_dst, uint32_t* s_scan,
+                                           uint16_t* s_idx, uint32_t& s_total, int wave, int lane,
+                                           int nb, int nba, int G, int xs, const BinArgs& a)
+{
+    constexpr int kT = KP::kThreads;
+    constexpr int kPer = kMaxBricksAll / kT;
+    const int t = threadIdx.x;
+    // 1: keys per brick
+    for (uint32_t k = lane; k < my; k += kWave) {
+        const uint32_t e = stage[wave][k];
+        if (e != kDropped)
+            atomicAdd(&s_cnt[e >> kKeyLocalBits], 1u);
+    }
+    __syncthreads();
+    // 2: a reservation per brick (issued first, so that its round trip
+    //    overlaps the scan) and the brick's first sorted position
+    uint32_t c[kPer], g[kPer];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        const int b = t * kPer + u;
+        c[u] = b < nb ? s_cnt[b] : 0u;
+        sum += c[u];
+        g[u] = c[u] ? atomicAdd(a.fill + (int64_t)xs * a.qstride + b, c[u]) : 0u;
+    }
+    uint32_t incl = sum;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        const uint32_t v = __shfl_up(incl, off);
+        incl += lane >= off ? v : 0u;
+    }
+    if (lane == kWave - 1)
+        s_scan[wave] = incl;
+    __syncthreads();
+    uint32_t wpre = 0;
+#pragma unroll
+    for (int w = 0; w < KP::kWaves; ++w)
+        wpre += w < wave ? s_scan[w] : 0u;
+    uint32_t pre = wpre + incl - sum;
+    if (t == kT - 1)
+        s_total = wpre + incl;
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        const int b = t * kPer + u;
+        if (b < nb) {
+            if (c[u]) {
+                const int64_t q = (int64_t)xs * a.qstride + b;
+                const uint32_t cap = a.cap[b];
+                const uint32_t room = cap > g[u] ? cap - g[u] : 0u;
+                s_dst[b] = make_uint2(a.qbase[q] + g[u] - pre, pre + min(room, c[u]));
+            }
+            s_cnt[b] = pre;
+            pre += c[u];
+        }
+    }
+    __syncthreads();
+    // 3a: each key's stage index at its sorted position
+    for (uint32_t k = lane; k < my; k += kWave) {
+        const uint32_t e = stage[wave][k];
+        if (e != kDropped) {
+            const uint32_t pos = atomicAdd(&s_cnt[e >> kKeyLocalBits], 1u);
+            s_idx[pos] = (uint16_t)(wave * KP::kStageCap + k);
+        }
+    }
+    __syncthreads();
+    // 3b: the keys in brick order, as votes of one (past the queue's room: the
+    //    overflow grid); then the counters are cleared for the next flush, and
+    //    no wave stages again before every key is stored (closing barrier)
+    const uint32_t total = s_total;
+    const uint32_t* flat = &stage[0][0];
+    for (uint32_t p = t; p < total; p += kT) {
+        const uint32_t e = flat[s_idx[p]];
+        const uint32_t b = e >> kKeyLocalBits;
+        const uint2 d = s_dst[b];
+        if (p < d.y) {
+            a.pool[(uint64_t)(d.x + p)] = (e & kKeyLocalMask) | (1u << 15);
+        } else {
+            const uint32_t l = e & kKeyLocalMask;
+            const uint32_t bx = b % (uint32_t)nba, by = (b / (uint32_t)nba) % (uint32_t)nba,
+                           bz = b / (uint32_t)(nba * nba);
+            const int64_t cell = ((int64_t)(bz * 32 + (l >> 10)) * G + (by * 32 + ((l >> 5) & 31u))) * G +
+                                 (bx * 32 + (l & 31u));
+            atomicAdd(a.ovf + cell, 1);
+            a.flags[b] = 1u;
+        }
+    }
+    for (int b = t; b < nb; b += kT)
+        s_cnt[b] = 0u;
+    __syncthreads();
+}
+
+// One block per (kThreads correspondences, chunk of samples).
+template <class KP>
+__global__ __launch_bounds__(KP::kThreads, KP::kBlocksPerCU) void k_vote_keys(
+    const float* __restrict__ x, const float* __restrict__ y, int64_t n, int G, float H, float gm,
+    int J, int chunk, int ngroups, const float2* __restrict__ table, int nba, BinArgs a)
+{
+    __shared__ uint32_t stage[KP::kWaves][KP::kStageCap];
+    __shared__ uint32_t s_cnt[kMaxBricksAll];
+    __shared__ uint2 s_dst[kMaxBricksAll];
+    __shared__ uint32_t s_scan[KP::kWaves];
+    __shared__ uint16_t s_idx[KP::kWaves * KP::kStageCap];
+    __shared__ uint32_t s_total;
+    const int nb = nba * nba * nba;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    const int xs = (int)(blockIdx.x & (kSets - 1));
+    const int cb = blockIdx.x / ngroups;
+    const int gb = blockIdx.x - cb * ngroups;
+    const int64_t i = (int64_t)gb * KP::kThreads + threadIdx.x;
+    const int j0 = cb * chunk;
+    const int j1 = min(J, j0 + chunk);
+    for (int b = threadIdx.x; b < nb; b += KP::kThreads)
+        s_cnt[b] = 0;
+    __syncthreads();
+    Quat u, v;
+    const bool ok = load_circle(x, y, n, i, u, v);
+    uint32_t* my_stage = stage[wave];
+    const uint32_t unba = (uint32_t)nba;
+    for (int js = j0; js < j1; js += KP::kWindow) {
+        const int je = min(j1, js + KP::kWindow);
+        for_samples<true>(u, v, table, js, je, H, gm, [&](const Cell& c, int j) {
+            my_stage[(j - js) * kWave + lane] = ok ? key_of(c, unba) : kDropped;
+        });
+        keys_flush<KP>(stage, (uint32_t)(je - js) * kWave, s_cnt, s_dst, s_scan, s_idx, s_total,
+                       wave, lane, nb, nba, G, xs, a);
+    }
+}
+
 // ----------------------------------------------------------- accumulate
 
 template <int kLog>
@@ -548,7 +724,7 @@ __global__ __launch_bounds__(Brick<kLog>::kThreads) void k_brick_accum(BinArgs a
     // launch has fewer workgroups than bricks); odd rounds run backwards, so
     // with bricks ordered heaviest first the workgroup with the heaviest brick
     // of one round gets the lightest of the next.
-    const int items = a.batch ? a.batch * nb : nb;
+    const int items = a.batch ? (a.counts ? a.counts[1] : a.batch) * nb : nb;
     const int nwg = (int)gridDim.x;
     int round = 0;
     for (int base = 0; base < items; base += nwg, ++round) {
@@ -564,7 +740,8 @@ __global__ __launch_bounds__(Brick<kLog>::kThreads) void k_brick_accum(BinArgs a
             b = (int)a.order[item];
         }
         const int qoff = inst * nb;
-        const int64_t gofs = (int64_t)inst * G * G * G;  // this instance's grid and overflow grid
+        // this instance's grid and overflow grid (by its index in the batch)
+        const int64_t gofs = (int64_t)(a.inst_of ? a.inst_of[inst] : inst) * G * G * G;
         const int bx = b % nba, by = (b / nba) % nba, bz = b / (nba * nba);
 
         for (int k = threadIdx.x; k < kBrickCells / 4; k += kAccumThreads)
@@ -732,14 +909,15 @@ int accum_blocks(int edge_log2, int items)
 int solve_edge_log2(int G) { return G <= 128 ? 4 : 5; }
 
 hipError_t launch_bin_prepare(const float* x, const float* y, int64_t n, int G, int J,
-                              int edge_log2, const float2* table, const BinArgs& a, hipStream_t s)
+                              int edge_log2, const float2* table, const BinArgs& a, hipStream_t s,
+                              bool keys)
 {
     const bool wide = G > kNarrowGrid;
-    if ((edge_log2 != 4 && edge_log2 != 5) || (edge_log2 == 4 && wide))
+    if ((edge_log2 != 4 && edge_log2 != 5) || (edge_log2 == 4 && (wide || keys)))
         return hipErrorInvalidValue;
     const int nba = brick_axis(G, edge_log2);
     const int nb = nba * nba * nba;
-    if (G > kMaxBrickGrid || nb > (wide ? kMaxBricksAll : kMaxBricks))
+    if (G > kMaxBrickGrid || nb > ((wide || keys) ? kMaxBricksAll : kMaxBricks))
         return hipErrorInvalidValue;
     const float H = (float)G * 0.5f;
     const float gm = (float)G - 0.5f;
@@ -756,19 +934,46 @@ hipError_t launch_bin_prepare(const float* x, const float* y, int64_t n, int G, 
         if (nwaves > (int64_t)INT32_MAX - 4)
             return hipErrorInvalidValue;
         const dim3 grid((unsigned)((nwaves + 3) / 4));
-        if (wide)
-            hipLaunchKernelGGL((k_bin_estimate<5, true>), grid, dim3(256), 0, s, x, y, n, H, gm, J,
-                               table, nba, chunk, (int)ngroups, (int)nwaves, a.est);
+        if (keys)
+            hipLaunchKernelGGL((k_bin_estimate<5, true, true>), grid, dim3(256), 0, s, x, y, n, H,
+                               gm, J, table, nba, chunk, (int)ngroups, (int)nwaves, a.est);
+        else if (wide)
+            hipLaunchKernelGGL((k_bin_estimate<5, true, false>), grid, dim3(256), 0, s, x, y, n, H,
+                               gm, J, table, nba, chunk, (int)ngroups, (int)nwaves, a.est);
         else if (edge_log2 == 5)
-            hipLaunchKernelGGL((k_bin_estimate<5, false>), grid, dim3(256), 0, s, x, y, n, H, gm, J,
-                               table, nba, chunk, (int)ngroups, (int)nwaves, a.est);
+            hipLaunchKernelGGL((k_bin_estimate<5, false, false>), grid, dim3(256), 0, s, x, y, n, H,
+                               gm, J, table, nba, chunk, (int)ngroups, (int)nwaves, a.est);
         else
-            hipLaunchKernelGGL((k_bin_estimate<4, false>), grid, dim3(256), 0, s, x, y, n, H, gm, J,
-                               table, nba, chunk, (int)ngroups, (int)nwaves, a.est);
+            hipLaunchKernelGGL((k_bin_estimate<4, false, false>), grid, dim3(256), 0, s, x, y, n, H,
+                               gm, J, table, nba, chunk, (int)ngroups, (int)nwaves, a.est);
         if (hipError_t e = hipGetLastError(); e != hipSuccess)
             return e;
     }
     hipLaunchKernelGGL(k_bin_plan, dim3(1), dim3(kPlanThreads), 0, s, a, nb);
+    return hipGetLastError();
+}
+
+hipError_t launch_key_vote(const float* x, const float* y, int64_t n, int G, int J,
+                           const float2* table, const BinArgs& a, hipStream_t s)
+{
+    if (n <= 0)
+        return hipSuccess;
+    const int nba = brick_axis(G, 5);
+    if (G > kMaxBrickGrid || nba * nba * nba > kMaxBricksAll || a.units || a.nsets != kSets)
+        return hipErrorInvalidValue;
+    const int64_t ngroups = (n + Keys::kThreads - 1) / Keys::kThreads;
+    // at least ~4 rounds of workgroups over the GPU, by splitting J into whole
+    // flush windows when there are few correspondences
+    const int64_t want = 4 * Keys::kBlocksPerCU * 256;
+    const int64_t nwin = (J + Keys::kWindow - 1) / Keys::kWindow;
+    const int64_t split = std::max<int64_t>(1, std::min<int64_t>(nwin, want / ngroups));
+    const int chunk = (int)(((nwin + split - 1) / split) * Keys::kWindow);
+    const int64_t nchunks = (J + chunk - 1) / chunk;
+    const int64_t blocks = ngroups * nchunks;
+    if (blocks > INT32_MAX)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_vote_keys<Keys>), dim3((unsigned)blocks), dim3(Keys::kThreads), 0, s, x, y,
+                       n, G, (float)G * 0.5f, (float)G - 0.5f, J, chunk, (int)ngroups, table, nba, a);
     return hipGetLastError();
 }
 
@@ -824,8 +1029,10 @@ hipError_t launch_brick_accum(int G, int K, int edge_log2, int32_t* grid, uint64
     // 32 768 bricks); 16^3 bricks (many small workgroups per CU) and one solve:
     // a workgroup per brick, which the hardware hands out in order (the plan's
     // heaviest first) as CUs free up (persistent was slower there)
-    const int blocks = (a.batch && edge_log2 == 5) ? accum_blocks(edge_log2, a.batch * nb)
-                                                   : (a.batch ? a.batch * nb : nb);
+    // (a batch planned on the device, of either edge, is launched persistent
+    // for its upper bound of bricks)
+    const int blocks = (a.batch && (edge_log2 == 5 || a.counts)) ? accum_blocks(edge_log2, a.batch * nb)
+                                                                 : (a.batch ? a.batch * nb : nb);
     if (edge_log2 == 5)
         hipLaunchKernelGGL(k_brick_accum<5>, dim3(blocks), dim3(Brick<5>::kThreads), 0, s, a, G, nba,
                            K, grid, partial);

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "rotvote.h"
+
 namespace rv {
 
 // Device-resident result of one solve, copied back once at the end.
@@ -58,7 +60,8 @@ constexpr int kMaxBrickGrid = 384;   // (384 / 32)^3 = 1728 bricks
 constexpr int kMaxBricksAll = 2048;  // brick tables of one solve (queue metadata, plan)
 constexpr int kEstimateStride = 64;  // the estimate samples every 64th correspondence
 
-// A batch work unit: up to 512 consecutive correspondences of one instance.
+// A batch work unit: up to 512 consecutive correspondences of one instance
+// (for the vote, the instance's index within its brick-size class).
 struct Unit {
     int32_t inst;
     int32_t count;
@@ -79,6 +82,10 @@ struct BinArgs {
     int32_t* ovf;        // [instances][G^3] overflow grids, zero between solves
     uint64_t pool_runs;  // pool capacity in runs (< 2^32)
     const Unit* units;   // batch: work units of the binned vote (null for one solve)
+    const int32_t* counts;   // batch (device): [0] units, [1] instances of this launch's class
+                             // (null: every launched block and `batch` instances)
+    const int32_t* inst_of;  // batch (device): class-local instance -> batch instance, which
+                             // indexes the overflow and kept grids (null: the same)
     int32_t nsets;
     int32_t qstride;
     int32_t batch;       // number of instances (0 for one solve)
@@ -93,24 +100,79 @@ int solve_edge_log2(int G);
 // accumulation, which writes every cell of the grid and one sorted list per
 // brick that holds the brick's K best cells.  Edge 16 needs G <= 256.
 hipError_t launch_bin_prepare(const float* x, const float* y, int64_t n, int G, int J,
-                              int edge_log2, const float2* table, const BinArgs& a, hipStream_t s);
+                              int edge_log2, const float2* table, const BinArgs& a, hipStream_t s,
+                              bool keys = false);
+// The key strategy's vote (32^3 bricks, every sample a key): after
+// launch_bin_prepare(..., keys = true), before launch_brick_accum(edge 5).
+hipError_t launch_key_vote(const float* x, const float* y, int64_t n, int G, int J,
+                           const float2* table, const BinArgs& a, hipStream_t s);
 hipError_t launch_bin_vote(const float* x, const float* y, int64_t n, int G, int J, int edge_log2,
                            const float2* table, const BinArgs& a, hipStream_t s);
 hipError_t launch_brick_accum(int G, int K, int edge_log2, int32_t* grid, uint64_t* partial,
                               const BinArgs& a, hipStream_t s);
 
-// Batches (G <= kMaxBatchGrid): the binned vote over work units, then the
-// per-instance top-K merge, rescore and mask.
+// Batches (G <= kMaxBatchGrid): planned on the device from the instances'
+// offsets, then the binned vote over work units and the accumulation over
+// (instance, brick), per brick-size class, then the per-instance top-K merge,
+// rescore and mask.
 constexpr int kMaxBatchGrid = 64;
 constexpr int kMaxBatchBricks = 64;  // (64 / 16)^3
 constexpr int kUnitSize = 512;       // correspondences per work unit
+constexpr int kBatchBuckets = 4;     // instance-size buckets of a batch schedule
+// Instance-size buckets: bucket k holds the instances with
+// kBucketBound[k - 1] <= n < kBucketBound[k].
+constexpr int64_t kBucketBound[kBatchBuckets - 1] = {512, 2048, 8192};
+
+// Per-instance plan written by the plan kernel.
+struct InstPlan {
+    int32_t cls;      // brick-size class: 0 = 16^3 bricks, 1 = 32^3
+    int32_t ci;       // index within the class
+    int32_t unit0;    // first vote unit within the class
+    int32_t gunit0;   // first unit of the batch-wide unit list
+    int32_t nunits;
+    uint32_t cap;     // run capacity of each of its queues
+    uint32_t rbase;   // first pool slot of its queues
+    int32_t reserved;
+};
+
+struct BatchPlanArgs {
+    const int64_t* offsets;  // device int64[B + 1]
+    int32_t B;
+    int32_t J;
+    int64_t n_cols;          // columns of the SoA input (offsets[B] must not exceed it)
+    int8_t bucket_edge[kBatchBuckets];  // brick edge (log2) per instance-size bucket
+    int32_t nb[2];           // bricks per instance of class 0 (16^3) and 1 (32^3)
+    double share[2];         // planned runs per brick per correspondence, per class
+    uint32_t slack[2];       // runs added to every queue, per class
+    uint64_t pool_runs;
+    InstPlan* inst;          // [B]
+    int32_t* counts;         // [0..1] class 0 units, instances; [2..3] class 1; [4] all units;
+                             // [5] 1 when the offsets are valid
+    uint32_t* cap[2];        // per class: [instance in class * nb + brick]
+    uint32_t* qbase[2];
+    uint32_t* fill[2];
+    uint32_t* flags[2];
+    int32_t* inst_of[2];     // per class: class index -> batch instance
+    Unit* units[2];          // per class: vote units (class-local instance)
+    Unit* units_all;         // every unit (batch instance), for rescoring and masks
+    Result* results;         // [B]: set for every instance when the offsets are invalid
+};
+// The plan (one workgroup) and its expansion into queues and units.
+hipError_t launch_batch_plan(const BatchPlanArgs& p, hipStream_t s);
+
 hipError_t launch_bin_vote_batch(const float* x, const float* y, int64_t n, int G, int J,
                                  int edge_log2, const float2* table, const BinArgs& a, int nunits,
                                  hipStream_t s);
-hipError_t launch_batch_finish(const float* x, const float* y, int64_t n, float T2, int B, int nb,
-                               int K, int G, const uint64_t* partial, const Unit* units, int nunits,
-                               const int64_t* offsets, const Candidates& c, uint8_t* mask,
-                               hipStream_t s, hipEvent_t after_topk, hipEvent_t after_rescore);
+// Per class: merge each instance's brick lists into its candidates (instances
+// past counts[1] of the class skip).
+hipError_t launch_batch_topk(const uint64_t* partial, int B, int nb, int K, int G,
+                             const int32_t* counts, const int32_t* inst_of, const Candidates& c,
+                             hipStream_t s);
+// Rescore and mask over the batch's unit list (units past *nunits skip).
+hipError_t launch_batch_rescore_mask(const float* x, const float* y, int64_t n, float T2,
+                                     const Unit* units, int max_units, const int32_t* nunits,
+                                     const int64_t* offsets, const Candidates& c, uint8_t* mask,
+                                     hipStream_t s, hipEvent_t after_rescore);
 
 // Least-squares refinement on an inlier set (Sec. 4.2): device-resident state
 // of the rounds (rotation, counts, convergence), float64 block partials of the
@@ -188,5 +250,15 @@ hipError_t launch_rescore(const float* x, const float* y, int64_t n, float T2,
                           const Candidates& c, hipStream_t s);
 hipError_t launch_mask(const float* x, const float* y, int64_t n, float T2, const Candidates& c,
                        uint8_t* mask, hipStream_t s);
+
+// Server lanes: handles whose vote grid and run pool are not allocated at
+// create but bound per solve from the server's arena.  The byte counts are
+// what one solve (or one batch of B instances, `cols` columns in all) needs
+// bound: the grid (global strategy) or grid + run pool (brick strategy), or
+// the batch's run pool; -1 for arguments outside the handle's limits.
+rv_status create_lane(rv_handle** out, const rv_config* cfg);
+int64_t lane_solve_bytes(const rv_handle* h, int64_t n, int32_t grid);
+int64_t lane_batch_bytes(const rv_handle* h, int64_t cols, int32_t B, int32_t grid);
+void lane_bind(rv_handle* h, int32_t* grid, uint32_t* pool, uint64_t pool_runs);
 
 }  // namespace rv

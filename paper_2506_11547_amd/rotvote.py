@@ -24,7 +24,7 @@ RV_OK, RV_EINVAL, RV_ENOMEM, RV_EDEVICE, RV_EUNSUPPORTED = 0, -1, -2, -3, -4
 RV_EAGAIN, RV_ETIMEDOUT = -5, -6
 STATUS_NAMES = {0: "RV_OK", -1: "RV_EINVAL", -2: "RV_ENOMEM", -3: "RV_EDEVICE",
                 -4: "RV_EUNSUPPORTED", -5: "RV_EAGAIN", -6: "RV_ETIMEDOUT"}
-STRATEGIES = {"auto": 0, "global": 1, "brick": 2}
+STRATEGIES = {"auto": 0, "global": 1, "brick": 2, "keys": 3}
 STRATEGY_NAMES = {v: k for k, v in STRATEGIES.items()}
 FLAG_TIMING = 1
 FLAG_BATCH_GRIDS = 2
@@ -32,6 +32,8 @@ MAX_TOPK = 64
 NOALLOC_MAX_GRID = 64
 NOALLOC_MAX_SAMPLES = 4096
 MAX_BATCH_GRID = 64
+BATCH_BUCKETS = 4
+BATCH_BUCKET_BOUNDS = (512, 2048, 8192)  # n < 512, [512, 2048), [2048, 8192), n >= 8192
 MAX_REFINE_ROUNDS = 64
 NUM_STAGES = 6
 STAGE_NAMES = ("prepare", "vote", "reduce", "topk", "rescore", "mask")
@@ -47,7 +49,10 @@ EXPORTS = ("rot_vote_default_config", "rot_vote_create", "rot_vote_destroy",
            "rot_vote_server_default_config",
            "rot_vote_server_create",
            "rot_vote_server_destroy", "rot_vote_server_submit", "rot_vote_server_wait",
-           "rot_vote_server_stats", "rot_vote_server_last_error", "rot_vote_solve_noalloc")
+           "rot_vote_server_stats", "rot_vote_server_last_error", "rot_vote_server_memory",
+           "rot_vote_server_pause", "rot_vote_server_request_bytes", "rot_vote_solve_noalloc",
+           "rot_vote_solve_batch_async", "rot_vote_set_batch_schedule",
+           "rot_vote_get_batch_schedule", "rot_vote_save_tuning", "rot_vote_load_tuning")
 
 
 class RvConfig(ct.Structure):
@@ -77,16 +82,20 @@ class ServerConfig(ct.Structure):
                 ("hbm_budget", ct.c_int64), ("reserved", ct.c_int32 * 4)]
 
 
+REQ_AFTER_STREAM = 1
+
+
 class Request(ct.Structure):
     _fields_ = [("x", ct.c_void_p), ("y", ct.c_void_p), ("n", ct.c_int64), ("grid", ct.c_int32),
                 ("eps_rad", ct.c_float), ("inlier_mask", ct.c_void_p),
-                ("refine_rounds", ct.c_int32), ("reserved", ct.c_int32)]
+                ("refine_rounds", ct.c_int32), ("flags", ct.c_uint32), ("stream", ct.c_void_p)]
 
 
 class Reply(ct.Structure):
     _fields_ = [("q", ct.c_float * 4), ("inlier_count", ct.c_int64), ("status", ct.c_int32),
                 ("batched", ct.c_int32), ("worker", ct.c_int32), ("refine_rounds_run", ct.c_int32),
-                ("t_submit", ct.c_double), ("t_start", ct.c_double), ("t_end", ct.c_double)]
+                ("t_submit", ct.c_double), ("t_start", ct.c_double), ("t_end", ct.c_double),
+                ("scratch_bytes", ct.c_int64)]
 
 
 class RotVoteError(RuntimeError):
@@ -158,11 +167,22 @@ def load_library(path: Path | str = LIB_PATH) -> ct.CDLL:
                                        ct.POINTER(i64), ct.POINTER(i32), vp]
     L.rot_vote_solve_multi.restype = i32
     L.rot_vote_tune.argtypes = [vp, vp, vp, i64, i32, f32, i32, vp, ct.POINTER(i32),
-                                ct.POINTER(f32 * 2)]
+                                ct.POINTER(f32 * 3)]
     L.rot_vote_tune.restype = i32
     L.rot_vote_tune_batch.argtypes = [vp, vp, vp, ct.POINTER(i64), i32, i32, f32, i32, vp,
-                                      ct.POINTER(i32), ct.POINTER(f32 * 2)]
+                                      ct.POINTER(i32 * BATCH_BUCKETS),
+                                      ct.POINTER(f32 * (BATCH_BUCKETS + 1))]
     L.rot_vote_tune_batch.restype = i32
+    L.rot_vote_solve_batch_async.argtypes = [vp, vp, vp, i64, vp, i32, i32, f32, vp, vp]
+    L.rot_vote_solve_batch_async.restype = i32
+    L.rot_vote_set_batch_schedule.argtypes = [vp, i32, ct.POINTER(i32 * BATCH_BUCKETS)]
+    L.rot_vote_set_batch_schedule.restype = i32
+    L.rot_vote_get_batch_schedule.argtypes = [vp, i32, ct.POINTER(i32 * BATCH_BUCKETS)]
+    L.rot_vote_get_batch_schedule.restype = i32
+    L.rot_vote_save_tuning.argtypes = [vp, ct.c_char_p]
+    L.rot_vote_save_tuning.restype = i32
+    L.rot_vote_load_tuning.argtypes = [vp, ct.c_char_p, ct.POINTER(i32)]
+    L.rot_vote_load_tuning.restype = i32
     L.rot_vote_get_footprint.argtypes = [vp, ct.POINTER(i64)]
     L.rot_vote_get_footprint.restype = i32
     L.rot_vote_server_default_config.argtypes = [ct.POINTER(ServerConfig)]
@@ -178,6 +198,13 @@ def load_library(path: Path | str = LIB_PATH) -> ct.CDLL:
     L.rot_vote_server_stats.argtypes = [vp, ct.POINTER(i32), ct.POINTER(i64), ct.POINTER(i64),
                                         ct.POINTER(i64)]
     L.rot_vote_server_stats.restype = i32
+    L.rot_vote_server_memory.argtypes = [vp, ct.POINTER(i64), ct.POINTER(i64), ct.POINTER(i64),
+                                         ct.POINTER(i64)]
+    L.rot_vote_server_memory.restype = i32
+    L.rot_vote_server_pause.argtypes = [vp, i32]
+    L.rot_vote_server_pause.restype = i32
+    L.rot_vote_server_request_bytes.argtypes = [vp, i64, i32, ct.POINTER(i64)]
+    L.rot_vote_server_request_bytes.restype = i32
     L.rot_vote_server_last_error.argtypes = [vp]
     L.rot_vote_server_last_error.restype = ct.c_char_p
     _lib = L
@@ -384,20 +411,21 @@ class Solver:
         return result, mask
 
     def tune(self, x: torch.Tensor, y: torch.Tensor, grid: int, eps_deg: float, reps: int = 3):
-        """Measures both vote strategies on this input and fixes the faster one
-        for `grid` (AUTO solves).  Returns (strategy name, {name: ms})."""
+        """Measures the vote strategies on this input and fixes the fastest
+        for `grid` (AUTO solves).  Returns (strategy name, {name: ms}); -1 ms
+        for a strategy the handle cannot run at this grid."""
         x = x.contiguous()
         y = y.contiguous()
         n = x.shape[1]
         scratch = torch.empty(n, dtype=torch.uint8, device=x.device)
         st = ct.c_int32()
-        ms = (ct.c_float * 2)()
+        ms = (ct.c_float * 3)()
         self._check(self._lib.rot_vote_tune(self._h, ct.c_void_p(x.data_ptr()),
                                             ct.c_void_p(y.data_ptr()), n, grid,
                                             ct.c_float(eps_deg_to_rad(eps_deg)), reps,
                                             ct.c_void_p(scratch.data_ptr()), ct.byref(st),
                                             ct.byref(ms)))
-        return STRATEGY_NAMES[st.value], {"global": ms[0], "brick": ms[1]}
+        return STRATEGY_NAMES[st.value], {"global": ms[0], "brick": ms[1], "keys": ms[2]}
 
     def solve_multi_raw(self, x_ptr: int, y_ptr: int, n: int, grid: int, eps_rad: float,
                         max_models: int, sep_rad: float, min_inliers: int, labels_ptr: int):
@@ -546,21 +574,70 @@ class Solver:
 
     def tune_batch(self, x: torch.Tensor, y: torch.Tensor, offsets, grid: int, eps_deg: float,
                    reps: int = 2):
-        """Measures 32^3 and 16^3 bricks on this batch and keeps the faster for
-        `grid`.  Returns (edge, {32: ms, 16: ms})."""
+        """Chooses the brick edge of each instance-size bucket by measurement on
+        this batch and keeps the schedule for `grid`.  Returns (edges per bucket,
+        ms: the batch time with 32^3 everywhere, then after trying each bucket at
+        16^3, -1 for a bucket without instances)."""
         x = x.contiguous()
         y = y.contiguous()
         B = len(offsets) - 1
         offs = (ct.c_int64 * (B + 1))(*[int(o) for o in offsets])
         scratch = torch.empty(max(1, x.shape[1]), dtype=torch.uint8, device=x.device)
-        edge = ct.c_int32()
-        ms = (ct.c_float * 2)()
+        edges = (ct.c_int32 * BATCH_BUCKETS)()
+        ms = (ct.c_float * (BATCH_BUCKETS + 1))()
         self._check(self._lib.rot_vote_tune_batch(self._h, ct.c_void_p(x.data_ptr()),
                                                   ct.c_void_p(y.data_ptr()), offs, B, grid,
                                                   ct.c_float(eps_deg_to_rad(eps_deg)), reps,
-                                                  ct.c_void_p(scratch.data_ptr()), ct.byref(edge),
+                                                  ct.c_void_p(scratch.data_ptr()), ct.byref(edges),
                                                   ct.byref(ms)))
-        return edge.value, {32: ms[0], 16: ms[1]}
+        return list(edges), list(ms)
+
+    def set_batch_schedule(self, grid: int, edges):
+        e = (ct.c_int32 * BATCH_BUCKETS)(*[int(v) for v in edges])
+        self._check(self._lib.rot_vote_set_batch_schedule(self._h, grid, ct.byref(e)))
+
+    def batch_schedule(self, grid: int) -> list:
+        e = (ct.c_int32 * BATCH_BUCKETS)()
+        self._check(self._lib.rot_vote_get_batch_schedule(self._h, grid, ct.byref(e)))
+        return list(e)
+
+    def save_tuning(self, path):
+        self._check(self._lib.rot_vote_save_tuning(self._h, str(path).encode()))
+
+    def load_tuning(self, path) -> int:
+        n = ct.c_int32()
+        self._check(self._lib.rot_vote_load_tuning(self._h, str(path).encode(), ct.byref(n)))
+        return n.value
+
+    def solve_batch_async_raw(self, x_ptr: int, y_ptr: int, n_cols: int, offsets_ptr: int, B: int,
+                              grid: int, eps_rad: float, results_ptr: int, mask_ptr: int):
+        """Direct C-ABI call: enqueues the device-planned batch on the handle's
+        stream and returns; B rv_results are written at results_ptr later."""
+        self._check(self._lib.rot_vote_solve_batch_async(
+            self._h, ct.c_void_p(x_ptr), ct.c_void_p(y_ptr), n_cols, ct.c_void_p(offsets_ptr), B,
+            grid, ct.c_float(eps_rad), ct.c_void_p(results_ptr), ct.c_void_p(mask_ptr)))
+        self._last_bgrid = grid
+
+    def solve_batch_async(self, x: torch.Tensor, y: torch.Tensor, offsets: torch.Tensor,
+                          grid: int, eps_deg: float, results: torch.Tensor | None = None,
+                          mask: torch.Tensor | None = None):
+        """Enqueues a batch whose offsets (int64 [B+1]) are a device tensor;
+        returns (results uint8 [B, RESULT_BYTES], mask) without waiting."""
+        for t, nm in ((x, "x"), (y, "y")):
+            if t.dtype != torch.float32 or t.dim() != 2 or t.shape[0] != 3 or not t.is_cuda \
+                    or not t.is_contiguous():
+                raise ValueError(f"{nm} must be a contiguous float32 [3, N] device tensor")
+        if offsets.dtype != torch.int64 or not offsets.is_cuda or not offsets.is_contiguous():
+            raise ValueError("offsets must be a contiguous int64 device tensor")
+        B = offsets.numel() - 1
+        if results is None:
+            results = torch.empty(max(B, 1), RESULT_BYTES, dtype=torch.uint8, device=x.device)
+        if mask is None:
+            mask = torch.empty(x.shape[1], dtype=torch.bool, device=x.device)
+        self.solve_batch_async_raw(x.data_ptr(), y.data_ptr(), x.shape[1], offsets.data_ptr(), B,
+                                   grid, eps_deg_to_rad(eps_deg), results.data_ptr(),
+                                   mask.data_ptr() if x.shape[1] else 0)
+        return results, mask
 
     def solve_batch_raw(self, x_ptr: int, y_ptr: int, offsets, grid: int, eps_rad: float,
                         mask_ptr: int):
@@ -654,11 +731,13 @@ class Solver:
 
 
 class Server:
-    """Request server (worker threads, one stream and handle each, batching of
-    small requests).  Inputs and masks are device tensors the caller keeps
-    alive until the reply is collected."""
+    """Request server: admission by each request's scratch footprint from one
+    device arena (``hbm_budget`` bytes), lanes (a thread, stream and handle
+    each) running admitted requests concurrently, batching of small requests.
+    Inputs and masks are device tensors the caller keeps alive until the reply
+    is collected."""
 
-    def __init__(self, device: int = 0, workers: int = 2, max_n: int = 1 << 20,
+    def __init__(self, device: int = 0, workers: int = 4, max_n: int = 1 << 20,
                  max_grid: int = 256, topk: int = 16, samples_per_circle: int = 0,
                  max_batch: int = 64, batch_max_n: int = 65536, max_queue: int = 1 << 20,
                  hbm_budget: int = 0):
@@ -697,11 +776,14 @@ class Server:
         self.close()
 
     def submit_raw(self, x_ptr: int, y_ptr: int, n: int, grid: int, eps_rad: float, mask_ptr: int,
-                   refine_rounds: int = 0) -> int:
+                   refine_rounds: int = 0, after_stream: int | None = None) -> int:
         """Queues a request on raw device addresses; returns its ticket (raises
-        RotVoteError with status RV_EAGAIN when the queue is full)."""
+        RotVoteError with status RV_EAGAIN when the queue is full).  With
+        ``after_stream`` (a raw hipStream_t, 0 for the null stream) the request
+        runs after the work already enqueued there."""
+        flags = REQ_AFTER_STREAM if after_stream is not None else 0
         r = Request(ct.c_void_p(x_ptr), ct.c_void_p(y_ptr), n, grid, eps_rad, ct.c_void_p(mask_ptr),
-                    refine_rounds, 0)
+                    refine_rounds, flags, ct.c_void_p(after_stream or 0))
         t = ct.c_uint64()
         st = self._lib.rot_vote_server_submit(self._h, ct.byref(r), ct.byref(t))
         if st != RV_OK:
@@ -709,7 +791,10 @@ class Server:
         return int(t.value)
 
     def submit(self, x: torch.Tensor, y: torch.Tensor, grid: int, eps_deg: float,
-               mask: torch.Tensor, refine_rounds: int = 0) -> int:
+               mask: torch.Tensor, refine_rounds: int = 0,
+               stream: torch.cuda.Stream | None = None) -> int:
+        """Queues a request; it runs after the work already enqueued on
+        ``stream`` (default: torch's current stream), which produced x and y."""
         for t, nm in ((x, "x"), (y, "y")):
             if t.dtype != torch.float32 or t.dim() != 2 or t.shape[0] != 3 or not t.is_cuda \
                     or not t.is_contiguous():
@@ -717,8 +802,9 @@ class Server:
         if x.shape != y.shape or mask.numel() != x.shape[1] or mask.element_size() != 1:
             raise ValueError("x, y must match and mask must be a 1-byte [N] tensor")
         n = x.shape[1]
+        s = stream if stream is not None else torch.cuda.current_stream(x.device)
         t = self.submit_raw(x.data_ptr(), y.data_ptr(), n, grid, eps_deg_to_rad(eps_deg),
-                            mask.data_ptr() if n else 0, refine_rounds)
+                            mask.data_ptr() if n else 0, refine_rounds, s.cuda_stream)
         self._keep[t] = (x, y, mask)
         return t
 
@@ -731,13 +817,30 @@ class Server:
         return dict(q=list(r.q), count=int(r.inlier_count), status=int(r.status),
                     batched=int(r.batched), worker=int(r.worker),
                     refine_rounds_run=int(r.refine_rounds_run), t_submit=r.t_submit,
-                    t_start=r.t_start, t_end=r.t_end)
+                    t_start=r.t_start, t_end=r.t_end, scratch_bytes=int(r.scratch_bytes))
 
     def stats(self) -> dict:
         w, q, f = ct.c_int32(), ct.c_int64(), ct.c_int64()
         b = ct.c_int64()
         self._lib.rot_vote_server_stats(self._h, ct.byref(w), ct.byref(b), ct.byref(q), ct.byref(f))
         return dict(workers=w.value, device_bytes=b.value, queued=q.value, in_flight=f.value)
+
+    def memory(self) -> dict:
+        a, u, p, f = ct.c_int64(), ct.c_int64(), ct.c_int64(), ct.c_int64()
+        self._lib.rot_vote_server_memory(self._h, ct.byref(a), ct.byref(u), ct.byref(p),
+                                         ct.byref(f))
+        return dict(arena_bytes=a.value, in_use=u.value, peak_in_use=p.value,
+                    peak_in_flight=f.value)
+
+    def pause(self, paused: bool = True):
+        self._lib.rot_vote_server_pause(self._h, int(paused))
+
+    def request_bytes(self, n: int, grid: int) -> int:
+        b = ct.c_int64()
+        st = self._lib.rot_vote_server_request_bytes(self._h, n, grid, ct.byref(b))
+        if st != RV_OK:
+            raise RotVoteError(st, self._lib.rot_vote_server_last_error(self._h).decode())
+        return b.value
 
 
 class Probe:

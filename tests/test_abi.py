@@ -125,11 +125,14 @@ def test_server_config_checks_without_gpu(lib_path):
     lib.rot_vote_server_last_error.restype = ct.c_char_p
     lib.rot_vote_server_last_error.argtypes = [ct.c_void_p]
     assert ct.sizeof(ServerConfig) == 72  # 4 4 8 4 4 4 4 8 8 8 16
+    from paper_2506_11547_amd.rotvote import Reply, Request
+    assert ct.sizeof(Request) == 56  # 8 8 8 4 4 8 4 4 8
+    assert ct.sizeof(Reply) == 72    # 16 8 4 4 4 4 8 8 8 8
     cfg = ServerConfig()
     lib.rot_vote_server_default_config(ct.byref(cfg))
-    assert cfg.workers == 2 and cfg.max_batch == 64 and cfg.hbm_budget == 0
+    assert cfg.workers == 4 and cfg.max_batch == 64 and cfg.hbm_budget == 0
     h = ct.c_void_p()
-    for field, value in (("workers", 0), ("workers", 17), ("max_queue", 0), ("max_n", 0)):
+    for field, value in (("workers", 0), ("workers", 65), ("max_queue", 0), ("max_n", 0)):
         bad = ServerConfig()
         lib.rot_vote_server_default_config(ct.byref(bad))
         setattr(bad, field, value)

@@ -135,10 +135,26 @@ def test_batch_equals_single_solves(rv):
             assert np.array_equal(m1.cpu().numpy(), mb[offs[b]:offs[b + 1]]), b
 
 
-def test_full_batch_workload_sampled(rv, orc):
+def oracle_batch(orc, bt, G, J, eps_rad, K):
+    """The oracle's solve of every instance of a batch, on all host threads
+    (one instance per thread; the histogram itself is dropped)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    def one(b):
+        xb, yb = bt.instance(b)
+        o = orc.solve(xb, yb, G, J, eps_rad, K)
+        del o["hist"]
+        return o
+
+    with ThreadPoolExecutor(oracle.threads()) as ex:
+        return list(ex.map(one, range(bt.B)))
+
+
+def test_full_batch_workload_every_instance(rv, orc):
     """The 4096-instance batch (N log-uniform on [100, 20000]) in the
-    configuration the benchmark times (no grids kept): sampled instances,
-    including the smallest and largest, against the oracle."""
+    configuration the benchmark times (no grids kept): every instance against
+    the oracle (candidates, candidate counts, winner, rotation bits, count and
+    mask), then the accuracy the method promises."""
     w = datagen.BATCH_WORKLOADS["batch"]
     bt = w.batch()
     n = int(bt.offsets[-1])
@@ -147,25 +163,21 @@ def test_full_batch_workload_sampled(rv, orc):
                    max_batch=bt.B) as s:
         q, cnt, mask = s.solve_batch(dev(bt.x), dev(bt.y), bt.offsets, w.grid, w.eps_deg)
         m = mask.cpu().numpy()
+        ref = oracle_batch(orc, bt, w.grid, w.samples, rv.eps_deg_to_rad(w.eps_deg), w.topk)
+        for b in range(bt.B):
+            o = ref[b]
+            top = s.batch_topk(b)
+            assert top["votes"] == o["top_counts"].tolist(), b
+            assert top["idx"] == o["top_idx"].tolist(), b
+            assert top["inliers"] == o["cand_counts"].tolist(), b
+            assert top["winner"] == o["winner"], b
+            assert np.array_equal(np.float32(q[b]).view(np.uint32), o["q"].view(np.uint32)), b
+            assert cnt[b] == o["count"], b
+            assert np.array_equal(m[bt.offsets[b]:bt.offsets[b + 1]], o["mask"]), b
         bound = 4 * math.sqrt(3) / w.grid * 180 / math.pi
         err = np.array([datagen.rotation_error_deg(np.array(q[b]), bt.q_gt[b])
                         for b in range(bt.B)])
         enough = sizes * (1 - bt.outlier_ratio) >= 50
-        worst_enough = int(np.flatnonzero(enough)[np.argmax(err[enough])])
-        r = np.random.default_rng(0)
-        # sampled parity, including the smallest and largest instances and the
-        # least accurate ones (so that an accuracy miss is the method's, not the kernels')
-        pick = sorted(set([int(np.argmin(sizes)), int(np.argmax(sizes)), 0, bt.B - 1,
-                           int(np.argmax(err)), worst_enough] +
-                          r.choice(bt.B, 12, replace=False).tolist()))
-        for b in pick:
-            xb, yb = bt.instance(b)
-            check_instance(rv, s, b, q[b], cnt[b], m[bt.offsets[b]:bt.offsets[b + 1]], xb, yb,
-                           w.grid, w.samples, w.eps_deg, w.topk, orc, grids=False)
-        # every instance: the mask agrees with the count, the rotation is canonical
-        for b in range(bt.B):
-            assert int(m[bt.offsets[b]:bt.offsets[b + 1]].sum()) == cnt[b]
-            assert q[b][0] >= 0.0
         # accuracy: the centre of the true rotation's cell is within 4 sqrt(3) / G
         # rad of it (half a cell diagonal in the chart, at most doubled by the
         # inverse projection, doubled again from quaternion to rotation angle);
@@ -175,25 +187,180 @@ def test_full_batch_workload_sampled(rv, orc):
         assert np.mean(err < bound) > 0.95, np.mean(err < bound)
 
 
-def test_tuned_brick_edge_changes_speed_only(rv):
-    """rot_vote_tune_batch times 32^3 and 16^3 bricks on the batch and keeps
-    the faster; results are identical either way."""
-    bt = datagen.make_batch(300, 100, 8000, 0.5, 0.99, 0.5, 17)
+def test_tuned_schedule_changes_speed_only(rv, tmp_path):
+    """rot_vote_tune_batch chooses a brick edge per instance-size bucket by
+    timing the batch; results are identical under every schedule, and the
+    schedule survives a save and a load of the tuning file."""
+    import json
+    bt = datagen.make_batch(300, 100, 12000, 0.5, 0.99, 0.5, 17)
     x, y = dev(bt.x), dev(bt.y)
+    path = tmp_path / "tuning.json"
     with rv.Solver(max_n=int(bt.offsets[-1]), max_grid=64, topk=16, samples_per_circle=512,
                    max_batch=bt.B) as s:
+        assert s.batch_schedule(64) == [32] * rv.BATCH_BUCKETS
         q0, c0, m0 = s.solve_batch(x, y, bt.offsets, 64, 1.0)
         m0 = m0.clone()
-        edge, ms = s.tune_batch(x, y, bt.offsets, 64, 1.0, reps=1)
-        assert edge in (16, 32) and ms[16] > 0 and ms[32] > 0
-        assert edge == (16 if ms[16] < ms[32] else 32)
+        edges, ms = s.tune_batch(x, y, bt.offsets, 64, 1.0, reps=1)
+        assert all(e in (16, 32) for e in edges) and ms[0] > 0
+        assert s.batch_schedule(64) == edges
         q1, c1, m1 = s.solve_batch(x, y, bt.offsets, 64, 1.0)
         assert np.array_equal(q0, q1) and np.array_equal(c0, c1) and torch.equal(m0, m1)
+        s.set_batch_schedule(64, [16, 32, 16, 32])
+        s.save_tuning(path)
+        s.save_tuning(path)  # merging into an existing file keeps one entry per key
+    doc = json.loads(path.read_text())
+    assert doc["format"] == "rotvote-tuning"
+    batch = [e for e in doc["entries"] if e["kind"] == "batch"]
+    assert [e["edge"] for e in sorted(batch, key=lambda e: e["n_lo"])] == [16, 32, 16, 32]
+    assert all(e["grid"] == 64 and e["J"] == 512 for e in batch)
+    with rv.Solver(max_n=1000, max_grid=64, samples_per_circle=512, max_batch=4) as s:
+        assert s.load_tuning(path) == 4 and s.batch_schedule(64) == [16, 32, 16, 32]
+    with rv.Solver(max_n=1000, max_grid=64, samples_per_circle=300, max_batch=4) as s:
+        assert s.load_tuning(path) == 0  # another J: not applied
     with rv.Solver(max_n=1000, max_grid=64, max_batch=4, batch_brick_edge=16) as s:
         with pytest.raises(rv.RotVoteError):
             s.tune_batch(x, y, [0, 10], 64, 1.0)
+        with pytest.raises(rv.RotVoteError):
+            s.set_batch_schedule(64, [32] * 4)
+        assert s.batch_schedule(64) == [16] * 4
     with pytest.raises(rv.RotVoteError):
         rv.Solver(max_n=1000, max_grid=64, max_batch=4, batch_brick_edge=8)
+    bad = tmp_path / "bad.json"
+    bad.write_text("{}")
+    with rv.Solver(max_n=1000, max_grid=64, max_batch=4) as s:
+        with pytest.raises(rv.RotVoteError):
+            s.load_tuning(bad)
+        with pytest.raises(rv.RotVoteError):
+            s.set_batch_schedule(64, [16, 32, 8, 32])
+
+
+def bucket_instances(seed):
+    """Instances in every size bucket, around the bucket bounds."""
+    r = np.random.default_rng(seed)
+    sizes = [0, 1, 300, 511, 512, 600, 2047, 2048, 3000, 0, 8191, 8192, 9000, 7]
+    return [(d.x, d.y) for d in (datagen.make_instance(n, float(r.uniform(0.4, 0.95)), 0.5,
+                                                       seed * 100 + k)
+                                 for k, n in enumerate(sizes))]
+
+
+@pytest.mark.parametrize("sched", [[16, 32, 16, 32], [32, 16, 32, 16], [16] * 4, [32] * 4])
+@pytest.mark.parametrize("G,J,K", [(64, 512, 16), (33, 241, 8)])
+def test_mixed_brick_classes_match_oracle(rv, orc, sched, G, J, K):
+    """Instances of one batch in different brick-size classes (by their size
+    bucket): every instance against the oracle, vote grids included."""
+    inst = bucket_instances(G)
+    x, y, offs = concat(inst)
+    with rv.Solver(max_n=int(offs[-1]), max_grid=G, topk=K, samples_per_circle=J,
+                   max_batch=len(inst), batch_grids=True) as s:
+        s.set_batch_schedule(G, sched)
+        q, cnt, mask = s.solve_batch(dev(x), dev(y), offs, G, 1.5)
+        m = mask.cpu().numpy()
+        for b, (xb, yb) in enumerate(inst):
+            check_instance(rv, s, b, q[b], cnt[b], m[offs[b]:offs[b + 1]], xb, yb, G, J, 1.5, K,
+                           orc)
+
+
+def decode_results(rv, res, B):
+    return [rv.decode_result(res[b]) for b in range(B)]
+
+
+@pytest.mark.parametrize("mode", ["relaxed", "global"])
+def test_async_batch_in_a_graph_replayed_on_new_batches(rv, orc, mode):
+    """The device-planned batch captured once into a HIP graph, then replayed
+    on three new batches (new offsets and new columns written into the
+    captured buffers; eager batches and synchronisations between replays):
+    every instance of every replay against the oracle."""
+    B, cap = 24, 40000
+    G, J, K, eps = 64, 512, 16, 1.0
+    r = np.random.default_rng(5)
+    batches = []
+    for k in range(3):
+        sizes = r.integers(0, 2400, B)
+        sizes[k] = 0
+        sizes[k + 3] = 9000 if k == 1 else int(sizes[k + 3])
+        inst = [(d.x, d.y) for d in (datagen.make_instance(int(n), float(r.uniform(0.5, 0.95)),
+                                                           0.5, 900 + 50 * k + b)
+                                     for b, n in enumerate(sizes))]
+        batches.append(inst)
+    stream = torch.cuda.Stream()
+    xb = torch.zeros(3, cap, dtype=torch.float32, device="cuda")
+    yb = torch.zeros_like(xb)
+    ob = torch.zeros(B + 1, dtype=torch.int64, device="cuda")
+    res = torch.zeros(B, rv.RESULT_BYTES, dtype=torch.uint8, device="cuda")
+    mask = torch.zeros(cap, dtype=torch.bool, device="cuda")
+
+    def load(inst):
+        x, y, offs = concat(inst)
+        assert offs[-1] <= cap
+        xb.zero_()
+        yb.zero_()
+        xb[:, :offs[-1]].copy_(dev(x))
+        yb[:, :offs[-1]].copy_(dev(y))
+        ob.copy_(torch.from_numpy(offs))
+        return offs
+
+    with rv.Solver(max_n=cap, max_grid=G, topk=K, samples_per_circle=J, max_batch=B,
+                   stream=stream) as s, \
+            rv.Solver(max_n=cap, max_grid=G, topk=K, samples_per_circle=J, max_batch=B) as eager:
+        s.set_batch_schedule(G, [16, 32, 16, 32])
+        load(batches[0])
+        torch.cuda.synchronize()
+        with torch.cuda.stream(stream):
+            s.solve_batch_async(xb, yb, ob, G, eps, results=res, mask=mask)  # uploads the table
+        stream.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=stream, capture_error_mode=mode):
+            s.solve_batch_async(xb, yb, ob, G, eps, results=res, mask=mask)
+        torch.cuda.synchronize()
+        for rep in range(2):
+            for inst in batches:
+                offs = load(inst)
+                res.zero_()
+                torch.cuda.synchronize()
+                g.replay()
+                torch.cuda.synchronize()
+                got = decode_results(rv, res, B)
+                m = mask.cpu().numpy()
+                x, y, _ = concat(inst)
+                qe, ce, _ = eager.solve_batch(dev(x), dev(y), offs, G, eps)
+                for b, (xh, yh) in enumerate(inst):
+                    o = orc.solve(xh, yh, G, J, rv.eps_deg_to_rad(eps), K)
+                    assert np.array_equal(np.float32(got[b]["q"]).view(np.uint32),
+                                          o["q"].view(np.uint32)), (rep, b)
+                    assert got[b]["count"] == o["count"] and got[b]["winner"] == o["winner"]
+                    assert got[b]["n_cand"] == len(o["top_counts"])
+                    assert np.array_equal(m[offs[b]:offs[b + 1]], o["mask"]), (rep, b)
+                    assert got[b]["q"] == qe[b].tolist() and got[b]["count"] == ce[b]
+        del g
+
+
+def test_async_batch_invalid_offsets_on_device(rv):
+    """Offsets that break the rules are caught by the plan kernel: every
+    instance reports winner -2 and no mask entry is written."""
+    B = 4
+    x = torch.randn(3, 1000, device="cuda")
+    mask = torch.full((1000,), 7, dtype=torch.uint8, device="cuda")
+    with rv.Solver(max_n=1000, max_grid=64, topk=16, max_batch=B) as s:
+        for offs in ([0, 10, 5, 20, 30], [1, 10, 20, 30, 40], [0, 10, 20, 30, 1001]):
+            ob = torch.tensor(offs, dtype=torch.int64, device="cuda")
+            res, _ = s.solve_batch_async(x, x, ob, 64, 1.0, mask=mask)
+            torch.cuda.synchronize()
+            for r in decode_results(rv, res, B):
+                assert r == {"q": [1.0, 0.0, 0.0, 0.0], "count": 0, "winner": -2, "n_cand": 0}
+            assert int((mask != 7).sum()) == 0
+        # and a valid batch afterwards is planned afresh
+        ob = torch.tensor([0, 100, 100, 600, 1000], dtype=torch.int64, device="cuda")
+        res, m = s.solve_batch_async(x, x, ob, 64, 1.0, mask=mask.view(torch.bool))
+        torch.cuda.synchronize()
+        q, c, m2 = s.solve_batch(x, x, [0, 100, 100, 600, 1000], 64, 1.0)
+        got = decode_results(rv, res, B)
+        assert [g["count"] for g in got] == c.tolist()
+        host = np.zeros(16, np.uint8)
+        for bad_ptr in (host.ctypes.data, ob.data_ptr() + 4):
+            with pytest.raises(rv.RotVoteError) as e:
+                s.solve_batch_async_raw(x.data_ptr(), x.data_ptr(), 1000, bad_ptr, B, 64, 0.01,
+                                        res.data_ptr(), mask.data_ptr())
+            assert e.value.status == rv.RV_EINVAL
 
 
 def test_batch_error_conventions(rv):

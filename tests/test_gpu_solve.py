@@ -79,7 +79,7 @@ def test_small_workload_matches_golden_and_oracle(rv, orc):
     assert g["plan"]["samples_per_circle"] == w.samples
 
 
-STRATEGIES = ["global", "brick"]
+STRATEGIES = ["global", "brick", "keys"]
 
 
 @pytest.mark.parametrize("strategy", STRATEGIES)
@@ -122,12 +122,14 @@ def test_large_workload_full_parity(rv, orc):
     assert datagen.rotation_error_deg(g["q"], inst.q_gt) < 1.5
 
 
-def test_paper_default_workload_full_parity(rv, orc):
+@pytest.mark.parametrize("strategy", ["auto", "brick"])
+def test_paper_default_workload_full_parity(rv, orc, strategy):
     """The paper's default resolution (G = 360, J = 180; N = 1e6, 99 % outliers)
-    on the brick path with 9-bit packed cells, against the oracle in full."""
+    on the key path (the automatic choice there) and on the run path with
+    9-bit packed cells, against the oracle in full."""
     w, inst = datagen.make_workload("paper_default")
-    g = run_gpu(rv, inst.x, inst.y, w.grid, w.samples, w.eps_deg, w.topk)
-    assert g["plan"]["strategy"] == "brick"
+    g = run_gpu(rv, inst.x, inst.y, w.grid, w.samples, w.eps_deg, w.topk, strategy)
+    assert g["plan"]["strategy"] == ("keys" if strategy == "auto" else strategy)
     o = orc.solve(inst.x, inst.y, w.grid, w.samples, eps_rad(rv, w.eps_deg), w.topk,
                   nthreads=oracle.threads())
     check_parity(g, o, w.grid)
@@ -135,14 +137,18 @@ def test_paper_default_workload_full_parity(rv, orc):
 
 def test_auto_strategy_choice(rv):
     inst = datagen.make_instance(2000, 0.5, 1.0, 11)
-    for G, want in ((8, "global"), (64, "global"), (72, "brick"), (128, "brick"), (256, "brick"),
-                    (360, "brick"), (400, "global")):
-        g = run_gpu(rv, inst.x, inst.y, G, 8 * G, 1.0, 8)
-        assert g["plan"]["strategy"] == want, G
+    for G, J, want in ((8, 64, "global"), (64, 512, "global"), (72, 576, "brick"),
+                       (128, 1024, "brick"), (256, 2048, "brick"), (360, 2880, "brick"),
+                       (400, 3200, "global"), (360, 180, "keys"), (128, 256, "keys"),
+                       (128, 257, "brick"), (64, 100, "global")):
+        g = run_gpu(rv, inst.x, inst.y, G, J, 1.0, 8)
+        assert g["plan"]["strategy"] == want, (G, J)
 
 
-@pytest.mark.parametrize("G,J", [(128, 1024), (200, 1600), (300, 600)])
-def test_brick_queue_overflow_is_exact(rv, orc, G, J):
+@pytest.mark.parametrize("G,J,strategy", [(128, 1024, "brick"), (200, 1600, "brick"),
+                                          (300, 600, "brick"), (300, 600, "keys"),
+                                          (100, 150, "keys")])
+def test_brick_queue_overflow_is_exact(rv, orc, G, J, strategy):
     """Queue capacities come from every 64th correspondence, all of them
     random here; the others (all but every 32nd) are one repeated
     correspondence, so its bricks overflow and their excess runs take the
@@ -156,7 +162,7 @@ def test_brick_queue_overflow_is_exact(rv, orc, G, J):
     x[:, rep] = np.float32([[0.3], [-0.5], [0.8]])
     y[:, rep] = np.float32([[0.9], [0.1], [-0.2]])
     o = orc.solve(x, y, G, J, eps_rad(rv, 1.0), 16, nthreads=oracle.threads())
-    with rv.Solver(max_n=n, max_grid=G, topk=16, samples_per_circle=J, strategy="brick") as s:
+    with rv.Solver(max_n=n, max_grid=G, topk=16, samples_per_circle=J, strategy=strategy) as s:
         for _ in range(2):  # the overflow grid must be left zeroed for the next solve
             q, cnt, mask = s.solve(dev(x), dev(y), G, 1.0)
             g = dict(q=np.array(q, np.float32), count=cnt, mask=mask.cpu().numpy(),
@@ -283,8 +289,8 @@ def test_tuned_strategy_changes_speed_only(rv, orc, G):
         q0, c0, m0 = s.solve(x, y, G, 1.0)
         m0 = m0.clone()
         best, ms = s.tune(x, y, G, 1.0, reps=2)
-        assert best in ("global", "brick") and ms["global"] > 0 and ms["brick"] > 0
-        assert best == ("brick" if ms["brick"] < ms["global"] else "global")
+        assert best in ("global", "brick", "keys") and min(ms.values()) > 0
+        assert best == min(ms, key=ms.get)
         q1, c1, m1 = s.solve(x, y, G, 1.0)
         assert s.plan()["strategy"] == best
         assert q0 == q1 and c0 == c1 and torch.equal(m0, m1)
