@@ -147,10 +147,16 @@ TRAFFIC_RECORDS = {"large": ROOT / "profiles" / "vote_bin__large_traffic.json",
                    "rigid": ROOT / "profiles" / "vote_bin__rigid_traffic.json"}
 
 
-def vote_kernel_name(grid: int, edge: int = 0) -> str:
-    """The vote kernel instance a brick solve launches: brick edge 2^5 or 2^4
-    (a single solve takes 16 up to grid 128, else 32; a batch its tuned edge),
-    wide run layout above grid 256."""
+KEY_VOTE_KERNEL = "rv::k_vote_keys<rv::KeyPack<16, 16, 1> >"
+
+
+def vote_kernel_name(grid: int, edge: int = 0, strategy: str = "brick") -> str:
+    """The vote kernel instance a binned solve launches: for runs, brick edge
+    2^5 or 2^4 (a single solve takes 16 up to grid 128, else 32; a batch its
+    tuned edge) and the wide run layout above grid 256; for keys, the key
+    kernel."""
+    if strategy == "keys":
+        return KEY_VOTE_KERNEL
     if edge == 0:
         edge = 16 if grid <= 128 else 32
     return f"rv::k_vote_bin<{5 if edge == 32 else 4}, {'true' if grid > 256 else 'false'}>"
@@ -825,8 +831,9 @@ def main():
         "stage_ms": stage_ms,
         "strategy_tuning": tuned,
         "roofline": alu_roofline("vote", achieved,
-                                 (measured_traffic(w.name, vote_kernel_name(w.grid))
-                                  if plan["strategy"] == "brick" else None),
+                                 (measured_traffic(w.name, vote_kernel_name(
+                                     w.grid, strategy=plan["strategy"]))
+                                  if plan["strategy"] in ("brick", "keys") else None),
                                  ops_per_sample=OPS_PER_SAMPLE, samples_per_launch=samples,
                                  vote_ms=stage_ms["vote"]),
         "result": {"q": q, "inliers": cnt, "e_R_deg": datagen.rotation_error_deg(q, inst.q_gt),

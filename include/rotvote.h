@@ -208,7 +208,8 @@ rv_status rot_vote_solve_noalloc(const float *x, const float *y, int64_t n, int3
  *   mask_scratch   device uint8[n] written by the timed solves.
  *   strategy_out   host (may be NULL): RV_VOTE_GLOBAL, RV_VOTE_BRICK or RV_VOTE_KEYS.
  *   ms_out         host float[3] (may be NULL): mean wall time per solve of
- *                  {global, brick, keys} in ms; -1 for a strategy not available.
+ *                  {global, brick, keys} in ms; -1 for a strategy not available
+ *                  or not timed (keys are timed only for J <= 4 G).
  * Needs n >= 1; reps in 1..1000. */
 rv_status rot_vote_tune(rv_handle *h, const float *x, const float *y, int64_t n, int32_t grid,
                         float eps_rad, int32_t reps, uint8_t *mask_scratch, int32_t *strategy_out,

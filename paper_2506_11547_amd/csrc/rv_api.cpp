@@ -869,6 +869,11 @@ RV_API rv_status rot_vote_tune(rv_handle* h, const float* x, const float* y, int
     for (int c = 0; c < 3; ++c) {
         if (cand[c] != RV_VOTE_GLOBAL && !brick_ok)
             continue;
+        // keys write every sample; beyond J = 2 kKeysMaxRatio G the circle
+        // stays in a cell for several samples and keys cannot win (they then
+        // outnumber the run pool's room), so they are not timed
+        if (cand[c] == RV_VOTE_KEYS && J > 2 * kKeysMaxRatio * grid)
+            continue;
         h->forced_strategy = cand[c];
         rv_status st = rot_vote_solve(h, x, y, n, grid, eps_rad, q, &cnt, mask_scratch);  // warm-up
         const auto t0 = std::chrono::steady_clock::now();

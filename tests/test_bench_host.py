@@ -36,6 +36,10 @@ def test_more_than_one_gpu_is_refused():
 ])
 def test_vote_kernel_name(grid, edge, name):
     assert bench.vote_kernel_name(grid, edge) == name
+    # the key strategy has one kernel instance (the source's configuration)
+    assert bench.vote_kernel_name(grid, edge, "keys") == bench.KEY_VOTE_KERNEL
+    src = (ROOT / "paper_2506_11547_amd" / "csrc" / "rv_bin.hip").read_text()
+    assert "using Keys = KeyPack<16, 16, 1>;" in src
 
 
 def make_record(tmp_path, workload, kernel, digests):

@@ -289,8 +289,10 @@ def test_tuned_strategy_changes_speed_only(rv, orc, G):
         q0, c0, m0 = s.solve(x, y, G, 1.0)
         m0 = m0.clone()
         best, ms = s.tune(x, y, G, 1.0, reps=2)
-        assert best in ("global", "brick", "keys") and min(ms.values()) > 0
-        assert best == min(ms, key=ms.get)
+        assert best in ("global", "brick") and ms["global"] > 0 and ms["brick"] > 0
+        assert ms["keys"] == -1  # J = 8 G: keys are not timed
+        timed = {k: v for k, v in ms.items() if v > 0}
+        assert best == min(timed, key=timed.get)
         q1, c1, m1 = s.solve(x, y, G, 1.0)
         assert s.plan()["strategy"] == best
         assert q0 == q1 and c0 == c1 and torch.equal(m0, m1)
@@ -300,6 +302,26 @@ def test_tuned_strategy_changes_speed_only(rv, orc, G):
                                   None, None)
         assert st == rv.RV_EINVAL
     o = orc.solve(inst.x, inst.y, G, 8 * G, eps_rad(rv, 1.0), 16)
+    assert np.array_equal(np.float32(q1).view(np.uint32), o["q"].view(np.uint32))
+    assert c1 == o["count"]
+
+
+def test_tuned_strategy_among_three(rv, orc):
+    """At J <= 4 G the tuner times keys too and fixes the fastest of the three
+    strategies; results are unchanged."""
+    G, J = 300, 300
+    inst = datagen.make_instance(30000, 0.9, 1.0, 77)
+    with rv.Solver(max_n=inst.n, max_grid=G, topk=16, samples_per_circle=J) as s:
+        x, y = dev(inst.x), dev(inst.y)
+        q0, c0, m0 = s.solve(x, y, G, 1.0)
+        assert s.plan()["strategy"] == "keys"  # J <= 2 G
+        m0 = m0.clone()
+        best, ms = s.tune(x, y, G, 1.0, reps=2)
+        assert min(ms.values()) > 0 and best == min(ms, key=ms.get)
+        q1, c1, m1 = s.solve(x, y, G, 1.0)
+        assert s.plan()["strategy"] == best
+        assert q0 == q1 and c0 == c1 and torch.equal(m0, m1)
+    o = orc.solve(inst.x, inst.y, G, J, eps_rad(rv, 1.0), 16)
     assert np.array_equal(np.float32(q1).view(np.uint32), o["q"].view(np.uint32))
     assert c1 == o["count"]
 
