@@ -442,9 +442,14 @@ rv_status create_impl(rv_handle** out, const rv_config* cfg, bool lane)
     const size_t brick_cells = (size_t)(brick_grid * brick_grid * brick_grid);
     uint64_t runs = 0;
     if (want_brick) {
-        // One solve: about 1.7 G runs per circle are expected at J = 8 G (at
-        // most J); room for 3 G per circle plus the per-queue slack.
-        const uint64_t per_circle = (uint64_t)std::min<int64_t>(h->max_J, 3 * (int64_t)h->max_grid);
+        // One solve: about 1.7 G runs per circle are expected at J = 8 G, and
+        // up to J (every sample, the key strategy) when J is small; room for
+        // 1.25 x min(J, 3 G) per circle, since the plan asks for 1.15 x its
+        // estimate (a pool without that margin scales every queue down, and a
+        // few percent of the entries then take the overflow atomics), plus the
+        // per-queue slack.
+        const uint64_t per_circle = (uint64_t)std::ceil(
+            1.25 * (double)std::min<int64_t>(h->max_J, 3 * (int64_t)h->max_grid));
         runs = (uint64_t)h->max_n * per_circle + (uint64_t)rv::kQueueSets * rv::kMaxBricksAll * 320u;
     }
     if (h->max_batch > 0) {

@@ -20,49 +20,74 @@ namespace rv {
 
 constexpr int kPlanThreads = 1024;
 constexpr int kPlanWaves = kPlanThreads / 64;
-constexpr int kScanVals = 5;  // class-0 instances, class-0 units, class-1 units, units, runs
+// scanned per instance: class-0 instances, class-0 units, class-1 units,
+// units (32-bit), and run-pool slots (64-bit)
+constexpr int kScan32 = 4;
 
-// Inclusive scans of kScanVals 64-bit values across the workgroup: per wave
-// with shuffles, then over the wave totals; returns the exclusive prefix of
-// this thread plus the carry, and adds the block's totals to the carry.
-__device__ __forceinline__ void block_scan(uint64_t (&v)[kScanVals], uint64_t (&carry)[kScanVals],
-                                           uint64_t (*s_w)[kScanVals], int wave, int lane)
+// Inclusive scans across the workgroup (per wave with shuffles, then over the
+// wave totals): v and r become this thread's exclusive prefixes plus the
+// carries, and the block's totals are added to the carries.
+__device__ __forceinline__ void block_scan(uint32_t (&v)[kScan32], uint64_t& r,
+                                           uint32_t (&carry)[kScan32], uint64_t& rcarry,
+                                           uint32_t (*s_w)[kScan32], uint64_t* s_r, int wave,
+                                           int lane)
 {
-    uint64_t incl[kScanVals];
+    uint32_t incl[kScan32];
 #pragma unroll
-    for (int k = 0; k < kScanVals; ++k) {
+    for (int k = 0; k < kScan32; ++k) {
         incl[k] = v[k];
 #pragma unroll
         for (int off = 1; off < 64; off <<= 1) {
-            const uint32_t lo = __shfl_up((uint32_t)incl[k], off);
-            const uint32_t hi = __shfl_up((uint32_t)(incl[k] >> 32), off);
-            const uint64_t w = ((uint64_t)hi << 32) | lo;
-            incl[k] += lane >= off ? w : 0ull;
+            const uint32_t w = __shfl_up(incl[k], off);
+            incl[k] += lane >= off ? w : 0u;
         }
-        if (lane == 63)
+    }
+    uint64_t rincl = r;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t lo = __shfl_up((uint32_t)rincl, off);
+        const uint32_t hi = __shfl_up((uint32_t)(rincl >> 32), off);
+        rincl += lane >= off ? (((uint64_t)hi << 32) | lo) : 0ull;
+    }
+    if (lane == 63) {
+#pragma unroll
+        for (int k = 0; k < kScan32; ++k)
             s_w[wave][k] = incl[k];
+        s_r[wave] = rincl;
     }
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < kScanVals; ++k) {
-        uint64_t pre = 0, tot = 0;
+    for (int k = 0; k < kScan32; ++k) {
+        uint32_t pre = 0, tot = 0;
         for (int w = 0; w < kPlanWaves; ++w) {
-            pre += w < wave ? s_w[w][k] : 0ull;
-            tot += s_w[w][k];
+            const uint32_t x = s_w[w][k];
+            pre += w < wave ? x : 0u;
+            tot += x;
         }
         v[k] = carry[k] + pre + incl[k] - v[k];  // exclusive
         carry[k] += tot;
     }
+    uint64_t rpre = 0, rtot = 0;
+    for (int w = 0; w < kPlanWaves; ++w) {
+        const uint64_t x = s_r[w];
+        rpre += w < wave ? x : 0ull;
+        rtot += x;
+    }
+    r = rcarry + rpre + rincl - r;
+    rcarry += rtot;
     __syncthreads();
 }
 
-__device__ __forceinline__ int bucket_of(int64_t n)
+// The brick-size class (0: 16^3, 1: 32^3) of an instance of n
+// correspondences, from its size bucket.  Plain selects: indexing the
+// by-value kernel argument would copy it to scratch memory.
+__device__ __forceinline__ int class_of(const BatchPlanArgs& p, int64_t n)
 {
-    int k = 0;
-#pragma unroll
-    for (int i = 0; i < kBatchBuckets - 1; ++i)
-        k += n >= kBucketBound[i] ? 1 : 0;
-    return k;
+    const int8_t e = n < kBucketBound[0]   ? p.bucket_edge[0]
+                     : n < kBucketBound[1] ? p.bucket_edge[1]
+                     : n < kBucketBound[2] ? p.bucket_edge[2]
+                                           : p.bucket_edge[3];
+    return e == 4 ? 0 : 1;
 }
 
 // Queue capacity of every brick of an instance of n correspondences: its
@@ -72,7 +97,9 @@ __device__ __forceinline__ uint64_t inst_cap(const BatchPlanArgs& p, int cls, in
 {
     if (n <= 0)
         return 0;
-    uint64_t c = ((uint64_t)ceil(p.share[cls] * (double)n) + p.slack[cls] + 63u) & ~63ull;
+    const double share = cls ? p.share[1] : p.share[0];
+    const uint32_t slack = cls ? p.slack[1] : p.slack[0];
+    uint64_t c = ((uint64_t)ceil(share * (double)n) + slack + 63u) & ~63ull;
     if (f < 1.0)
         c = (uint64_t)((double)c * f) & ~63ull;
     return c;
@@ -83,7 +110,8 @@ __device__ __forceinline__ uint64_t inst_cap(const BatchPlanArgs& p, int cls, in
 // per-instance plan).
 __global__ __launch_bounds__(kPlanThreads) void k_batch_plan(BatchPlanArgs p)
 {
-    __shared__ uint64_t s_w[kPlanWaves][kScanVals];
+    __shared__ uint32_t s_w[kPlanWaves][kScan32];
+    __shared__ uint64_t s_r[kPlanWaves];
     __shared__ int s_bad;
     __shared__ uint64_t s_runs;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
@@ -98,8 +126,8 @@ __global__ __launch_bounds__(kPlanThreads) void k_batch_plan(BatchPlanArgs p)
         const int64_t n = p.offsets[b + 1] - p.offsets[b];
         if (n < 0 || n * (int64_t)p.J > (int64_t)INT32_MAX)
             atomicOr(&s_bad, 1);
-        const int cls = p.bucket_edge[bucket_of(n)] == 4 ? 0 : 1;
-        runs += inst_cap(p, cls, n, 1.0) * (uint64_t)p.nb[cls];
+        const int cls = class_of(p, n);
+        runs += inst_cap(p, cls, n, 1.0) * (uint64_t)(cls ? p.nb[1] : p.nb[0]);
     }
     atomicAdd((unsigned long long*)&s_runs, (unsigned long long)runs);
     __syncthreads();
@@ -117,7 +145,8 @@ __global__ __launch_bounds__(kPlanThreads) void k_batch_plan(BatchPlanArgs p)
         return;
     }
     const double f = s_runs > p.pool_runs ? (double)p.pool_runs / (double)s_runs : 1.0;
-    uint64_t carry[kScanVals] = {0, 0, 0, 0, 0};
+    uint32_t carry[kScan32] = {0, 0, 0, 0};
+    uint64_t rcarry = 0;
     for (int base = 0; base < B; base += kPlanThreads) {
         const int b = base + t;
         int64_t n = 0;
@@ -125,23 +154,23 @@ __global__ __launch_bounds__(kPlanThreads) void k_batch_plan(BatchPlanArgs p)
         uint64_t cap = 0;
         if (b < B) {
             n = p.offsets[b + 1] - p.offsets[b];
-            cls = p.bucket_edge[bucket_of(n)] == 4 ? 0 : 1;
+            cls = class_of(p, n);
             cap = inst_cap(p, cls, n, f);
         }
-        const uint64_t units = (uint64_t)((n + kUnitSize - 1) / kUnitSize);
-        uint64_t v[kScanVals] = {(b < B && cls == 0) ? 1ull : 0ull, cls == 0 ? units : 0ull,
-                                 cls == 1 ? units : 0ull, units,
-                                 b < B ? cap * (uint64_t)p.nb[cls] : 0ull};
-        block_scan(v, carry, s_w, wave, lane);
+        const uint32_t units = (uint32_t)((n + kUnitSize - 1) / kUnitSize);
+        uint32_t v[kScan32] = {(b < B && cls == 0) ? 1u : 0u, cls == 0 ? units : 0u,
+                               cls == 1 ? units : 0u, units};
+        uint64_t r = b < B ? cap * (uint64_t)(cls ? p.nb[1] : p.nb[0]) : 0ull;
+        block_scan(v, r, carry, rcarry, s_w, s_r, wave, lane);
         if (b < B) {
             InstPlan ip;
             ip.cls = cls;
-            ip.ci = cls == 0 ? (int32_t)v[0] : (int32_t)((uint64_t)b - v[0]);
+            ip.ci = cls == 0 ? (int32_t)v[0] : (int32_t)((uint32_t)b - v[0]);
             ip.unit0 = (int32_t)(cls == 0 ? v[1] : v[2]);
             ip.gunit0 = (int32_t)v[3];
             ip.nunits = (int32_t)units;
             ip.cap = (uint32_t)cap;
-            ip.rbase = (uint32_t)v[4];
+            ip.rbase = (uint32_t)r;
             ip.reserved = 0;
             p.inst[b] = ip;
         }
@@ -165,23 +194,29 @@ __global__ __launch_bounds__(256) void k_batch_expand(BatchPlanArgs p)
     if (b >= p.B || p.counts[5] == 0)
         return;
     const InstPlan ip = p.inst[b];
-    const int cls = ip.cls;
-    const int nb = p.nb[cls];
+    // plain selects (see class_of)
+    const bool c1 = ip.cls != 0;
+    const int nb = c1 ? p.nb[1] : p.nb[0];
+    uint32_t* cap = c1 ? p.cap[1] : p.cap[0];
+    uint32_t* qbase = c1 ? p.qbase[1] : p.qbase[0];
+    uint32_t* fill = c1 ? p.fill[1] : p.fill[0];
+    uint32_t* flags = c1 ? p.flags[1] : p.flags[0];
+    Unit* units = c1 ? p.units[1] : p.units[0];
     if (lane == 0)
-        p.inst_of[cls][ip.ci] = b;
+        (c1 ? p.inst_of[1] : p.inst_of[0])[ip.ci] = b;
     for (int k = lane; k < nb; k += 64) {
         const int64_t q = (int64_t)ip.ci * nb + k;
-        p.cap[cls][q] = ip.cap;
-        p.qbase[cls][q] = ip.rbase + (uint32_t)k * ip.cap;
-        p.fill[cls][q] = 0u;
-        p.flags[cls][q] = 0u;
+        cap[q] = ip.cap;
+        qbase[q] = ip.rbase + (uint32_t)k * ip.cap;
+        fill[q] = 0u;
+        flags[q] = 0u;
     }
     const int64_t first = p.offsets[b];
     const int64_t n = p.offsets[b + 1] - first;
     for (int j = lane; j < ip.nunits; j += 64) {
         const int64_t f = first + (int64_t)j * kUnitSize;
         const int32_t cnt = (int32_t)min<int64_t>(kUnitSize, n - (int64_t)j * kUnitSize);
-        p.units[cls][ip.unit0 + j] = Unit{ip.ci, cnt, f};
+        units[ip.unit0 + j] = Unit{ip.ci, cnt, f};
         p.units_all[ip.gunit0 + j] = Unit{b, cnt, f};
     }
 }
