@@ -309,6 +309,7 @@ __device__ __forceinline__ void bin_flush_sorted(uint32_t (*stage)[Pack<true>::k
     constexpr int kT = P::kThreads;
     constexpr int kPer = P::kMaxBricksHere / kT;
     static_assert(P::kWaves * P::kStageCap <= 65536, "16-bit sort index");
+    static_assert(P::kMaxBricksHere % kT == 0, "every brick has a thread in the scan");
     const int t = threadIdx.x;
     // 1: runs per brick (zero-length entries are marked dropped)
     for (uint32_t k = lane; k < my; k += kWave) {
@@ -537,10 +538,13 @@ __global__ __launch_bounds__(Pack<kWide>::kThreads, Pack<kWide>::kBlocksPerCU) v
 // than the samples).  Every sample is a key, brick index << 15 | cell within
 // its 32^3 brick, written by every lane at a fixed slot (sample, lane) of its
 // wave's staging, with no ballot or compaction; an unusable correspondence
-// writes a dropped marker.  Every kWindow samples (the same sample index in
-// every wave, so no flush check) the workgroup sorts its keys by brick (a
-// counting sort in LDS: counts, one reservation per brick, positions) and
-// stores them position by position into the bricks' queues as single votes
+// writes a dropped marker.  Each key is counted into its brick's LDS counter
+// as it is staged, and the count before it (its rank within the brick) kept
+// beside it.  Every kWindow samples (the same sample index in every wave, so
+// no flush check) the workgroup sorts its keys by brick (a counting sort in
+// LDS: one reservation per brick and a scan of the counts give each brick's
+// first position, and a key's position is that plus its rank) and stores
+// them position by position into the bricks' queues as single votes
 // (cell | 1 << 15), so one store instruction writes consecutive slots of a
 // few bricks' queues.  The brick accumulation is the run strategy's.
 template <int kWaves_, int kWindow_, int kBlocks_>
@@ -553,11 +557,13 @@ struct KeyPack {
     static constexpr int kSplit = kWindow;    // chunks of J for few circles
     static_assert(kWindow % 8 == 0, "the sample loop reads the table eight entries at a time");
     static_assert(kWaves * kStageCap <= 65536, "16-bit sort index");
+    static_assert(kMaxBricksAll % kThreads == 0, "every brick has a thread in the flush's scan");
 };
 // 16 waves in one workgroup per CU, flushing every 16 samples (1024 keys per
-// wave; 120 KiB of LDS): measured at G = 360, J = 180 against 8 waves in two
-// workgroups per CU with 16-sample (5 % slower) and 8-sample windows (29 %
-// slower): larger flushes write longer stretches of each brick's queue.
+// wave; 152 KiB of LDS with the ranks): measured at G = 360, J = 180 against 8
+// waves in two workgroups per CU with 16-sample (5 % slower) and 8-sample
+// windows (29 % slower), and 8 waves in one workgroup with 24-sample windows
+// (49 % slower): larger flushes write longer stretches of each brick's queue.
 using Keys = KeyPack<16, 16, 1>;
 
 constexpr uint32_t kKeyLocalBits = 15;  // cell within a 32^3 brick
@@ -571,7 +577,8 @@ __device__ __forceinline__ uint32_t key_of(const Cell& c, uint32_t nba)
 }
 
 template <class KP>
-__device__ __forceinline__ void keys_flush(uint32_t (*stage)[KP::kStageCap], uint32_t my,
+__device__ __forceinline__ void keys_flush(uint32_t (*stage)[KP::kStageCap],
+                                           uint16_t (*rank)[KP::kStageCap], uint32_t my,
                                            uint32_t* s_cnt, uint2* s_dst, uint32_t* s_scan,
                                            uint16_t* s_idx, uint32_t& s_total, int wave, int lane,
                                            int nb, int nba, int G, int xs, const BinArgs& a)
@@ -579,15 +586,8 @@ __device__ __forceinline__ void keys_flush(uint32_t (*stage)[KP::kStageCap], uin
     constexpr int kT = KP::kThreads;
     constexpr int kPer = kMaxBricksAll / kT;
     const int t = threadIdx.x;
-    // 1: keys per brick
-    for (uint32_t k = lane; k < my; k += kWave) {
-        const uint32_t e = stage[wave][k];
-        if (e != kDropped)
-            atomicAdd(&s_cnt[e >> kKeyLocalBits], 1u);
-    }
+    // the keys were counted per brick (and ranked) as they were staged
     __syncthreads();
-    // 2: a reservation per brick (issued first, so that its round trip
-    //    overlaps the scan) and the brick's first sorted position
     uint32_t c[kPer], g[kPer];
     uint32_t sum = 0;
 #pragma unroll
@@ -623,23 +623,18 @@ __device__ __forceinline__ void keys_flush(uint32_t (*stage)[KP::kStageCap], uin
                 const uint32_t room = cap > g[u] ? cap - g[u] : 0u;
                 s_dst[b] = make_uint2(a.qbase[q] + g[u] - pre, pre + min(room, c[u]));
             }
-            s_cnt[b] = pre;
+            s_cnt[b] = pre;  // the brick's first sorted position
             pre += c[u];
         }
     }
     __syncthreads();
-    // 3a: each key's stage index at its sorted position
+    // 3a: each key's stage index at its brick's first position plus its rank
     for (uint32_t k = lane; k < my; k += kWave) {
         const uint32_t e = stage[wave][k];
-        if (e != kDropped) {
-            const uint32_t pos = atomicAdd(&s_cnt[e >> kKeyLocalBits], 1u);
-            s_idx[pos] = (uint16_t)(wave * KP::kStageCap + k);
-        }
+        if (e != kDropped)
+            s_idx[s_cnt[e >> kKeyLocalBits] + rank[wave][k]] = (uint16_t)(wave * KP::kStageCap + k);
     }
     __syncthreads();
-    // 3b: the keys in brick order, as votes of one (past the queue's room: the
-    //    overflow grid); then the counters are cleared for the next flush, and
-    //    no wave stages again before every key is stored (closing barrier)
     const uint32_t total = s_total;
     const uint32_t* flat = &stage[0][0];
     for (uint32_t p = t; p < total; p += kT) {
@@ -670,6 +665,7 @@ __global__ __launch_bounds__(KP::kThreads, KP::kBlocksPerCU) void k_vote_keys(
     int J, int chunk, int ngroups, const float2* __restrict__ table, int nba, BinArgs a)
 {
     __shared__ uint32_t stage[KP::kWaves][KP::kStageCap];
+    __shared__ uint16_t rank[KP::kWaves][KP::kStageCap];
     __shared__ uint32_t s_cnt[kMaxBricksAll];
     __shared__ uint2 s_dst[kMaxBricksAll];
     __shared__ uint32_t s_scan[KP::kWaves];
@@ -690,14 +686,19 @@ __global__ __launch_bounds__(KP::kThreads, KP::kBlocksPerCU) void k_vote_keys(
     Quat u, v;
     const bool ok = load_circle(x, y, n, i, u, v);
     uint32_t* my_stage = stage[wave];
+    uint16_t* my_rank = rank[wave];
     const uint32_t unba = (uint32_t)nba;
     for (int js = j0; js < j1; js += KP::kWindow) {
         const int je = min(j1, js + KP::kWindow);
         for_samples<true>(u, v, table, js, je, H, gm, [&](const Cell& c, int j) {
-            my_stage[(j - js) * kWave + lane] = ok ? key_of(c, unba) : kDropped;
+            const uint32_t key = key_of(c, unba);
+            const int slot = (j - js) * kWave + lane;
+            my_stage[slot] = ok ? key : kDropped;
+            if (ok)
+                my_rank[slot] = (uint16_t)atomicAdd(&s_cnt[key >> kKeyLocalBits], 1u);
         });
-        keys_flush<KP>(stage, (uint32_t)(je - js) * kWave, s_cnt, s_dst, s_scan, s_idx, s_total,
-                       wave, lane, nb, nba, G, xs, a);
+        keys_flush<KP>(stage, rank, (uint32_t)(je - js) * kWave, s_cnt, s_dst, s_scan, s_idx,
+                       s_total, wave, lane, nb, nba, G, xs, a);
     }
 }
 
