@@ -126,6 +126,7 @@ def measured_ceilings(full: bool = False) -> dict:
         out["global_atomic_contiguous_per_s"] = {
             f"{mib}MiB": p.ceiling_global_atomic(mib << 18, contiguous=True) for mib in (1, 64)}
         out["copy_gb_s"] = p.ceiling_copy() / 1e9
+        out["read_gb_s"] = p.ceiling_read() / 1e9
     _CEILINGS[key] = out
     return out
 

@@ -78,6 +78,10 @@ int rvp_ceil_global_atomic(int64_t cells, int blocks, int iters, int contiguous,
  * multiple of 16). */
 int rvp_ceil_copy(int64_t bytes, double *bytes_per_s);
 
+/* Bytes read per second by a streaming read of `bytes` (a multiple of 16),
+ * four independent 16-byte loads per thread and step. */
+int rvp_ceil_read(int64_t bytes, double *bytes_per_s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -733,7 +733,8 @@ rv_status vote_candidates(rv_handle* h, const float* x, const float* y, int64_t 
         RV_HIP(h, hipEventRecord(h->ev[2], s), "event");
     int nlists;
     if (brick) {
-        RV_HIP(h, rv::launch_brick_accum(grid, h->K, edge, h->d_hist, h->d_partial, h->bin, s),
+        RV_HIP(h, rv::launch_brick_accum(grid, h->K, edge, !keys && grid <= rv::kNarrowGrid,
+                                         h->d_hist, h->d_partial, h->bin, s),
                "brick accumulate");
         const int nba = rv::brick_axis(grid, edge);
         nlists = nba * nba * nba;
@@ -1255,7 +1256,7 @@ rv_status enqueue_batch(rv_handle* h, const float* x, const float* y, int64_t n_
         RV_HIP(h, hipEventRecord(h->ev[2], s), "event");
     for (int c = 1; c >= 0; --c)
         if (use[c])
-            RV_HIP(h, rv::launch_brick_accum(grid, h->K, edge[c],
+            RV_HIP(h, rv::launch_brick_accum(grid, h->K, edge[c], true,
                                              h->batch_grids ? h->d_bgrids : nullptr,
                                              h->d_cpartial[c], a[c], s),
                    "batch brick accumulate");

@@ -39,11 +39,13 @@ struct Brick {
     static constexpr int kWaves = kThreads / kWave;
 };
 constexpr int kSets = kQueueSets;
+typedef uint32_t v4u __attribute__((ext_vector_type(4)));  // for non-temporal loads
 constexpr int kStep = 8;  // samples between flush checks
-// A staged run is its packed cell with the run length above it: 8-bit axes
-// and an 8-bit length (runs cut every 240 samples) for G <= 256, 9-bit axes
-// and a 5-bit length (cut every 24 samples) for G <= 384.  Cuts are multiples
-// of 8 samples: the sample loop reads the table eight entries at a time.
+// A staged run is its cell and its length: for G <= 256 the cell one byte
+// per axis in bytes 1-3 and the length in byte 0 (runs cut every 240
+// samples); for G <= 384 the cell 9 bits per axis with a 5-bit length above
+// it (cut every 24 samples).  Cuts are multiples of 8 samples: the sample
+// loop reads the table eight entries at a time.
 template <bool kWide>
 struct Pack {
     static constexpr int kBits = kWide ? 9 : 8;
@@ -89,6 +91,30 @@ __device__ __forceinline__ uint32_t local_of(uint32_t pc)
     const uint32_t ix = pc & P::kAxis, iy = (pc >> P::kBits) & P::kAxis,
                    iz = (pc >> (2 * P::kBits)) & P::kAxis;
     return ((iz & m) << (2 * kLog)) | ((iy & m) << kLog) | (ix & m);
+}
+
+// Narrow staged runs (G <= 256): the cell one byte per axis in bytes 1-3
+// (Cell::r8) and the run length in byte 0.  Their queue entries keep the
+// brick-local coordinates in place (the low kLog bits of bytes 1-3) with the
+// length: a mask, where the accumulation, which has ALU to spare, takes them
+// apart.
+template <int kLog>
+__device__ __forceinline__ uint32_t run_brick(uint32_t e, int nba)
+{
+    const uint32_t bx = __builtin_amdgcn_ubfe(e, 8 + kLog, 8 - kLog);
+    const uint32_t by = __builtin_amdgcn_ubfe(e, 16 + kLog, 8 - kLog);
+    const uint32_t bz = e >> (24 + kLog);
+    return __umul24(__umul24(bz, (uint32_t)nba) + by, (uint32_t)nba) + bx;
+}
+template <int kLog>
+constexpr uint32_t kSpreadMask = (Brick<kLog>::kMask << 8) | (Brick<kLog>::kMask << 16) |
+                                 (Brick<kLog>::kMask << 24) | 0xFFu;
+template <int kLog>
+__device__ __forceinline__ uint32_t spread_local(uint32_t e)
+{
+    // x + edge * y from bytes 1 and 2 by a byte dot product, plus z << 2 kLog
+    constexpr uint32_t kWeights = (1u << 8) | ((uint32_t)Brick<kLog>::kEdge << 16);
+    return __builtin_amdgcn_udot4(e, kWeights, (e >> 24) << (2 * kLog), false);
 }
 
 }  // namespace
@@ -234,12 +260,12 @@ __global__ __launch_bounds__(kPlanThreads) void k_bin_plan(BinArgs a, int nb)
 
 // ------------------------------------------------------------ vote + bin
 
-// Staged runs: cell packed one byte per axis, run length in the top byte.
-// Flush: runs counted per brick, one reservation atomic per brick, then each
-// written to its queue slot as brick-local cell | length << 15 (or, past the
+// Narrow staged runs (cell in bytes 1-3, length in byte 0).  Flush: runs
+// counted per brick, one reservation atomic per brick, then each written to
+// its queue slot as its spread brick-local cell and length (or, past the
 // queue's capacity, added to the overflow grid).
-template <int kLog, bool kWide>
-__device__ __forceinline__ void bin_flush(uint32_t (*stage)[Pack<kWide>::kStageCap], uint32_t my,
+template <int kLog>
+__device__ __forceinline__ void bin_flush(uint32_t (*stage)[Pack<false>::kStageCap], uint32_t my,
                                           uint32_t* s_cnt, uint2* s_dst, int wave, int lane, int nb,
                                           int nba, int G, int xs, int qoff, int64_t ovf_off,
                                           const BinArgs& a)
@@ -247,16 +273,16 @@ __device__ __forceinline__ void bin_flush(uint32_t (*stage)[Pack<kWide>::kStageC
     // 1: runs per brick (zero-length entries are marked dropped)
     for (uint32_t k = lane; k < my; k += kWave) {
         const uint32_t e = stage[wave][k];
-        if ((e >> Pack<kWide>::kLenShift) == 0u) {
+        if ((e & 0xFFu) == 0u) {
             stage[wave][k] = kDropped;
             continue;
         }
-        atomicAdd(&s_cnt[brick_of<kLog, kWide>(e & Pack<kWide>::kCellMask, nba)], 1u);
+        atomicAdd(&s_cnt[run_brick<kLog>(e, nba)], 1u);
     }
     __syncthreads();
     // 2: one reservation per brick in its queue; the first pool slot of this
     //    flush's runs and the room left before the queue's capacity
-    for (int b = threadIdx.x; b < nb; b += Pack<kWide>::kThreads) {
+    for (int b = threadIdx.x; b < nb; b += Pack<false>::kThreads) {
         const uint32_t c = s_cnt[b];
         if (c) {
             const int64_t q = (int64_t)xs * a.qstride + qoff + b;
@@ -266,26 +292,22 @@ __device__ __forceinline__ void bin_flush(uint32_t (*stage)[Pack<kWide>::kStageC
         }
     }
     __syncthreads();
-    // 3: each run to its slot (brick and cell recomputed from the staged
-    //    entry).  Ranks count each brick's total back down to zero, so the
-    //    counters are clear for the next flush once every wave is through
-    //    here; the step barrier that precedes any flush guarantees that.
+    // 3: each run to its slot (brick recomputed from the staged entry).  Ranks
+    //    count each brick's total back down to zero, so the counters are clear
+    //    for the next flush once every wave is through here; the step barrier
+    //    that precedes any flush guarantees that.
     for (uint32_t k = lane; k < my; k += kWave) {
         const uint32_t e = stage[wave][k];
         if (e == kDropped)
             continue;
-        const uint32_t pc = e & Pack<kWide>::kCellMask;
-        const uint32_t len = e >> Pack<kWide>::kLenShift;
-        const uint32_t b = brick_of<kLog, kWide>(pc, nba);
+        const uint32_t b = run_brick<kLog>(e, nba);
         const uint32_t rank = atomicSub(&s_cnt[b], 1u) - 1u;
         const uint2 d = s_dst[b];
         if (rank < d.y) {
-            a.pool[(uint64_t)(d.x + rank)] = local_of<kLog, kWide>(pc) | (len << 15);
+            a.pool[(uint64_t)(d.x + rank)] = e & kSpreadMask<kLog>;
         } else {
-            using P = Pack<kWide>;
-            const int64_t cell = ((int64_t)((pc >> (2 * P::kBits)) & P::kAxis) * G +
-                                  ((pc >> P::kBits) & P::kAxis)) * G + (pc & P::kAxis);
-            atomicAdd(a.ovf + ovf_off + cell, (int32_t)len);
+            const int64_t cell = ((int64_t)(e >> 24) * G + ((e >> 16) & 0xFFu)) * G + ((e >> 8) & 0xFFu);
+            atomicAdd(a.ovf + ovf_off + cell, (int32_t)(e & 0xFFu));
             a.flags[qoff + b] = 1u;
         }
     }
@@ -465,13 +487,15 @@ __global__ __launch_bounds__(Pack<kWide>::kThreads, Pack<kWide>::kBlocksPerCU) v
     Quat u, v;
     const bool ok = load_circle(x, y, n, i0 + threadIdx.x, u, v) && (i0 + threadIdx.x < iend);
     uint32_t fill = 0;  // this wave's staged runs (wave-uniform)
-    // The open run of each lane: its cell and length.  A run is emitted when
-    // the cell changes and at every run-block end, where its length restarts
-    // from 0; a block whose first sample leaves that cell emits a zero-length
-    // entry, which the flush drops.  The first run starts with a real cell of
-    // zero length for the same reason.
+    // The open run of each lane: its cell and length (narrow: `run`, the cell
+    // in bytes 1-3 and the length in byte 0, kept as the staged entry itself).
+    // A run is emitted when the cell changes and at every run-block end, where
+    // its length restarts from 0; a block whose first sample leaves that cell
+    // emits a zero-length entry, which the flush drops.  The first run starts
+    // with a real cell of zero length for the same reason.
     uint32_t cur = 0u;
     uint32_t cnt = 0u;
+    uint32_t run = 0u;
     uint32_t* my_stage = stage[wave];
     int slot = 0;
 
@@ -485,7 +509,7 @@ __global__ __launch_bounds__(Pack<kWide>::kThreads, Pack<kWide>::kBlocksPerCU) v
         const uint32_t r = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
                                                      __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
         const bool mine = change && ok;
-        *(mine ? (my_stage + fill + r) : my_dummy) = cur | (cnt << P::kLenShift);
+        *(mine ? (my_stage + fill + r) : my_dummy) = kWide ? cur | (cnt << P::kLenShift) : run;
         fill += (uint32_t)__popcll(m);
     };
 
@@ -494,7 +518,7 @@ __global__ __launch_bounds__(Pack<kWide>::kThreads, Pack<kWide>::kBlocksPerCU) v
             bin_flush_sorted<kLog>(stage, my, s_cnt, s_dst, &s_dummy[0][0], s_idx, s_total, wave,
                                    lane, nb, nba, G, xs, qoff, ovf_off, a);
         else
-            bin_flush<kLog, kWide>(stage, my, s_cnt, s_dst, wave, lane, nb, nba, G, xs, qoff,
+            bin_flush<kLog>(stage, my, s_cnt, s_dst, wave, lane, nb, nba, G, xs, qoff,
                                    ovf_off, a);
     };
 
@@ -502,11 +526,19 @@ __global__ __launch_bounds__(Pack<kWide>::kThreads, Pack<kWide>::kBlocksPerCU) v
         const int je = min(j1, jb + kSplit);
         for (int js = jb; js < je; js += kStep) {
             for_samples<true>(u, v, table, js, min(je, js + kStep), H, gm, [&](const Cell& c, int) {
-                const uint32_t pc = packed_coords<kWide>(c);
-                const bool change = pc != cur;
-                emit(change);
-                cnt = change ? 1u : cnt + 1u;
-                cur = change ? pc : cur;
+                if constexpr (kWide) {
+                    const uint32_t pc = packed_coords<kWide>(c);
+                    const bool change = pc != cur;
+                    emit(change);
+                    cnt = change ? 1u : cnt + 1u;
+                    cur = change ? pc : cur;
+                } else {
+                    // the run grows by one sample, or a new one opens here
+                    const bool change = c.r8 != cur;
+                    emit(change);
+                    run = (change ? c.r8 : run) + 1u;
+                    cur = c.r8;
+                }
             });
             if (lane == 0)
                 atomicMax(&s_maxfill[slot], fill);
@@ -522,6 +554,7 @@ __global__ __launch_bounds__(Pack<kWide>::kThreads, Pack<kWide>::kBlocksPerCU) v
         }
         emit(true);  // close every run at the block end (run lengths stay below 256)
         cnt = 0u;
+        run &= ~0xFFu;
     }
     if (lane == 0)
         atomicMax(&s_maxfill[slot], fill);
@@ -704,7 +737,9 @@ __global__ __launch_bounds__(KP::kThreads, KP::kBlocksPerCU) void k_vote_keys(
 
 // ----------------------------------------------------------- accumulate
 
-template <int kLog>
+// kSpread: queue entries of narrow runs (spread local cell, length in byte
+// 0); else the brick-local cell with the length above bit 15 (wide runs, keys).
+template <int kLog, bool kSpread>
 __global__ __launch_bounds__(Brick<kLog>::kThreads) void k_brick_accum(BinArgs a, int G, int nba, int K,
                                                                    int32_t* __restrict__ grid,
                                                                    uint64_t* __restrict__ partial)
@@ -740,6 +775,7 @@ __global__ __launch_bounds__(Brick<kLog>::kThreads) void k_brick_accum(BinArgs a
             inst = 0;
             b = (int)a.order[item];
         }
+        const int set0 = 0, set1 = a.nsets;
         const int qoff = inst * nb;
         // this instance's grid and overflow grid (by its index in the batch)
         const int64_t gofs = (int64_t)(a.inst_of ? a.inst_of[inst] : inst) * G * G * G;
@@ -752,13 +788,21 @@ __global__ __launch_bounds__(Brick<kLog>::kThreads) void k_brick_accum(BinArgs a
         __syncthreads();
 
         const uint32_t cap = a.cap[qoff + b];
-        // Software-pipelined queue reads: the next 8 KiB per wave are in flight
-        // while the current ones are added into LDS.  Queues start on 64-run
-        // boundaries and their capacity is a multiple of 64, so vector loads of
-        // 4 runs starting below the fill count stay inside the queue.
+        // The item's queue sets are read concurrently: the waves split into as
+        // many groups as there are sets (at most one per wave), each group
+        // streaming its sets in turn, so the latency of one set's first reads
+        // overlaps the others'.  Software-pipelined queue reads: the next 8 KiB
+        // per wave are in flight while the current ones are added into LDS.
+        // Queues start on 64-run boundaries and their capacity is a multiple
+        // of 64, so vector loads of 4 runs starting below the fill count stay
+        // inside the queue.
         constexpr int kUnroll = 8;
-        constexpr uint32_t kStride = kAccumThreads * 4;
-        for (int xs = 0; xs < a.nsets; ++xs) {
+        const int nset_here = set1 - set0;
+        const int groups = min(kAccumWaves, nset_here);
+        const int wpg = kAccumWaves / max(groups, 1);
+        const int grp = wave / wpg;
+        const uint32_t kStride = (uint32_t)wpg * kWave * 4;
+        for (int xs = set0 + grp; grp < groups && xs < set1; xs += groups) {
             const uint32_t cnt = min(a.fill[(int64_t)xs * a.qstride + qoff + b], cap);
             const uint32_t* q = a.pool + a.qbase[(int64_t)xs * a.qstride + qoff + b];
             if (cnt == 0)
@@ -767,11 +811,23 @@ __global__ __launch_bounds__(Brick<kLog>::kThreads) void k_brick_accum(BinArgs a
             // compiler can keep the next batch in flight across the LDS atomics
             const uint32_t last = (cnt - 1u) & ~3u;
             uint4 cur[kUnroll], nxt[kUnroll];
-            uint32_t k0 = threadIdx.x * 4;
+            auto add_entry = [&](uint32_t e) {
+                if constexpr (kSpread)
+                    atomicAdd(&acc[spread_local<kLog>(e)], e & 0xFFu);
+                else
+                    atomicAdd(&acc[e & 0x7FFFu], e >> 15);
+            };
+            uint32_t k0 = (uint32_t)((wave - grp * wpg) * kWave + lane) * 4;
+            // non-temporal: each entry is read once, and streaming the queues
+            // through L2 as ordinary lines took 12 % (one solve) to 25 % (the
+            // key strategy's many small queues) longer
             auto load = [&](uint4 (&r)[kUnroll], uint32_t base) {
     #pragma unroll
-                for (int u = 0; u < kUnroll; ++u)
-                    r[u] = *reinterpret_cast<const uint4*>(q + min(base + u * kStride, last));
+                for (int u = 0; u < kUnroll; ++u) {
+                    const v4u t = __builtin_nontemporal_load(
+                        reinterpret_cast<const v4u*>(q + min(base + u * kStride, last)));
+                    r[u] = make_uint4(t.x, t.y, t.z, t.w);
+                }
             };
             load(cur, k0);
             while (k0 < cnt) {
@@ -781,10 +837,10 @@ __global__ __launch_bounds__(Brick<kLog>::kThreads) void k_brick_accum(BinArgs a
                 for (int u = 0; u < kUnroll; ++u) {
                     const uint32_t k = k0 + u * kStride;
                     // entries past cnt add nothing
-                    if (k < cnt) atomicAdd(&acc[cur[u].x & 0x7FFFu], cur[u].x >> 15);
-                    if (k + 1 < cnt) atomicAdd(&acc[cur[u].y & 0x7FFFu], cur[u].y >> 15);
-                    if (k + 2 < cnt) atomicAdd(&acc[cur[u].z & 0x7FFFu], cur[u].z >> 15);
-                    if (k + 3 < cnt) atomicAdd(&acc[cur[u].w & 0x7FFFu], cur[u].w >> 15);
+                    if (k < cnt) add_entry(cur[u].x);
+                    if (k + 1 < cnt) add_entry(cur[u].y);
+                    if (k + 2 < cnt) add_entry(cur[u].z);
+                    if (k + 3 < cnt) add_entry(cur[u].w);
                 }
     #pragma unroll
                 for (int u = 0; u < kUnroll; ++u)
@@ -893,9 +949,9 @@ int accum_blocks(int edge_log2, int items)
             return items;
         const hipError_t e =
             edge_log2 == 5
-                ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_brick_accum<5>,
+                ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_brick_accum<5, true>,
                                                                Brick<5>::kThreads, 0)
-                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_brick_accum<4>,
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_brick_accum<4, true>,
                                                                Brick<4>::kThreads, 0);
         if (e != hipSuccess || cus < 1 || occ < 1)
             return items;
@@ -1015,10 +1071,10 @@ hipError_t launch_bin_vote(const float* x, const float* y, int64_t n, int G, int
     return hipGetLastError();
 }
 
-hipError_t launch_brick_accum(int G, int K, int edge_log2, int32_t* grid, uint64_t* partial,
-                              const BinArgs& a, hipStream_t s)
+hipError_t launch_brick_accum(int G, int K, int edge_log2, bool spread, int32_t* grid,
+                              uint64_t* partial, const BinArgs& a, hipStream_t s)
 {
-    if (edge_log2 != 4 && edge_log2 != 5)
+    if ((edge_log2 != 4 && edge_log2 != 5) || (edge_log2 == 4 && !spread))
         return hipErrorInvalidValue;
     const int nba = brick_axis(G, edge_log2);
     const int nb = nba * nba * nba;
@@ -1034,12 +1090,15 @@ hipError_t launch_brick_accum(int G, int K, int edge_log2, int32_t* grid, uint64
     // for its upper bound of bricks)
     const int blocks = (a.batch && (edge_log2 == 5 || a.counts)) ? accum_blocks(edge_log2, a.batch * nb)
                                                                  : (a.batch ? a.batch * nb : nb);
-    if (edge_log2 == 5)
-        hipLaunchKernelGGL(k_brick_accum<5>, dim3(blocks), dim3(Brick<5>::kThreads), 0, s, a, G, nba,
-                           K, grid, partial);
+    if (edge_log2 == 4)
+        hipLaunchKernelGGL((k_brick_accum<4, true>), dim3(blocks), dim3(Brick<4>::kThreads), 0, s, a,
+                           G, nba, K, grid, partial);
+    else if (spread)
+        hipLaunchKernelGGL((k_brick_accum<5, true>), dim3(blocks), dim3(Brick<5>::kThreads), 0, s, a,
+                           G, nba, K, grid, partial);
     else
-        hipLaunchKernelGGL(k_brick_accum<4>, dim3(blocks), dim3(Brick<4>::kThreads), 0, s, a, G, nba,
-                           K, grid, partial);
+        hipLaunchKernelGGL((k_brick_accum<5, false>), dim3(blocks), dim3(Brick<5>::kThreads), 0, s, a,
+                           G, nba, K, grid, partial);
     return hipGetLastError();
 }
 

@@ -1,7 +1,8 @@
 // Micro-benchmarks of the ceilings that can bound the solve's kernels on the
 // GPU they run on: 32-bit VALU issue (independent FMA chains), LDS atomic adds
 // (random and bank-distinct addresses), relaxed device-scope atomic adds on a
-// grid of a given size (random cells), and a streaming device copy.  The
+// grid of a given size (random cells), a streaming device copy and a
+// streaming read.  The
 // benchmark divides the vote's achieved rate by these as well as by the
 // published peaks.  Measurement hooks only: not used by a solve.
 //
@@ -97,6 +98,30 @@ __global__ __launch_bounds__(256) void k_ceil_copy(const uint4* __restrict__ src
     const int64_t stride = (int64_t)gridDim.x * 256;
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride)
         dst[i] = src[i];
+}
+
+// Streaming read: every thread sums four independent 16-byte loads per
+// step (so several are in flight), writing one word per thread at the end.
+__global__ __launch_bounds__(256) void k_ceil_read(const uint4* __restrict__ src,
+                                                   uint32_t* __restrict__ out, int64_t n)
+{
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    uint32_t acc[4] = {0u, 0u, 0u, 0u};
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    for (; i + 3 * stride < n; i += 4 * stride) {
+        uint4 v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            v[u] = src[i + u * stride];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            acc[u] += v[u].x ^ v[u].y ^ v[u].z ^ v[u].w;
+    }
+    for (; i < n; i += stride) {
+        const uint4 v = src[i];
+        acc[0] += v.x ^ v.y ^ v.z ^ v.w;
+    }
+    out[(int64_t)blockIdx.x * 256 + threadIdx.x] = acc[0] + acc[1] + acc[2] + acc[3];
 }
 
 // Runs launch() twice and returns the second run's milliseconds in *ms.
@@ -227,6 +252,41 @@ RVP_API int rvp_ceil_global_atomic(int64_t cells, int blocks, int iters, int con
     if (total != 2 * adds)  // two launches
         return -1;
     *atomics_per_s = (double)adds / (ms * 1e-3);
+    return 0;
+}
+
+// Streaming read of `bytes` (a multiple of 16): bytes read per second.
+RVP_API int rvp_ceil_read(int64_t bytes, double* bytes_per_s)
+{
+    if (bytes <= 0 || bytes % 16 || !bytes_per_s)
+        return -1;
+    constexpr int kBlocks = 256 * 32;
+    uint4* src = nullptr;
+    uint32_t* out = nullptr;
+    if (hipMalloc(&src, (size_t)bytes) != hipSuccess)
+        return -1;
+    if (hipMalloc(&out, (size_t)kBlocks * 256 * sizeof(uint32_t)) != hipSuccess) {
+        (void)hipFree(src);
+        return -1;
+    }
+    // every word 0x01010101: each 16-byte load xors to 0, so every sum is 0
+    int rc = hipMemset(src, 1, (size_t)bytes) == hipSuccess ? 0 : -1;
+    const int64_t n = bytes / 16;
+    float ms = 0.0f;
+    if (!rc)
+        rc = timed([&] {
+            hipLaunchKernelGGL(k_ceil_read, dim3(kBlocks), dim3(256), 0, 0, src, out, n);
+        }, &ms);
+    uint32_t first = 1u;
+    if (!rc && hipMemcpy(&first, out, sizeof(first), hipMemcpyDeviceToHost) != hipSuccess)
+        rc = -1;
+    (void)hipFree(src);
+    (void)hipFree(out);
+    if (rc)
+        return rc;
+    if (first != 0u)
+        return -1;
+    *bytes_per_s = (double)bytes / (ms * 1e-3);
     return 0;
 }
 

@@ -109,6 +109,7 @@ __device__ __forceinline__ float recip_1_2(float d)
 struct Cell {
     unsigned x, y, z;
     unsigned y_b1;  // y << 8 when G <= 256 (see cell_coords); unused values cost nothing
+    unsigned r8;    // x << 8 | y << 16 | z << 24 when G <= 256
 };
 
 template <bool kFastRecip>
@@ -139,6 +140,19 @@ __device__ __forceinline__ Cell cell_coords(float qw, float qx, float qy, float 
     asm("v_cvt_u32_f32_sdwa %0, %1 dst_sel:BYTE_1 dst_unused:UNUSED_PAD src0_sel:DWORD"
         : "=v"(c.y_b1)
         : "v"(my));
+    // The cell one byte per axis in bytes 1-3 (G <= 256; byte 0 free for a
+    // run length), each conversion written into its byte of a zeroed register.
+    unsigned xb, yb, zb;
+    asm("v_cvt_u32_f32_sdwa %0, %1 dst_sel:BYTE_1 dst_unused:UNUSED_PAD src0_sel:DWORD"
+        : "=v"(xb)
+        : "v"(__builtin_amdgcn_fmed3f(tx, 0.0f, gm)));
+    asm("v_cvt_u32_f32_sdwa %0, %1 dst_sel:BYTE_2 dst_unused:UNUSED_PAD src0_sel:DWORD"
+        : "=v"(yb)
+        : "v"(my));
+    asm("v_cvt_u32_f32_sdwa %0, %1 dst_sel:BYTE_3 dst_unused:UNUSED_PAD src0_sel:DWORD"
+        : "=v"(zb)
+        : "v"(__builtin_amdgcn_fmed3f(tz, 0.0f, gm)));
+    c.r8 = xb | yb | zb;
     return c;
 }
 

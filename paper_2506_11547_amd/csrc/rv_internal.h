@@ -108,8 +108,10 @@ hipError_t launch_key_vote(const float* x, const float* y, int64_t n, int G, int
                            const float2* table, const BinArgs& a, hipStream_t s);
 hipError_t launch_bin_vote(const float* x, const float* y, int64_t n, int G, int J, int edge_log2,
                            const float2* table, const BinArgs& a, hipStream_t s);
-hipError_t launch_brick_accum(int G, int K, int edge_log2, int32_t* grid, uint64_t* partial,
-                              const BinArgs& a, hipStream_t s);
+// spread: the queues hold narrow runs (G <= 256, the binned vote's), else
+// wide runs or keys; edge 16 is narrow only.
+hipError_t launch_brick_accum(int G, int K, int edge_log2, bool spread, int32_t* grid,
+                              uint64_t* partial, const BinArgs& a, hipStream_t s);
 
 // Batches (G <= kMaxBatchGrid): planned on the device from the instances'
 // offsets, then the binned vote over work units and the accumulation over

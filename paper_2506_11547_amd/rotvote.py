@@ -864,9 +864,10 @@ class Probe:
         L.rvp_ceil_lds_atomic.argtypes = [i32, i32, i32, d]
         L.rvp_ceil_global_atomic.argtypes = [i64, i32, i32, i32, d]
         L.rvp_ceil_copy.argtypes = [i64, d]
+        L.rvp_ceil_read.argtypes = [i64, d]
         for f in (L.rvp_recip, L.rvp_div_sqrt, L.rvp_basis, L.rvp_cells, L.rvp_decode,
                   L.rvp_residual, L.rvp_table, L.rvp_ceil_valu, L.rvp_ceil_lds_atomic,
-                  L.rvp_ceil_global_atomic, L.rvp_ceil_copy):
+                  L.rvp_ceil_global_atomic, L.rvp_ceil_copy, L.rvp_ceil_read):
             f.restype = i32
 
     @staticmethod
@@ -935,6 +936,10 @@ class Probe:
     def ceiling_copy(self, nbytes: int = 1 << 30) -> float:
         """Bytes read plus written per second by a device copy."""
         return self._rate(self.lib.rvp_ceil_copy, nbytes)
+
+    def ceiling_read(self, nbytes: int = 1 << 30) -> float:
+        """Bytes read per second by a streaming read."""
+        return self._rate(self.lib.rvp_ceil_read, nbytes)
 
     def residual(self, x: torch.Tensor, y: torch.Tensor, q: torch.Tensor) -> torch.Tensor:
         torch.cuda.synchronize()
