@@ -142,10 +142,10 @@ def alu_roofline(kernel: str, achieved_gops: float, traffic, **extra) -> dict:
             **extra}
 
 
-TRAFFIC_RECORDS = {"large": ROOT / "profiles" / "vote_bin__large_traffic.json",
-                   "batch": ROOT / "profiles" / "vote_bin__batch_traffic.json",
-                   "paper_default": ROOT / "profiles" / "vote_bin__paper_default_traffic.json",
-                   "rigid": ROOT / "profiles" / "vote_bin__rigid_traffic.json"}
+# committed HBM-byte records of a workload's vote kernel, one per profiled
+# strategy (profiles/vote_bin__*, vote_keys__*)
+TRAFFIC_RECORDS = {w: [ROOT / "profiles" / f"vote_{k}__{w}_traffic.json" for k in ("bin", "keys")]
+                   for w in ("large", "batch", "paper_default", "rigid")}
 
 
 KEY_VOTE_KERNEL = "rv::k_vote_keys<rv::KeyPack<16, 16, 1> >"
@@ -169,11 +169,15 @@ def measured_traffic(workload: str, kernel: str):
     profile is of another workload or kernel instance, or the kernel's sources
     changed since."""
     import hashlib
-    try:
-        rec = json.loads(TRAFFIC_RECORDS[workload].read_text())
-    except (KeyError, OSError, ValueError):
-        return None
-    if rec.get("workload") != workload or rec.get("kernel") != kernel:
+    rec = None
+    for path in TRAFFIC_RECORDS.get(workload, []):
+        try:
+            r = json.loads(path.read_text())
+        except (OSError, ValueError):
+            continue
+        if r.get("workload") == workload and r.get("kernel") == kernel:
+            rec = r
+    if rec is None:
         return None
     for path, digest in rec["sources_sha256"].items():
         try:
@@ -493,6 +497,7 @@ def run_rigid(args):
     pm = torch.empty(m.shape[1], dtype=torch.uint8, device=dev)
     q, c, _ = solver.solve(m, nn, G, eps_deg, mask=pm)
     vote_ms = solver.timings()["vote"]
+    strategy = solver.plan()["strategy"]
     ev[2].record(stream)
     q, c, ran = solver.refine(m, nn, q, pm, eps_deg, max_rounds=rounds)
     ev[3].record(stream)
@@ -513,12 +518,12 @@ def run_rigid(args):
                       "seed": seed, "mu": mu, "grid": G, "samples_per_circle": J, "topk": K,
                       "eps_deg": eps_deg, "refine_rounds": rounds,
                       "t_domain": [t_min, t_min + t_cells * t_step], "t_step": t_step,
-                      "t_inlier": tau},
+                      "t_inlier": tau, "vote_strategy": strategy},
            "solves_per_s": 1.0 / dt,
            "pair_tests_per_s": n * (n - 1) / 2 / (stage_ms["pairs"] * 1e-3),
            "stage_ms": stage_ms, "vote_ms": vote_ms,
            "roofline": alu_roofline("vote (pairs)", achieved,
-                                    measured_traffic("rigid", vote_kernel_name(G)),
+                                    measured_traffic("rigid", vote_kernel_name(G, strategy=strategy)),
                                     ops_per_sample=OPS_PER_SAMPLE, samples_per_launch=P * J,
                                     vote_ms=vote_ms),
            "result": {"pairs": P, "rot_inliers": r["rot_inliers"],

@@ -98,14 +98,21 @@ __device__ __forceinline__ uint32_t local_of(uint32_t pc)
 // brick-local coordinates in place (the low kLog bits of bytes 1-3) with the
 // length: a mask, where the accumulation, which has ALU to spare, takes them
 // apart.
-template <int kLog>
-__device__ __forceinline__ uint32_t run_brick(uint32_t e, int nba)
+// The brick of a narrow staged run: its brick coordinates, one per byte 1-3,
+// weighted 1, nba and nba^2 by a byte dot product.  `weights` holds those
+// bytes (brick_weights); nba^2 fits a byte since a narrow solve has at most
+// 512 bricks.
+__host__ __device__ constexpr uint32_t brick_weights(int nba)
 {
-    const uint32_t bx = __builtin_amdgcn_ubfe(e, 8 + kLog, 8 - kLog);
-    const uint32_t by = __builtin_amdgcn_ubfe(e, 16 + kLog, 8 - kLog);
-    const uint32_t bz = e >> (24 + kLog);
-    return __umul24(__umul24(bz, (uint32_t)nba) + by, (uint32_t)nba) + bx;
+    return (1u << 8) | ((uint32_t)nba << 16) | ((uint32_t)(nba * nba) << 24);
 }
+template <int kLog>
+__device__ __forceinline__ uint32_t run_brick(uint32_t e, uint32_t weights)
+{
+    constexpr uint32_t kHigh = ((0xFFu >> kLog) << 8) | ((0xFFu >> kLog) << 16) | ((0xFFu >> kLog) << 24);
+    return __builtin_amdgcn_udot4((e >> kLog) & kHigh, weights, 0u, false);
+}
+static_assert(kMaxBricks <= 512, "nba^2 <= 64 for narrow solves");
 template <int kLog>
 constexpr uint32_t kSpreadMask = (Brick<kLog>::kMask << 8) | (Brick<kLog>::kMask << 16) |
                                  (Brick<kLog>::kMask << 24) | 0xFFu;
@@ -270,6 +277,7 @@ __device__ __forceinline__ void bin_flush(uint32_t (*stage)[Pack<false>::kStageC
                                           int nba, int G, int xs, int qoff, int64_t ovf_off,
                                           const BinArgs& a)
 {
+    const uint32_t weights = brick_weights(nba);
     // 1: runs per brick (zero-length entries are marked dropped)
     for (uint32_t k = lane; k < my; k += kWave) {
         const uint32_t e = stage[wave][k];
@@ -277,7 +285,7 @@ __device__ __forceinline__ void bin_flush(uint32_t (*stage)[Pack<false>::kStageC
             stage[wave][k] = kDropped;
             continue;
         }
-        atomicAdd(&s_cnt[run_brick<kLog>(e, nba)], 1u);
+        atomicAdd(&s_cnt[run_brick<kLog>(e, weights)], 1u);
     }
     __syncthreads();
     // 2: one reservation per brick in its queue; the first pool slot of this
@@ -300,7 +308,7 @@ __device__ __forceinline__ void bin_flush(uint32_t (*stage)[Pack<false>::kStageC
         const uint32_t e = stage[wave][k];
         if (e == kDropped)
             continue;
-        const uint32_t b = run_brick<kLog>(e, nba);
+        const uint32_t b = run_brick<kLog>(e, weights);
         const uint32_t rank = atomicSub(&s_cnt[b], 1u) - 1u;
         const uint2 d = s_dst[b];
         if (rank < d.y) {

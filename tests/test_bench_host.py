@@ -56,18 +56,28 @@ def test_traffic_record_follows_the_sources(tmp_path, monkeypatch):
     good = {src: hashlib.sha256((ROOT / src).read_bytes()).hexdigest()}
     kernel = "rv::k_vote_bin<5, false>"
     monkeypatch.setitem(bench.TRAFFIC_RECORDS, "large",
-                        make_record(tmp_path, "large", kernel, good))
+                        [make_record(tmp_path, "large", kernel, good)])
     assert bench.measured_traffic("large", kernel) == 4096.0
     # another kernel instance or workload than the record's: no figure
     assert bench.measured_traffic("large", "rv::k_vote_bin<5, true>") is None
     assert bench.measured_traffic("medium", kernel) is None
+    # the record of the kernel the solve ran, among the workload's records
+    keys = tmp_path / "keys"
+    keys.mkdir()
+    monkeypatch.setitem(bench.TRAFFIC_RECORDS, "large",
+                        [tmp_path / "missing.json", make_record(keys, "large", bench.KEY_VOTE_KERNEL, good),
+                         make_record(tmp_path, "large", kernel, good)])
+    assert bench.measured_traffic("large", kernel) == 4096.0
+    assert bench.measured_traffic("large", bench.KEY_VOTE_KERNEL) == 4096.0
     # a source changed since the profile: no figure
     monkeypatch.setitem(bench.TRAFFIC_RECORDS, "large",
-                        make_record(tmp_path, "large", kernel, {src: "0" * 64}))
+                        [make_record(tmp_path, "large", kernel, {src: "0" * 64})])
     assert bench.measured_traffic("large", kernel) is None
     # an unreadable record: no figure
-    monkeypatch.setitem(bench.TRAFFIC_RECORDS, "large", tmp_path / "missing.json")
+    monkeypatch.setitem(bench.TRAFFIC_RECORDS, "large", [tmp_path / "missing.json"])
     assert bench.measured_traffic("large", kernel) is None
+    # the committed records are the workloads' bin and key profiles
+    assert bench.TRAFFIC_RECORDS["paper_default"][1].name == "vote_keys__paper_default_traffic.json"
 
 
 def test_roofline_constants():
