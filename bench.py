@@ -8,7 +8,10 @@ deg, K = 64.  Inputs are resident in HBM before the timed region starts.
 Prints one JSON line.  ``value`` is circle-sample votes per second of the whole
 solve (N * J / seconds per solve); solves/s, the per-stage device times (HIP
 events recorded on the solve stream inside the timed region), the roofline of
-the dominant kernel and the CPU oracle's rate on a bounded sample ride along.
+the dominant kernel and the CPU oracle's rate ride along, and so does the
+metric's served half: after the timed solves, ``--serve-duration`` seconds (20
+by default, 0 skips it) of the serve workload below, whose p99 latency is
+``served_p99_ms``.
 
 ``--workload serve`` drives the request server with Poisson arrivals (2000
 requests/s; N log-uniform on [1e3, 1e6]; G = 64 / 128 / 256 for N below 1e4 /
@@ -71,6 +74,9 @@ def parse():
                     help="batch workload: instances the CPU oracle times")
     ap.add_argument("--duration", type=float, default=60.0,
                     help="serve workload: seconds of arrivals")
+    ap.add_argument("--serve-duration", type=float, default=20.0,
+                    help="large workload: seconds of the served leg after the timed solves "
+                         "(0 skips it)")
     ap.add_argument("--rate", type=float, default=2000.0, help="serve workload: requests/s")
     ap.add_argument("--workers", type=int, default=8, help="serve workload: server lanes")
     ap.add_argument("--hbm-budget-gib", type=float, default=8.0,
@@ -313,9 +319,10 @@ def serve_pool(per_tier: int, seed: int):
     return pool
 
 
-def run_serve(args):
-    import threading
-
+def serve_measure(rate: float, duration: float, workers: int, hbm_budget_gib: float) -> dict:
+    """Poisson arrivals of the seeded request pool at `rate` requests/s for
+    `duration` s into a Server; the serving statistics, the run's
+    configuration and the throughput figures."""
     import numpy as np
     import torch
 
@@ -331,12 +338,12 @@ def run_serve(args):
         masks = [torch.empty(inst.n, dtype=torch.uint8, device=dev) for _ in range(4)]
         res.append((G, inst.n, x, y, masks))
     rng = np.random.default_rng(seed + 1)
-    n_req = int(rng.poisson(args.rate * args.duration))
-    arrivals = np.sort(rng.uniform(0.0, args.duration, n_req))
+    n_req = int(rng.poisson(rate * duration))
+    arrivals = np.sort(rng.uniform(0.0, duration, n_req))
     picks = rng.integers(0, len(res), n_req)
-    srv = rotvote.Server(workers=args.workers, max_n=1_000_000, max_grid=256, topk=16,
+    srv = rotvote.Server(workers=workers, max_n=1_000_000, max_grid=256, topk=16,
                          max_batch=64, batch_max_n=65536, max_queue=1 << 22,
-                         hbm_budget=int(args.hbm_budget_gib * (1 << 30)))
+                         hbm_budget=int(hbm_budget_gib * (1 << 30)))
     # warm-up: one request of every pool entry
     for k, (G, n, x, y, masks) in enumerate(res):
         srv.wait(srv.submit(x, y, G, eps_deg, masks[0]))
@@ -372,29 +379,18 @@ def run_serve(args):
     end = max(r["t_end"] for r in replies)
     span = end - t0
     samples = np.array([res[int(k)][1] * 8 * res[int(k)][0] for k in picks], np.float64)
-    offered = samples.sum() / args.duration
+    offered = samples.sum() / duration
     achieved = samples.sum() / span
     tier = np.array([res[int(k)][0] for k in picks])
-    out = {
-        "metric": METRIC,
-        "value": achieved,
-        "unit": "votes/s",
-        "n_gpus": 1,
-        "steps": n_req,
-        "warmup": len(res),
-        "ms_per_step": span / n_req * 1e3,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": "serve", "rate_rps": args.rate, "duration_s": args.duration,
+    return {
+        "requests": n_req, "warmup": len(res), "span_s": span, "achieved_votes_per_s": achieved,
+        "config": {"workload": "serve", "rate_rps": rate, "duration_s": duration,
                    "n_range": [1_000, 1_000_000], "grids": [64, 128, 256], "outlier_ratio": [0.8, 0.99],
                    "sigma_deg": 1.0, "eps_deg": eps_deg, "topk": 16, "seed": seed,
                    "pool_per_tier": 24, "workers": st["workers"], "max_batch": 64,
                    "hbm_budget_bytes": mem["arena_bytes"]},
         "serving": {
-            "requests": n_req, "offered_rps": n_req / args.duration, "achieved_rps": n_req / span,
+            "requests": n_req, "offered_rps": n_req / duration, "achieved_rps": n_req / span,
             "offered_votes_per_s": offered, "achieved_votes_per_s": achieved,
             "saturated": bool(achieved < 0.97 * offered),
             "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3),
@@ -414,6 +410,26 @@ def run_serve(args):
                 for g in (64, 128, 256)
                 if any(t == g and r["batched"] == 1 for r, t in zip(replies, tier))},
         },
+    }
+
+
+def run_serve(args):
+    m = serve_measure(args.rate, args.duration, args.workers, args.hbm_budget_gib)
+    out = {
+        "metric": METRIC,
+        "value": m["achieved_votes_per_s"],
+        "unit": "votes/s",
+        "n_gpus": 1,
+        "steps": m["requests"],
+        "warmup": m["warmup"],
+        "ms_per_step": m["span_s"] / m["requests"] * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": m["config"],
+        "serving": m["serving"],
     }
     print(json.dumps(out), flush=True)
 
@@ -847,6 +863,12 @@ def main():
         "refine": refine,
         "async": pipelined,
     }
+    if args.serve_duration > 0 and w.name == "large":
+        # the metric's served half: the request server under Poisson arrivals
+        # (the same leg as --workload serve, shorter), after the timed solves
+        m = serve_measure(args.rate, args.serve_duration, args.workers, args.hbm_budget_gib)
+        out["served_p99_ms"] = m["serving"]["latency_ms"]["p99"]
+        out["serving"] = dict(m["serving"], config=m["config"])
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, inst, args.cpu_runs, args.cpu_single_fraction,
                                            args.cpu_single_runs)

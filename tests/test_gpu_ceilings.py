@@ -45,10 +45,17 @@ def test_copy_ceiling_below_hbm_peak(probe):
     assert 0.5e12 < r < 1.05 * HBM_PEAK, r
 
 
+def test_read_ceiling_below_hbm_peak(probe):
+    r = probe.ceiling_read(1 << 30)
+    assert 0.5e12 < r < 1.05 * HBM_PEAK, r
+
+
 def test_invalid_arguments_refused(probe):
     with pytest.raises(RuntimeError):
         probe.ceiling_global_atomic(3000)          # not a power of two
     with pytest.raises(RuntimeError):
         probe.ceiling_copy(100)                    # not a multiple of 16
+    with pytest.raises(RuntimeError):
+        probe.ceiling_read(100)                    # not a multiple of 16
     with pytest.raises(RuntimeError):
         probe.ceiling_valu(blocks=0)
