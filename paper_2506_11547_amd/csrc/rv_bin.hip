@@ -172,17 +172,19 @@ __global__ __launch_bounds__(256) void k_bin_estimate(const float* __restrict__ 
 
 // One block.  cap = 1.15 x the estimated runs of the brick spread over the
 // queue sets, plus slack, in multiples of 64 runs (queues start 256-byte
-// aligned); scaled down if the pool cannot hold them all.  Resets the fill
+// aligned); scaled down if the pool cannot hold them all; the bricks in
+// decreasing order of capacity for the accumulation.  Resets the fill
 // counters, the overflow flags and the estimate for the next solve.
 constexpr int kPlanThreads = kMaxBricksAll / 2;  // two bricks per thread
+constexpr int kPlanBuckets = 2 * kWave;          // capacity buckets of the accumulation order
 
 __global__ __launch_bounds__(kPlanThreads) void k_bin_plan(BinArgs a, int nb)
 {
     __shared__ uint64_t s_scan[kPlanThreads / kWave];
     __shared__ uint64_t s_total;
-    __shared__ uint64_t s_sort[kMaxBricksAll];
+    __shared__ uint32_t s_hist[kPlanBuckets];
     const int t = threadIdx.x;
-    const int b0 = 2 * t, b1 = 2 * t + 1;
+    const int b0 = 2 * t;  // this thread's bricks: b0 and b0 + 1
     uint64_t cap[2] = {0, 0};
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
@@ -225,36 +227,51 @@ __global__ __launch_bounds__(kPlanThreads) void k_bin_plan(BinArgs a, int nb)
         __syncthreads();
         scan(excl0, excl1);
     }
-    // accumulation order: heaviest bricks first (bitonic sort of cap << 16 | b,
-    // descending, two elements per thread, over the next power of two >= nb;
-    // the padding is 0 and sorts last)
-    s_sort[b0] = b0 < nb ? ((cap[0] << 16) | (uint64_t)b0) : 0ull;
-    s_sort[b1] = b1 < nb ? ((cap[1] << 16) | (uint64_t)b1) : 0ull;
+    // accumulation order: heaviest bricks first, by a counting sort into
+    // capacity buckets a quarter octave wide (largest first); within a bucket
+    // the order is whichever the LDS atomics give.  The order only schedules
+    // the accumulation (one workgroup per brick, handed out in order): any
+    // order gives the same histogram.
+    constexpr int kBuckets = kPlanBuckets;
+    if (t < kBuckets)
+        s_hist[t] = 0u;
     __syncthreads();
-    int np = 2;
-    while (np < nb)
-        np <<= 1;
-    for (int k = 2; k <= np; k <<= 1) {
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            if (2 * t < np) {
-                const int i = 2 * t - (t & (j - 1));  // the lower index of this thread's pair
-                const uint64_t p = s_sort[i], q = s_sort[i + j];
-                const bool desc = (i & k) == 0;
-                if (desc ? (p < q) : (p > q)) {
-                    s_sort[i] = q;
-                    s_sort[i + j] = p;
-                }
-            }
-            __syncthreads();
+    int bk[2] = {0, 0};
+    uint32_t pos[2] = {0u, 0u};
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        if (b0 + h >= nb)
+            continue;
+        const uint64_t c = cap[h];
+        int key = 0;  // 4 floor(log2 c) + the next two bits; c < 2^32
+        if (c != 0) {
+            const int l = 63 - __clzll((long long)c);
+            key = 4 * l + (l >= 2 ? (int)((c >> (l - 2)) & 3u) : 0);
         }
+        bk[h] = kBuckets - 1 - min(key, kBuckets - 1);
+        pos[h] = atomicAdd(&s_hist[bk[h]], 1u);
     }
+    __syncthreads();
+    if (t < kWave) {
+        // exclusive scan of the bucket counts, two buckets per lane, in place
+        const uint32_t v0 = s_hist[2 * t], v1 = s_hist[2 * t + 1];
+        uint32_t incl = v0 + v1;
+#pragma unroll
+        for (int off = 1; off < kWave; off <<= 1) {
+            const uint32_t w = __shfl_up(incl, off);
+            incl += t >= off ? w : 0u;
+        }
+        s_hist[2 * t] = incl - v0 - v1;
+        s_hist[2 * t + 1] = incl - v1;
+    }
+    __syncthreads();
     const uint64_t excl[2] = {excl0, excl1};
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         const int b = b0 + h;
         if (b >= nb)
             continue;
-        a.order[b] = (uint32_t)(s_sort[b] & 0xFFFFu);
+        a.order[s_hist[bk[h]] + pos[h]] = (uint32_t)b;
         a.cap[b] = (uint32_t)cap[h];
         for (int xs = 0; xs < kSets; ++xs) {
             a.qbase[xs * a.qstride + b] = (uint32_t)(xs * s_total + excl[h]);

@@ -72,7 +72,8 @@ struct Unit {
 // sets (one per XCD) and qstride = kMaxBricksAll; a batch uses one set and
 // qstride = B * nb.
 struct BinArgs {
-    uint32_t* pool;      // run queues; entry = local cell | run length << 15
+    uint32_t* pool;      // run queues; entry = narrow run: brick-local bits of bytes 1-3 and the
+                         // length in byte 0; wide run or key: local cell | length << 15
     uint32_t* fill;      // [nsets][qstride] runs appended per queue
     uint32_t* qbase;     // [nsets][qstride] first pool slot of each queue
     uint32_t* cap;       // [qstride] capacity of each queue of the brick
