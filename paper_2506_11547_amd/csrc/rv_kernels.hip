@@ -120,11 +120,14 @@ hipError_t launch_vote_global(const float* x, const float* y, int64_t n, int G, 
 
 // -------------------------------------------------------------------- top-K
 //
-// Per-block sorted top-64 lists over disjoint parts of the grid, then one
-// block merges the lists, decodes the K best cells and clears their counters.
+// Per-block sorted top-64 lists over disjoint parts of the grid (or the brick
+// accumulation's per-brick lists), then one block merges the lists that can
+// hold a key of the top K (their maximum reaches the K-th largest maximum),
+// decodes the K best cells and clears their counters.
 
 constexpr int kTopkThreads = 1024;
 constexpr int kTopkWaves = kTopkThreads / kWave;
+constexpr int kTopkFloorLists = 256;  // more lists than this: the final merge prunes them
 
 __global__ __launch_bounds__(kTopkThreads) void k_topk_partial(const int32_t* __restrict__ hist,
                                                                int64_t ncell,
@@ -185,16 +188,60 @@ __global__ __launch_bounds__(kTopkThreads) void k_topk_final(const uint64_t* __r
                                                              Candidates c)
 {
     __shared__ uint64_t lists[kTopkWaves][kWave];
+    __shared__ uint64_t s_floor;
+    __shared__ uint16_t s_keep[kTopkMaxBlocks];
+    __shared__ uint32_t s_nkeep;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    uint64_t list = 0;
+    // Many lists: first a floor, the K-th largest of the lists' maxima (each
+    // list's lane 0).  K distinct cells reach it, so every key of the top K
+    // does, and a list whose maximum is below it holds none of them: only the
+    // lists that reach it are merged, without their entries below it.  (Few
+    // lists are merged whole: the floor would cost more than it saves.)
+    const bool pruned = nblocks > kTopkFloorLists;
+    uint64_t floor_k = 0;
+    int nkeep = nblocks;
+    if (pruned) {
+        if (threadIdx.x == 0)
+            s_nkeep = 0u;
+        uint64_t m = 0;
+        for (int base = wave * kWave; base < nblocks; base += kTopkThreads) {
+            const int b = base + lane;
+            const uint64_t v = b < nblocks ? partial[(int64_t)b * kWave] : 0ull;
+            m = wave_insert_sorted(m, wave_sort_desc(v, lane), lane);
+        }
+        m = block_merge<kTopkWaves>(m, lists, wave, lane);
+        if (wave == 0 && lane == 0)
+            s_floor = lane_u64(m, K - 1);
+        __syncthreads();
+        floor_k = s_floor;
+        for (int base = wave * kWave; base < nblocks; base += kTopkThreads) {
+            const int b = base + lane;
+            const uint64_t v = b < nblocks ? partial[(int64_t)b * kWave] : 0ull;
+            const bool reach = v != 0ull && v >= floor_k;
+            const uint64_t mk = __ballot(reach);
+            uint32_t first = 0u;
+            if (lane == 0 && mk)
+                first = atomicAdd(&s_nkeep, (uint32_t)__popcll(mk));
+            first = __shfl(first, 0);
+            const uint32_t r = __builtin_amdgcn_mbcnt_hi((uint32_t)(mk >> 32),
+                                                         __builtin_amdgcn_mbcnt_lo((uint32_t)mk, 0u));
+            if (reach)
+                s_keep[first + r] = (uint16_t)b;
+        }
+        __syncthreads();
+        nkeep = (int)s_nkeep;
+    }
     // eight lists in flight per wave, so the merge does not wait on each load
-    for (int b0 = wave; b0 < nblocks; b0 += kTopkWaves * 8) {
+    uint64_t list = 0;
+    for (int i0 = wave; i0 < nkeep; i0 += kTopkWaves * 8) {
         uint64_t pre[8];
 #pragma unroll
         for (int r = 0; r < 8; ++r) {
-            const int b = b0 + r * kTopkWaves;
-            pre[r] = b < nblocks ? partial[(int64_t)b * kWave + lane] : 0ull;
+            const int i = i0 + r * kTopkWaves;
+            const int b = i < nkeep ? (pruned ? (int)s_keep[i] : i) : 0;
+            const uint64_t e = i < nkeep ? partial[(int64_t)b * kWave + lane] : 0ull;
+            pre[r] = e >= floor_k ? e : 0ull;
         }
 #pragma unroll
         for (int r = 0; r < 8; ++r)
@@ -221,6 +268,8 @@ __global__ __launch_bounds__(kTopkThreads) void k_topk_final(const uint64_t* __r
 hipError_t launch_topk_final(const uint64_t* partial, int nblocks, int K, int G,
                              const Candidates& c, hipStream_t s)
 {
+    if (nblocks < 0 || nblocks > kTopkMaxBlocks)
+        return hipErrorInvalidValue;  // the kernel indexes at most kTopkMaxBlocks lists
     hipLaunchKernelGGL(k_topk_final, dim3(1), dim3(kTopkThreads), 0, s, partial, nblocks, K, G, c);
     return hipGetLastError();
 }
