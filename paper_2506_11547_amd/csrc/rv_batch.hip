@@ -285,13 +285,18 @@ __global__ __launch_bounds__(kUnitThreads) void k_rescore_batch(const float* __r
                                                                 Candidates c)
 {
     __shared__ uint32_t part[kUnitWaves][64];
+    __shared__ float4 s_q[kMaxTopK];
     if (nunits && (int)blockIdx.x >= *nunits)
         return;
     const Unit un = units[blockIdx.x];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int ncand = __builtin_amdgcn_readfirstlane(c.result[un.inst].n_cand);
-    const float4* cq = c.q + (int64_t)un.inst * kMaxTopK;
+    // the instance's candidates, read once per block (not a scalar load
+    // waited on in every iteration)
+    if ((int)threadIdx.x < ncand)
+        s_q[threadIdx.x] = c.q[(int64_t)un.inst * kMaxTopK + threadIdx.x];
+    __syncthreads();
     const int64_t i = un.first + threadIdx.x;
     float a[3] = {1.0f, 0.0f, 0.0f};
     float b[3] = {1.0f, 0.0f, 0.0f};
@@ -308,12 +313,14 @@ __global__ __launch_bounds__(kUnitThreads) void k_rescore_batch(const float* __r
         P[m] = a[m] + b[m];
     }
     uint32_t acc = 0;
+    const uint64_t okm = __builtin_amdgcn_ballot_w64(ok);
     for (int k = 0; k < ncand; ++k) {
-        const float4 q4 = cq[k];
+        const float4 q4 = s_q[k];
         const Quat q{q4.x, q4.y, q4.z, q4.w};
-        const bool in = ok && (residual2(D, P, q) <= T2);
-        // the ballot runs on every lane (inside the select it would see lane k only)
-        const uint32_t cnt = (uint32_t)__popcll(__ballot(in));
+        // unusable lanes hold finite placeholders: tested too, then dropped by
+        // the mask (no branch per candidate); the ballot runs on every lane
+        const uint32_t cnt =
+            (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(residual2(D, P, q) <= T2) & okm);
         acc += (lane == k) ? cnt : 0u;
     }
     part[wave][lane] = acc;

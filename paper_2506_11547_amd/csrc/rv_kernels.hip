@@ -282,39 +282,62 @@ hipError_t launch_topk_final(const uint64_t* partial, int nblocks, int K, int G,
 // k's count, a block reduction in LDS, one atomic per candidate per block.
 
 constexpr int kRescoreThreads = 256;
+// groups of 64 correspondences a wave holds at once: 4, or 1 below this many
+// correspondences (fewer waves would then share the work)
+constexpr int64_t kRescoreTileMinN = 65536;
 
+template <int kRescoreTile>
 __global__ __launch_bounds__(kRescoreThreads) void k_rescore(const float* __restrict__ x,
                                                              const float* __restrict__ y,
                                                              int64_t n, float T2, Candidates c)
 {
     __shared__ uint32_t partial[kRescoreThreads / kWave][kWave];
+    __shared__ float4 s_q[kWave];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int ncand = __builtin_amdgcn_readfirstlane(c.result->n_cand);
+    // the candidates' rotations, read once per block (a scalar load per
+    // candidate waited on its latency in every iteration)
+    if (threadIdx.x < ncand)
+        s_q[threadIdx.x] = c.q[threadIdx.x];
+    __syncthreads();
     uint32_t acc = 0;
-    const int64_t stride = (int64_t)gridDim.x * kRescoreThreads;
-    for (int64_t base = (int64_t)blockIdx.x * kRescoreThreads + wave * kWave; base < n;
-         base += stride) {
-        const int64_t i = base + lane;
-        float a[3] = {1.0f, 0.0f, 0.0f};
-        float b[3] = {1.0f, 0.0f, 0.0f};
-        bool ok = false;
-        if (i < n) {
-            const bool oka = load_unit(x, n, i, a);
-            const bool okb = load_unit(y, n, i, b);
-            ok = oka && okb;
-        }
-        float D[3], P[3];
+    // each wave holds kRescoreTile groups of 64 correspondences in registers
+    // and tests every candidate against all of them: the count of candidate
+    // k goes to lane k of acc once per tile, not once per group
+    const int64_t stride = (int64_t)gridDim.x * kRescoreThreads * kRescoreTile;
+    for (int64_t base = ((int64_t)blockIdx.x * (kRescoreThreads / kWave) + wave) * kWave * kRescoreTile;
+         base < n; base += stride) {
+        float D[kRescoreTile][3], P[kRescoreTile][3];
+        uint64_t okm[kRescoreTile];
 #pragma unroll
-        for (int m = 0; m < 3; ++m) {
-            D[m] = a[m] - b[m];
-            P[m] = a[m] + b[m];
+        for (int r = 0; r < kRescoreTile; ++r) {
+            const int64_t i = base + r * kWave + lane;
+            float a[3] = {1.0f, 0.0f, 0.0f};
+            float b[3] = {1.0f, 0.0f, 0.0f};
+            bool ok = false;
+            if (i < n) {
+                const bool oka = load_unit(x, n, i, a);
+                const bool okb = load_unit(y, n, i, b);
+                ok = oka && okb;
+            }
+            okm[r] = __builtin_amdgcn_ballot_w64(ok);
+#pragma unroll
+            for (int m = 0; m < 3; ++m) {
+                D[r][m] = a[m] - b[m];
+                P[r][m] = a[m] + b[m];
+            }
         }
         for (int k = 0; k < ncand; ++k) {
-            const float4 q4 = c.q[k];
+            const float4 q4 = s_q[k];
             const Quat q{q4.x, q4.y, q4.z, q4.w};
-            const bool in = ok && (residual2(D, P, q) <= T2);
-            const uint32_t cnt = (uint32_t)__popcll(__ballot(in));
+            // unusable lanes hold finite placeholders: tested too, then
+            // dropped by their group's mask (no branch per candidate)
+            uint32_t cnt = 0;
+#pragma unroll
+            for (int r = 0; r < kRescoreTile; ++r)
+                cnt += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(residual2(D[r], P[r], q) <= T2) &
+                                          okm[r]);
             acc += (lane == k) ? cnt : 0u;
         }
     }
@@ -335,8 +358,13 @@ hipError_t launch_rescore(const float* x, const float* y, int64_t n, float T2, c
 {
     if (n <= 0)
         return hipSuccess;
-    const int blocks = (int)std::min<int64_t>((n + kRescoreThreads - 1) / kRescoreThreads, 2048);
-    hipLaunchKernelGGL(k_rescore, dim3(blocks), dim3(kRescoreThreads), 0, s, x, y, n, T2, c);
+    const int tile = n >= kRescoreTileMinN ? 4 : 1;
+    const int64_t per_block = (int64_t)kRescoreThreads * tile;
+    const int blocks = (int)std::min<int64_t>((n + per_block - 1) / per_block, 2048);
+    if (tile == 4)
+        hipLaunchKernelGGL(k_rescore<4>, dim3(blocks), dim3(kRescoreThreads), 0, s, x, y, n, T2, c);
+    else
+        hipLaunchKernelGGL(k_rescore<1>, dim3(blocks), dim3(kRescoreThreads), 0, s, x, y, n, T2, c);
     return hipGetLastError();
 }
 
