@@ -793,11 +793,10 @@ RV_API rv_status rot_vote_solve(rv_handle* h, const float* x, const float* y, in
     RV_HIP(h, rv::launch_rescore(x, y, n, T2, c, s), "rescore");
     if (tm)
         RV_HIP(h, hipEventRecord(h->ev[5], s), "event");
-    RV_HIP(h, rv::launch_mask(x, y, n, T2, c, inlier_mask, s), "mask");
+    // the mask kernel also writes the result record into the pinned host copy
+    RV_HIP(h, rv::launch_mask(x, y, n, T2, c, inlier_mask, s, h->h_result), "mask");
     if (tm)
         RV_HIP(h, hipEventRecord(h->ev[6], s), "event");
-    RV_HIP(h, hipMemcpyAsync(h->h_result, h->d_result, sizeof(rv::Result), hipMemcpyDeviceToHost, s),
-           "result readback");
     RV_HIP(h, hipStreamSynchronize(s), "sync");
     h->events_recorded = tm;
     const rv::Result& r = *h->h_result;

@@ -251,8 +251,10 @@ hipError_t launch_translation(const float* x, const float* y, int64_t n, const f
 
 hipError_t launch_rescore(const float* x, const float* y, int64_t n, float T2,
                           const Candidates& c, hipStream_t s);
+// host_result (pinned host memory, or null): where the result record is also
+// written, so a synchronous caller needs no device-to-host copy
 hipError_t launch_mask(const float* x, const float* y, int64_t n, float T2, const Candidates& c,
-                       uint8_t* mask, hipStream_t s);
+                       uint8_t* mask, hipStream_t s, Result* host_result = nullptr);
 
 // Server lanes: handles whose vote grid and run pool are not allocated at
 // create but bound per solve from the server's arena.  The byte counts are

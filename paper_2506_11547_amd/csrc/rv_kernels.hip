@@ -376,7 +376,8 @@ hipError_t launch_rescore(const float* x, const float* y, int64_t n, float T2, c
 
 __global__ __launch_bounds__(256) void k_mask(const float* __restrict__ x,
                                               const float* __restrict__ y, int64_t n, float T2,
-                                              Candidates c, uint8_t* __restrict__ mask)
+                                              Candidates c, uint8_t* __restrict__ mask,
+                                              Result* __restrict__ host_result)
 {
     __shared__ int s_win;
     const int lane = threadIdx.x & 63;
@@ -406,6 +407,19 @@ __global__ __launch_bounds__(256) void k_mask(const float* __restrict__ x,
         r->q[3] = q.z;
         r->count = win >= 0 ? (int64_t)c.inliers[win] : 0;
         r->winner = win;
+        if (host_result) {
+            // the same record straight into the caller's pinned host memory
+            // (visible to the host once the kernel has completed)
+            Result h;
+            h.q[0] = q.w;
+            h.q[1] = q.x;
+            h.q[2] = q.y;
+            h.q[3] = q.z;
+            h.count = r->count;
+            h.winner = win;
+            h.n_cand = r->n_cand;
+            *host_result = h;
+        }
     }
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
@@ -427,10 +441,10 @@ __global__ __launch_bounds__(256) void k_mask(const float* __restrict__ x,
 }
 
 hipError_t launch_mask(const float* x, const float* y, int64_t n, float T2, const Candidates& c,
-                       uint8_t* mask, hipStream_t s)
+                       uint8_t* mask, hipStream_t s, Result* host_result)
 {
     const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 2048));
-    hipLaunchKernelGGL(k_mask, dim3(blocks), dim3(256), 0, s, x, y, n, T2, c, mask);
+    hipLaunchKernelGGL(k_mask, dim3(blocks), dim3(256), 0, s, x, y, n, T2, c, mask, host_result);
     return hipGetLastError();
 }
 
