@@ -19,6 +19,7 @@
 // capacities only change speed, never the histogram.
 #include <algorithm>
 #include <atomic>
+#include <cmath>
 
 #include "rv_device.h"
 #include "rv_internal.h"
@@ -986,6 +987,46 @@ int accum_blocks(int edge_log2, int items)
     return std::max(1, std::min(items, v));
 }
 
+// Compute units of the current device (cached per device).
+int device_cus()
+{
+    static std::atomic<int> cached[kMaxDevices];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices)
+        return 256;
+    int v = cached[dev].load(std::memory_order_relaxed);
+    if (v <= 0) {
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v < 1)
+            return 256;
+        cached[dev].store(v, std::memory_order_relaxed);
+    }
+    return v;
+}
+
+// Samples per vote workgroup.  A launch of ngroups x n workgroups runs
+// `resident` of them at a time; each costs its samples plus about
+// kChunkCost sample-equivalents (circle set-up, its last partial flush), and
+// the last ones to start leave the GPU partly idle for about half a
+// workgroup: n = sqrt(J resident / (2 ngroups kChunkCost)) balances the two.
+// Workgroups start in chunk order, so the first n - 1 chunks are equal and
+// the last about a quarter of their length: the launch's last, partial round
+// is then made of short workgroups.  Chunks are whole multiples of `unit`
+// samples.  (Measured on one solve at N = 1e6, G = 256, J = 2048: one chunk
+// 2.33 ms, five equal 2.14, four of 480 and one of 128 samples 2.09; at
+// N = 1e5, G = 128, J = 1024: five of 240 samples 0.171 ms, eight equal
+// 0.157, ten of 96 and one of 64 0.141.)
+int vote_chunk(int J, int64_t ngroups, int64_t resident, int unit)
+{
+    constexpr double kChunkCost = 16.0;
+    const double best = std::sqrt((double)J * (double)resident / (2.0 * (double)ngroups * kChunkCost));
+    const int64_t units = (J + unit - 1) / unit;
+    const int64_t n = std::min<int64_t>(std::max<int64_t>(1, std::llround(best)), units);
+    if (n <= 1)
+        return (int)(units * unit);
+    const double full = ((double)J - (double)J / (4.0 * (double)n)) / (double)(n - 1);
+    return (int)(std::max<int64_t>(1, (int64_t)(full / (double)unit)) * unit);
+}
+
 }  // namespace
 
 int solve_edge_log2(int G) { return G <= 128 ? 4 : 5; }
@@ -1044,12 +1085,8 @@ hipError_t launch_key_vote(const float* x, const float* y, int64_t n, int G, int
     if (G > kMaxBrickGrid || nba * nba * nba > kMaxBricksAll || a.units || a.nsets != kSets)
         return hipErrorInvalidValue;
     const int64_t ngroups = (n + Keys::kThreads - 1) / Keys::kThreads;
-    // at least ~4 rounds of workgroups over the GPU, by splitting J into whole
-    // flush windows when there are few correspondences
-    const int64_t want = 4 * Keys::kBlocksPerCU * 256;
-    const int64_t nwin = (J + Keys::kWindow - 1) / Keys::kWindow;
-    const int64_t split = std::max<int64_t>(1, std::min<int64_t>(nwin, want / ngroups));
-    const int chunk = (int)(((nwin + split - 1) / split) * Keys::kWindow);
+    // J split into whole flush windows (vote_chunk)
+    const int chunk = vote_chunk(J, ngroups, (int64_t)Keys::kBlocksPerCU * device_cus(), Keys::kWindow);
     const int64_t nchunks = (J + chunk - 1) / chunk;
     const int64_t blocks = ngroups * nchunks;
     if (blocks > INT32_MAX)
@@ -1069,14 +1106,10 @@ hipError_t launch_bin_vote(const float* x, const float* y, int64_t n, int G, int
         return hipErrorInvalidValue;
     const int threads = wide ? Pack<true>::kThreads : Pack<false>::kThreads;
     const int64_t ngroups = (n + threads - 1) / threads;
-    // at least ~4 rounds of workgroups over the GPU (3 resident per CU, 1 wide),
-    // by splitting J into whole run blocks when there are few correspondences
-    const int split_len = wide ? Pack<true>::kSplit : Pack<false>::kSplit;
-    const int64_t want =
-        4 * (wide ? Pack<true>::kBlocksPerCU : Pack<false>::kBlocksPerCU) * 256;
-    const int64_t nblk = (J + split_len - 1) / split_len;
-    const int64_t split = std::max<int64_t>(1, std::min<int64_t>(nblk, want / ngroups));
-    const int chunk = (int)(((nblk + split - 1) / split) * split_len);
+    // J split into whole table rows of 8 samples (vote_chunk); runs are cut
+    // at chunk starts and every kSplit samples after
+    const int chunk = vote_chunk(
+        J, ngroups, (int64_t)(wide ? Pack<true>::kBlocksPerCU : Pack<false>::kBlocksPerCU) * device_cus(), 8);
     const int64_t nchunks = (J + chunk - 1) / chunk;
     const int64_t blocks = ngroups * nchunks;
     if (blocks > INT32_MAX || G > kMaxBrickGrid)
