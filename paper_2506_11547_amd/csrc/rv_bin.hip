@@ -129,7 +129,7 @@ __device__ __forceinline__ uint32_t spread_local(uint32_t e)
 
 // ------------------------------------------------------------- estimate
 
-// Runs per brick of every kEstimateStride-th correspondence.  One wave per
+// Runs per brick of every stride-th correspondence.  One wave per
 // (64 sampled correspondences, chunk of `chunk` samples, a multiple of 8), so
 // the table index stays wave-uniform and the work spreads over the whole GPU.
 
@@ -139,7 +139,7 @@ __global__ __launch_bounds__(256) void k_bin_estimate(const float* __restrict__ 
                                                       float H, float gm, int J,
                                                       const float2* __restrict__ table, int nba,
                                                       int chunk, int ngroups, int nwaves,
-                                                      uint32_t* __restrict__ est)
+                                                      int stride, uint32_t* __restrict__ est)
 {
     __shared__ uint32_t s_est[Pack<kWide>::kMaxBricksHere];
     const int nb = nba * nba * nba;
@@ -150,7 +150,7 @@ __global__ __launch_bounds__(256) void k_bin_estimate(const float* __restrict__ 
     if (wave < nwaves) {
         const int c = wave / ngroups;
         const int g = wave - c * ngroups;
-        const int64_t i = ((int64_t)g * kWave + (threadIdx.x & 63)) * kEstimateStride;
+        const int64_t i = ((int64_t)g * kWave + (threadIdx.x & 63)) * stride;
         Quat u, v;
         const bool ok = load_circle(x, y, n, i, u, v);
         uint32_t cur = 0xFFFFFFFFu;
@@ -179,7 +179,7 @@ __global__ __launch_bounds__(256) void k_bin_estimate(const float* __restrict__ 
 constexpr int kPlanThreads = kMaxBricksAll / 2;  // two bricks per thread
 constexpr int kPlanBuckets = 2 * kWave;          // capacity buckets of the accumulation order
 
-__global__ __launch_bounds__(kPlanThreads) void k_bin_plan(BinArgs a, int nb)
+__global__ __launch_bounds__(kPlanThreads) void k_bin_plan(BinArgs a, int nb, int stride)
 {
     __shared__ uint64_t s_scan[kPlanThreads / kWave];
     __shared__ uint64_t s_total;
@@ -191,7 +191,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_bin_plan(BinArgs a, int nb)
     for (int h = 0; h < 2; ++h) {
         const int b = b0 + h;
         if (b < nb) {
-            const uint64_t e = (uint64_t)a.est[b] * kEstimateStride;
+            const uint64_t e = (uint64_t)a.est[b] * (uint64_t)stride;
             cap[h] = ((e * 115 / 100) / kSets + 256 + 63) & ~63ull;
         }
     }
@@ -1044,8 +1044,9 @@ hipError_t launch_bin_prepare(const float* x, const float* y, int64_t n, int G, 
         return hipErrorInvalidValue;
     const float H = (float)G * 0.5f;
     const float gm = (float)G - 0.5f;
+    const int stride = estimate_stride(n, keys);
     if (n > 0) {
-        const int64_t nsamp = (n + kEstimateStride - 1) / kEstimateStride;
+        const int64_t nsamp = (n + stride - 1) / stride;
         const int64_t ngroups = (nsamp + kWave - 1) / kWave;
         // chunks of whole table rows (8 samples) for about 4096 waves
         const int64_t rows = (J + 7) / 8;
@@ -1059,20 +1060,20 @@ hipError_t launch_bin_prepare(const float* x, const float* y, int64_t n, int G, 
         const dim3 grid((unsigned)((nwaves + 3) / 4));
         if (keys)
             hipLaunchKernelGGL((k_bin_estimate<5, true, true>), grid, dim3(256), 0, s, x, y, n, H,
-                               gm, J, table, nba, chunk, (int)ngroups, (int)nwaves, a.est);
+                               gm, J, table, nba, chunk, (int)ngroups, (int)nwaves, stride, a.est);
         else if (wide)
             hipLaunchKernelGGL((k_bin_estimate<5, true, false>), grid, dim3(256), 0, s, x, y, n, H,
-                               gm, J, table, nba, chunk, (int)ngroups, (int)nwaves, a.est);
+                               gm, J, table, nba, chunk, (int)ngroups, (int)nwaves, stride, a.est);
         else if (edge_log2 == 5)
             hipLaunchKernelGGL((k_bin_estimate<5, false, false>), grid, dim3(256), 0, s, x, y, n, H,
-                               gm, J, table, nba, chunk, (int)ngroups, (int)nwaves, a.est);
+                               gm, J, table, nba, chunk, (int)ngroups, (int)nwaves, stride, a.est);
         else
             hipLaunchKernelGGL((k_bin_estimate<4, false, false>), grid, dim3(256), 0, s, x, y, n, H,
-                               gm, J, table, nba, chunk, (int)ngroups, (int)nwaves, a.est);
+                               gm, J, table, nba, chunk, (int)ngroups, (int)nwaves, stride, a.est);
         if (hipError_t e = hipGetLastError(); e != hipSuccess)
             return e;
     }
-    hipLaunchKernelGGL(k_bin_plan, dim3(1), dim3(kPlanThreads), 0, s, a, nb);
+    hipLaunchKernelGGL(k_bin_plan, dim3(1), dim3(kPlanThreads), 0, s, a, nb, stride);
     return hipGetLastError();
 }
 

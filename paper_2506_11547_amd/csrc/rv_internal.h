@@ -58,7 +58,15 @@ constexpr int kMaxBricks = 512;      // (256 / 32)^3: bricks of a solve with 8-b
 constexpr int kNarrowGrid = 256;     // up to here cells pack 8 bits per axis, beyond 9
 constexpr int kMaxBrickGrid = 384;   // (384 / 32)^3 = 1728 bricks
 constexpr int kMaxBricksAll = 2048;  // brick tables of one solve (queue metadata, plan)
-constexpr int kEstimateStride = 64;  // the estimate samples every 64th correspondence
+// The estimate samples every 64th correspondence, every 128th when runs are
+// voted for 2^19 or more (each brick's estimate then still rests on thousands
+// of sampled runs; keys, one per sample, keep the finer stride: their light
+// bricks' estimates are too noisy at 128).
+constexpr int kEstimateStride = 64;
+inline int estimate_stride(int64_t n, bool keys)
+{
+    return (!keys && n >= ((int64_t)1 << 19)) ? 2 * kEstimateStride : kEstimateStride;
+}
 
 // A batch work unit: up to 512 consecutive correspondences of one instance
 // (for the vote, the instance's index within its brick-size class).
