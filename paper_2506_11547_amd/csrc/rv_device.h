@@ -141,18 +141,19 @@ __device__ __forceinline__ Cell cell_coords(float qw, float qx, float qy, float 
         : "=v"(c.y_b1)
         : "v"(my));
     // The cell one byte per axis in bytes 1-3 (G <= 256; byte 0 free for a
-    // run length), each conversion written into its byte of a zeroed register.
-    unsigned xb, yb, zb;
+    // run length): x converted into byte 1 of a zeroed register, y and z into
+    // bytes 2 and 3 of the same register, its other bytes kept.
+    unsigned r8;
     asm("v_cvt_u32_f32_sdwa %0, %1 dst_sel:BYTE_1 dst_unused:UNUSED_PAD src0_sel:DWORD"
-        : "=v"(xb)
+        : "=v"(r8)
         : "v"(__builtin_amdgcn_fmed3f(tx, 0.0f, gm)));
-    asm("v_cvt_u32_f32_sdwa %0, %1 dst_sel:BYTE_2 dst_unused:UNUSED_PAD src0_sel:DWORD"
-        : "=v"(yb)
+    asm("v_cvt_u32_f32_sdwa %0, %1 dst_sel:BYTE_2 dst_unused:UNUSED_PRESERVE src0_sel:DWORD"
+        : "+v"(r8)
         : "v"(my));
-    asm("v_cvt_u32_f32_sdwa %0, %1 dst_sel:BYTE_3 dst_unused:UNUSED_PAD src0_sel:DWORD"
-        : "=v"(zb)
+    asm("v_cvt_u32_f32_sdwa %0, %1 dst_sel:BYTE_3 dst_unused:UNUSED_PRESERVE src0_sel:DWORD"
+        : "+v"(r8)
         : "v"(__builtin_amdgcn_fmed3f(tz, 0.0f, gm)));
-    c.r8 = xb | yb | zb;
+    c.r8 = r8;
     return c;
 }
 
