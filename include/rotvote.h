@@ -63,8 +63,12 @@ typedef enum rv_vote_strategy {
 } rv_vote_strategy;
 
 enum {
-    RV_FLAG_TIMING = 1u,       /* record per-stage HIP events (rot_vote_get_timings) */
-    RV_FLAG_BATCH_GRIDS = 2u   /* keep every batch instance's vote grid (test hook) */
+    RV_FLAG_TIMING = 1u,          /* record per-stage HIP events (rot_vote_get_timings) */
+    RV_FLAG_BATCH_GRIDS = 2u,     /* keep every batch instance's vote grid (test hook) */
+    RV_FLAG_KEEP_HISTOGRAM = 4u   /* write every solve's whole vote grid to the handle
+                                     (rot_vote_get_histogram).  Without it the brick and
+                                     key strategies keep only each brick's best cells,
+                                     which is all the solve's results need */
 };
 
 enum {
@@ -420,8 +424,9 @@ rv_status rot_vote_get_batch_histogram(rv_handle *h, int32_t b, int32_t *dst_dev
 rv_status rot_vote_get_batch_topk(rv_handle *h, int32_t b, int32_t *n_cand, int32_t *votes,
                                   int32_t *cell_idx, int64_t *inliers, int32_t *winner);
 
-/* Test hook: copies the last solve's vote grid (G^3 int32, x fastest) to the
- * device buffer dst.  RV_EINVAL before the first solve. */
+/* Test hook (RV_FLAG_KEEP_HISTOGRAM): copies the last solve's vote grid (G^3
+ * int32, x fastest) to the device buffer dst.  RV_EINVAL before the first
+ * solve and for a handle created without the flag. */
 rv_status rot_vote_get_histogram(rv_handle *h, int32_t *dst_device);
 
 /* Test hook: the last solve's candidates.  Writes *n_cand (<= K) and, for

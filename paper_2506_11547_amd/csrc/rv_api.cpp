@@ -155,6 +155,7 @@ struct rv_handle {
     hipEvent_t ev[kStages + 1] = {};
     hipEvent_t ev_switch = nullptr;      // orders a stream change (rot_vote_set_stream)
     bool timing = false;
+    bool keep_hist = false;             // RV_FLAG_KEEP_HISTOGRAM: brick solves write the grid
     bool events_recorded = false;
 
     // last solve
@@ -336,7 +337,7 @@ rv_status create_impl(rv_handle** out, const rv_config* cfg, bool lane)
         return fail(nullptr, RV_EINVAL, "rot_vote_create: topk outside 1..64");
     if (cfg->vote_strategy < RV_VOTE_AUTO || cfg->vote_strategy > RV_VOTE_KEYS)
         return fail(nullptr, RV_EINVAL, "rot_vote_create: unknown vote_strategy");
-    if (cfg->flags & ~(uint32_t)(RV_FLAG_TIMING | RV_FLAG_BATCH_GRIDS))
+    if (cfg->flags & ~(uint32_t)(RV_FLAG_TIMING | RV_FLAG_BATCH_GRIDS | RV_FLAG_KEEP_HISTOGRAM))
         return fail(nullptr, RV_EINVAL, "rot_vote_create: unknown flags");
     if (cfg->max_batch < 0)
         return fail(nullptr, RV_EINVAL, "rot_vote_create: max_batch < 0");
@@ -365,6 +366,7 @@ rv_status create_impl(rv_handle** out, const rv_config* cfg, bool lane)
     h->K = cfg->topk;
     h->max_J = cfg->samples_per_circle > 0 ? cfg->samples_per_circle : 8 * cfg->max_grid;
     h->timing = (cfg->flags & RV_FLAG_TIMING) != 0;
+    h->keep_hist = (cfg->flags & RV_FLAG_KEEP_HISTOGRAM) != 0;
 
     auto bail = [&](hipError_t e, const char* what) {
         std::string m = std::string("rot_vote_create: ") + what + ": " + hipGetErrorString(e);
@@ -733,8 +735,11 @@ rv_status vote_candidates(rv_handle* h, const float* x, const float* y, int64_t 
         RV_HIP(h, hipEventRecord(h->ev[2], s), "event");
     int nlists;
     if (brick) {
+        // the whole grid only for the histogram hook: the top-K needs the
+        // bricks' lists alone
         RV_HIP(h, rv::launch_brick_accum(grid, h->K, edge, !keys && grid <= rv::kNarrowGrid,
-                                         h->d_hist, h->d_partial, h->bin, s),
+                                         h->keep_hist ? h->d_hist : nullptr, h->d_partial, h->bin,
+                                         s),
                "brick accumulate");
         const int nba = rv::brick_axis(grid, edge);
         nlists = nba * nba * nba;
@@ -1759,6 +1764,8 @@ RV_API rv_status rot_vote_get_histogram(rv_handle* h, int32_t* dst_device)
         return RV_EINVAL;
     if (!h->solved)
         return fail(h, RV_EINVAL, "rot_vote_get_histogram: no solve yet");
+    if (!h->keep_hist)
+        return fail(h, RV_EINVAL, "rot_vote_get_histogram: create with RV_FLAG_KEEP_HISTOGRAM");
     if (!dst_device || !is_device_memory(dst_device))
         return fail(h, RV_EINVAL, "rot_vote_get_histogram: dst must be device memory");
     const size_t bytes = (size_t)h->last_grid * h->last_grid * h->last_grid * sizeof(int32_t);

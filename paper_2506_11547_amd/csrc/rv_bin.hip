@@ -779,7 +779,7 @@ __global__ __launch_bounds__(Brick<kLog>::kThreads) void k_brick_accum(BinArgs a
     __shared__ uint64_t lists[kAccumWaves][kWave];
     __shared__ uint32_t s_floor;
     const int nb = nba * nba * nba;
-    const int wave = threadIdx.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
     uint4* acc4 = reinterpret_cast<uint4*>(acc);
     // A workgroup takes one brick per round of gridDim.x (persistent when the
@@ -806,6 +806,21 @@ __global__ __launch_bounds__(Brick<kLog>::kThreads) void k_brick_accum(BinArgs a
         // this instance's grid and overflow grid (by its index in the batch)
         const int64_t gofs = (int64_t)(a.inst_of ? a.inst_of[inst] : inst) * G * G * G;
         const int bx = b % nba, by = (b / nba) % nba, bz = b / (nba * nba);
+
+        // Without a grid to write, a brick that no run reached (nothing queued
+        // in any set, nothing overflowed) holds only zero counts: its list is
+        // empty and it needs no LDS pass.  Cells outside the chart's unit ball
+        // are never voted, so about half of a large grid's bricks are empty.
+        if (grid == nullptr) {
+            uint32_t any = a.flags[qoff + b];
+            for (int z = 0; z < a.nsets; ++z)
+                any |= a.fill[(int64_t)z * a.qstride + qoff + b];
+            if (any == 0u) {
+                if (wave == 0)
+                    partial[(int64_t)(qoff + b) * kWave + lane] = 0ull;
+                continue;
+            }
+        }
 
         for (int k = threadIdx.x; k < kBrickCells / 4; k += kAccumThreads)
             acc4[k] = make_uint4(0u, 0u, 0u, 0u);
@@ -837,13 +852,23 @@ __global__ __launch_bounds__(Brick<kLog>::kThreads) void k_brick_accum(BinArgs a
             // compiler can keep the next batch in flight across the LDS atomics
             const uint32_t last = (cnt - 1u) & ~3u;
             uint4 cur[kUnroll], nxt[kUnroll];
+            // the entry's LDS byte address: the cell index times four, folded
+            // into the decode's weights and shifts
             auto add_entry = [&](uint32_t e) {
-                if constexpr (kSpread)
-                    atomicAdd(&acc[spread_local<kLog>(e)], e & 0xFFu);
-                else
-                    atomicAdd(&acc[e & 0x7FFFu], e >> 15);
+                uint32_t off, len;
+                if constexpr (kSpread) {
+                    constexpr uint32_t kW4 = (4u << 8) | ((uint32_t)(4 * kEdge) << 16);
+                    off = __builtin_amdgcn_udot4(e, kW4, (e >> 24) << (2 * kLog + 2), false);
+                    len = e & 0xFFu;
+                } else {
+                    off = (e << 2) & (0x7FFFu << 2);
+                    len = e >> 15;
+                }
+                atomicAdd(reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(acc) + off), len);
             };
-            uint32_t k0 = (uint32_t)((wave - grp * wpg) * kWave + lane) * 4;
+            // kb: the wave's first entry of the batch (wave-uniform)
+            uint32_t kb = (uint32_t)(wave - grp * wpg) * kWave * 4;
+            uint32_t k0 = kb + (uint32_t)lane * 4;
             // non-temporal: each entry is read once, and streaming the queues
             // through L2 as ordinary lines took 12 % (one solve) to 25 % (the
             // key strategy's many small queues) longer
@@ -856,22 +881,34 @@ __global__ __launch_bounds__(Brick<kLog>::kThreads) void k_brick_accum(BinArgs a
                 }
             };
             load(cur, k0);
-            while (k0 < cnt) {
+            while (kb < cnt) {
                 const uint32_t kn = k0 + kStride * kUnroll;
                 load(nxt, kn);
+                if (cnt - kb >= (kUnroll - 1) * kStride + kWave * 4) {
+                    // every entry of the wave's batch is below cnt
     #pragma unroll
-                for (int u = 0; u < kUnroll; ++u) {
-                    const uint32_t k = k0 + u * kStride;
-                    // entries past cnt add nothing
-                    if (k < cnt) add_entry(cur[u].x);
-                    if (k + 1 < cnt) add_entry(cur[u].y);
-                    if (k + 2 < cnt) add_entry(cur[u].z);
-                    if (k + 3 < cnt) add_entry(cur[u].w);
+                    for (int u = 0; u < kUnroll; ++u) {
+                        add_entry(cur[u].x);
+                        add_entry(cur[u].y);
+                        add_entry(cur[u].z);
+                        add_entry(cur[u].w);
+                    }
+                } else {
+    #pragma unroll
+                    for (int u = 0; u < kUnroll; ++u) {
+                        const uint32_t k = k0 + u * kStride;
+                        // entries past cnt add nothing
+                        if (k < cnt) add_entry(cur[u].x);
+                        if (k + 1 < cnt) add_entry(cur[u].y);
+                        if (k + 2 < cnt) add_entry(cur[u].z);
+                        if (k + 3 < cnt) add_entry(cur[u].w);
+                    }
                 }
     #pragma unroll
                 for (int u = 0; u < kUnroll; ++u)
                     cur[u] = nxt[u];
                 k0 = kn;
+                kb += kStride * kUnroll;
             }
         }
         __syncthreads();

@@ -28,6 +28,7 @@ STRATEGIES = {"auto": 0, "global": 1, "brick": 2, "keys": 3}
 STRATEGY_NAMES = {v: k for k, v in STRATEGIES.items()}
 FLAG_TIMING = 1
 FLAG_BATCH_GRIDS = 2
+FLAG_KEEP_HISTOGRAM = 4
 MAX_TOPK = 64
 NOALLOC_MAX_GRID = 64
 NOALLOC_MAX_SAMPLES = 4096
@@ -291,7 +292,7 @@ class Solver:
                  topk: int = 16, samples_per_circle: int = 0, strategy: str = "auto",
                  timing: bool = False, stream: torch.cuda.Stream | None = None,
                  max_batch: int = 0, batch_grids: bool = False, batch_brick_edge: int = 0,
-                 max_pairs: int = 0):
+                 max_pairs: int = 0, keep_histogram: bool = False):
         if not torch.cuda.is_available():
             raise RuntimeError("rotvote needs a HIP GPU; none is visible")
         self._lib = load_library()
@@ -306,7 +307,8 @@ class Solver:
         cfg.samples_per_circle = samples_per_circle
         cfg.topk = topk
         cfg.vote_strategy = STRATEGIES[strategy]
-        cfg.flags = (FLAG_TIMING if timing else 0) | (FLAG_BATCH_GRIDS if batch_grids else 0)
+        cfg.flags = ((FLAG_TIMING if timing else 0) | (FLAG_BATCH_GRIDS if batch_grids else 0)
+                     | (FLAG_KEEP_HISTOGRAM if keep_histogram else 0))
         cfg.max_batch = max_batch
         cfg.batch_brick_edge = batch_brick_edge
         cfg.max_pairs = max_pairs

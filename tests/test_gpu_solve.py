@@ -38,16 +38,34 @@ def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
 
+def same_results(a, b):
+    """Two solves' results are identical (rotation bits, count, mask, candidates, plan)."""
+    assert np.array_equal(a["q"].view(np.uint32), b["q"].view(np.uint32))
+    assert a["count"] == b["count"]
+    assert np.array_equal(a["mask"], b["mask"])
+    assert a["top"] == b["top"] and a["plan"] == b["plan"]
+
+
 def run_gpu(rv, x, y, G, J, eps_deg, K, strategy="auto"):
-    with rv.Solver(max_n=max(1, x.shape[1]), max_grid=G, topk=K, samples_per_circle=J,
-                   strategy=strategy) as s:
-        q, cnt, mask = s.solve(dev(x), dev(y), G, eps_deg)
-        hist = s.histogram().cpu().numpy()
-        top = s.topk()
-        plan = s.plan()
-        torch.cuda.synchronize()
-        return dict(q=np.array(q, np.float32), count=cnt, mask=mask.cpu().numpy(), hist=hist,
-                    top=top, plan=plan)
+    """The solve as a caller runs it (no vote grid kept: the brick strategies
+    write only their bricks' lists), then on a handle that keeps the grid for
+    the histogram hook; both must give the same results."""
+    res = []
+    for keep in (False, True):
+        with rv.Solver(max_n=max(1, x.shape[1]), max_grid=G, topk=K, samples_per_circle=J,
+                       strategy=strategy, keep_histogram=keep) as s:
+            q, cnt, mask = s.solve(dev(x), dev(y), G, eps_deg)
+            r = dict(q=np.array(q, np.float32), count=cnt, mask=mask.cpu().numpy(),
+                     top=s.topk(), plan=s.plan())
+            if keep:
+                r["hist"] = s.histogram().cpu().numpy()
+            else:
+                with pytest.raises(rv.RotVoteError):
+                    s.histogram()
+            torch.cuda.synchronize()
+            res.append(r)
+    same_results(res[0], res[1])
+    return res[1]
 
 
 def check_parity(g, o, G):
@@ -162,12 +180,19 @@ def test_brick_queue_overflow_is_exact(rv, orc, G, J, strategy):
     x[:, rep] = np.float32([[0.3], [-0.5], [0.8]])
     y[:, rep] = np.float32([[0.9], [0.1], [-0.2]])
     o = orc.solve(x, y, G, J, eps_rad(rv, 1.0), 16, nthreads=oracle.threads())
-    with rv.Solver(max_n=n, max_grid=G, topk=16, samples_per_circle=J, strategy=strategy) as s:
-        for _ in range(2):  # the overflow grid must be left zeroed for the next solve
-            q, cnt, mask = s.solve(dev(x), dev(y), G, 1.0)
-            g = dict(q=np.array(q, np.float32), count=cnt, mask=mask.cpu().numpy(),
-                     hist=s.histogram().cpu().numpy(), top=s.topk(), plan=s.plan())
-            check_parity(g, o, G)
+    for keep in (True, False):
+        with rv.Solver(max_n=n, max_grid=G, topk=16, samples_per_circle=J, strategy=strategy,
+                       keep_histogram=keep) as s:
+            for _ in range(2):  # the overflow grid must be left zeroed for the next solve
+                q, cnt, mask = s.solve(dev(x), dev(y), G, 1.0)
+                g = dict(q=np.array(q, np.float32), count=cnt, mask=mask.cpu().numpy(),
+                         top=s.topk(), plan=s.plan())
+                if keep:
+                    g["hist"] = s.histogram().cpu().numpy()
+                    check_parity(g, o, G)
+                    kept = g
+                else:
+                    same_results(g, kept)
 
 
 @pytest.mark.parametrize("strategy", STRATEGIES)
@@ -200,7 +225,7 @@ def test_all_unusable_and_empty(rv, strategy):
     assert g["count"] == 0 and g["hist"].sum() == 0
     assert g["q"].tolist() == [1.0, 0.0, 0.0, 0.0]
     assert not g["mask"].any() and g["top"]["winner"] == -1
-    with rv.Solver(max_n=10, max_grid=16, topk=4, strategy=strategy) as s:
+    with rv.Solver(max_n=10, max_grid=16, topk=4, strategy=strategy, keep_histogram=True) as s:
         e = torch.empty(3, 0, dtype=torch.float32, device="cuda")
         q, cnt, mask = s.solve(e, e, 16, 1.0)
         assert q == [1.0, 0.0, 0.0, 0.0] and cnt == 0 and mask.numel() == 0
@@ -220,7 +245,7 @@ def test_noise_free_recovers_rotation_exactly_in_cell(rv, orc, strategy):
 
 def test_repeat_and_handle_reuse_are_deterministic(rv):
     w, inst = datagen.make_workload("small")
-    with rv.Solver(max_n=20000, max_grid=128, topk=16) as s:
+    with rv.Solver(max_n=20000, max_grid=128, topk=16, keep_histogram=True) as s:
         x, y = dev(inst.x), dev(inst.y)
         q1, c1, m1 = s.solve(x, y, 64, 1.0)
         h1 = s.histogram().clone()
