@@ -737,9 +737,11 @@ rv_status vote_candidates(rv_handle* h, const float* x, const float* y, int64_t 
     if (brick) {
         // the whole grid only for the histogram hook: the top-K needs the
         // bricks' lists alone
-        RV_HIP(h, rv::launch_brick_accum(grid, h->K, edge, !keys && grid <= rv::kNarrowGrid,
-                                         h->keep_hist ? h->d_hist : nullptr, h->d_partial, h->bin,
-                                         s),
+        const rv::QueueFormat fmt = keys ? rv::QueueFormat::kKeys
+                                    : grid <= rv::kNarrowGrid ? rv::QueueFormat::kNarrow
+                                                              : rv::QueueFormat::kWide;
+        RV_HIP(h, rv::launch_brick_accum(grid, h->K, edge, fmt, h->keep_hist ? h->d_hist : nullptr,
+                                         h->d_partial, h->bin, s),
                "brick accumulate");
         const int nba = rv::brick_axis(grid, edge);
         nlists = nba * nba * nba;
@@ -1260,7 +1262,7 @@ rv_status enqueue_batch(rv_handle* h, const float* x, const float* y, int64_t n_
         RV_HIP(h, hipEventRecord(h->ev[2], s), "event");
     for (int c = 1; c >= 0; --c)
         if (use[c])
-            RV_HIP(h, rv::launch_brick_accum(grid, h->K, edge[c], true,
+            RV_HIP(h, rv::launch_brick_accum(grid, h->K, edge[c], rv::QueueFormat::kNarrow,
                                              h->batch_grids ? h->d_bgrids : nullptr,
                                              h->d_cpartial[c], a[c], s),
                    "batch brick accumulate");

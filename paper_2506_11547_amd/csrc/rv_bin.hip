@@ -20,6 +20,7 @@
 #include <algorithm>
 #include <atomic>
 #include <cmath>
+#include <type_traits>
 
 #include "rv_device.h"
 #include "rv_internal.h"
@@ -603,9 +604,10 @@ __global__ __launch_bounds__(Pack<kWide>::kThreads, Pack<kWide>::kBlocksPerCU) v
 // no flush check) the workgroup sorts its keys by brick (a counting sort in
 // LDS: one reservation per brick and a scan of the counts give each brick's
 // first position, and a key's position is that plus its rank) and stores
-// them position by position into the bricks' queues as single votes
-// (cell | 1 << 15), so one store instruction writes consecutive slots of a
-// few bricks' queues.  The brick accumulation is the run strategy's.
+// them position by position into the bricks' queues as 16-bit brick-local
+// cells (one vote each), so one store instruction writes consecutive slots of
+// a few bricks' queues.  The accumulation reads eight keys per 16-byte load
+// and adds one per key.
 template <int kWaves_, int kWindow_, int kBlocks_>
 struct KeyPack {
     static constexpr int kWaves = kWaves_;
@@ -701,7 +703,7 @@ __device__ __forceinline__ void keys_flush(uint32_t (*stage)[KP::kStageCap],
         const uint32_t b = e >> kKeyLocalBits;
         const uint2 d = s_dst[b];
         if (p < d.y) {
-            a.pool[(uint64_t)(d.x + p)] = (e & kKeyLocalMask) | (1u << 15);
+            reinterpret_cast<uint16_t*>(a.pool)[(uint64_t)(d.x + p)] = (uint16_t)(e & kKeyLocalMask);
         } else {
             const uint32_t l = e & kKeyLocalMask;
             const uint32_t bx = b % (uint32_t)nba, by = (b / (uint32_t)nba) % (uint32_t)nba,
@@ -763,9 +765,21 @@ __global__ __launch_bounds__(KP::kThreads, KP::kBlocksPerCU) void k_vote_keys(
 
 // ----------------------------------------------------------- accumulate
 
-// kSpread: queue entries of narrow runs (spread local cell, length in byte
-// 0); else the brick-local cell with the length above bit 15 (wide runs, keys).
-template <int kLog, bool kSpread>
+// (w & 0xFFFF) << 2 in one instruction: the shift reads the low half-word
+// (the compiler forms the high half-word's variant by itself, not this one).
+__device__ __forceinline__ uint32_t low_half_x4(uint32_t w)
+{
+    uint32_t r;
+    asm("v_lshlrev_b32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:WORD_0"
+        : "=v"(r)
+        : "v"(2u), "v"(w));
+    return r;
+}
+
+// kFmt: queue entries of narrow runs (spread local cell, length in byte 0),
+// of wide runs (brick-local cell, length above bit 15) or keys (16-bit
+// brick-local cells, one vote each).
+template <int kLog, QueueFormat kFmt>
 __global__ __launch_bounds__(Brick<kLog>::kThreads) void k_brick_accum(BinArgs a, int G, int nba, int K,
                                                                    int32_t* __restrict__ grid,
                                                                    uint64_t* __restrict__ partial)
@@ -834,41 +848,65 @@ __global__ __launch_bounds__(Brick<kLog>::kThreads) void k_brick_accum(BinArgs a
         // streaming its sets in turn, so the latency of one set's first reads
         // overlaps the others'.  Software-pipelined queue reads: the next 8 KiB
         // per wave are in flight while the current ones are added into LDS.
-        // Queues start on 64-run boundaries and their capacity is a multiple
-        // of 64, so vector loads of 4 runs starting below the fill count stay
-        // inside the queue.
+        // Queues start on 64-entry boundaries and their capacity is a multiple
+        // of 64, so 16-byte vector loads (4 runs or 8 keys) starting below the
+        // fill count stay inside the queue.
+        constexpr bool kKeys16 = kFmt == QueueFormat::kKeys;
+        using Entry = typename std::conditional<kKeys16, uint16_t, uint32_t>::type;
+        constexpr uint32_t kPerVec = 16 / sizeof(Entry);
         constexpr int kUnroll = 8;
         const int nset_here = set1 - set0;
         const int groups = min(kAccumWaves, nset_here);
         const int wpg = kAccumWaves / max(groups, 1);
         const int grp = wave / wpg;
-        const uint32_t kStride = (uint32_t)wpg * kWave * 4;
+        const uint32_t kStride = (uint32_t)wpg * kWave * kPerVec;
         for (int xs = set0 + grp; grp < groups && xs < set1; xs += groups) {
             const uint32_t cnt = min(a.fill[(int64_t)xs * a.qstride + qoff + b], cap);
-            const uint32_t* q = a.pool + a.qbase[(int64_t)xs * a.qstride + qoff + b];
+            const Entry* q = reinterpret_cast<const Entry*>(a.pool) +
+                             a.qbase[(int64_t)xs * a.qstride + qoff + b];
             if (cnt == 0)
                 continue;
             // loads are unconditional (clamped to the queue's last vector) so the
             // compiler can keep the next batch in flight across the LDS atomics
-            const uint32_t last = (cnt - 1u) & ~3u;
+            const uint32_t last = (cnt - 1u) & ~(kPerVec - 1u);
             uint4 cur[kUnroll], nxt[kUnroll];
-            // the entry's LDS byte address: the cell index times four, folded
-            // into the decode's weights and shifts
-            auto add_entry = [&](uint32_t e) {
-                uint32_t off, len;
-                if constexpr (kSpread) {
-                    constexpr uint32_t kW4 = (4u << 8) | ((uint32_t)(4 * kEdge) << 16);
-                    off = __builtin_amdgcn_udot4(e, kW4, (e >> 24) << (2 * kLog + 2), false);
-                    len = e & 0xFFu;
-                } else {
-                    off = (e << 2) & (0x7FFFu << 2);
-                    len = e >> 15;
+            // Adds the entries of one vector whose first entry is number k
+            // (every entry when `all`).  The LDS byte address is the cell index
+            // times four, folded into the decode's weights and shifts.
+            auto add_vec = [&](const uint4& v, uint32_t k, bool all) {
+                const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+    #pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    if constexpr (kKeys16) {
+                        // two keys per word; bit 15 of each is clear
+                        if (all || k + 2 * i < cnt)
+                            atomicAdd(reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(acc) +
+                                                                  low_half_x4(w[i])),
+                                      1u);
+                        if (all || k + 2 * i + 1 < cnt)
+                            atomicAdd(reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(acc) +
+                                                                  ((w[i] >> 16) << 2)),
+                                      1u);
+                    } else {
+                        uint32_t off, len;
+                        const uint32_t e = w[i];
+                        if constexpr (kFmt == QueueFormat::kNarrow) {
+                            constexpr uint32_t kW4 = (4u << 8) | ((uint32_t)(4 * kEdge) << 16);
+                            off = __builtin_amdgcn_udot4(e, kW4, (e >> 24) << (2 * kLog + 2), false);
+                            len = e & 0xFFu;
+                        } else {
+                            off = (e << 2) & (0x7FFFu << 2);
+                            len = e >> 15;
+                        }
+                        if (all || k + i < cnt)
+                            atomicAdd(reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(acc) + off),
+                                      len);
+                    }
                 }
-                atomicAdd(reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(acc) + off), len);
             };
             // kb: the wave's first entry of the batch (wave-uniform)
-            uint32_t kb = (uint32_t)(wave - grp * wpg) * kWave * 4;
-            uint32_t k0 = kb + (uint32_t)lane * 4;
+            uint32_t kb = (uint32_t)(wave - grp * wpg) * kWave * kPerVec;
+            uint32_t k0 = kb + (uint32_t)lane * kPerVec;
             // non-temporal: each entry is read once, and streaming the queues
             // through L2 as ordinary lines took 12 % (one solve) to 25 % (the
             // key strategy's many small queues) longer
@@ -884,25 +922,16 @@ __global__ __launch_bounds__(Brick<kLog>::kThreads) void k_brick_accum(BinArgs a
             while (kb < cnt) {
                 const uint32_t kn = k0 + kStride * kUnroll;
                 load(nxt, kn);
-                if (cnt - kb >= (kUnroll - 1) * kStride + kWave * 4) {
+                if (cnt - kb >= (kUnroll - 1) * kStride + kWave * kPerVec) {
                     // every entry of the wave's batch is below cnt
     #pragma unroll
-                    for (int u = 0; u < kUnroll; ++u) {
-                        add_entry(cur[u].x);
-                        add_entry(cur[u].y);
-                        add_entry(cur[u].z);
-                        add_entry(cur[u].w);
-                    }
+                    for (int u = 0; u < kUnroll; ++u)
+                        add_vec(cur[u], 0u, true);
                 } else {
+                    // entries past cnt add nothing
     #pragma unroll
-                    for (int u = 0; u < kUnroll; ++u) {
-                        const uint32_t k = k0 + u * kStride;
-                        // entries past cnt add nothing
-                        if (k < cnt) add_entry(cur[u].x);
-                        if (k + 1 < cnt) add_entry(cur[u].y);
-                        if (k + 2 < cnt) add_entry(cur[u].z);
-                        if (k + 3 < cnt) add_entry(cur[u].w);
-                    }
+                    for (int u = 0; u < kUnroll; ++u)
+                        add_vec(cur[u], k0 + u * kStride, false);
                 }
     #pragma unroll
                 for (int u = 0; u < kUnroll; ++u)
@@ -1012,9 +1041,9 @@ int accum_blocks(int edge_log2, int items)
             return items;
         const hipError_t e =
             edge_log2 == 5
-                ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_brick_accum<5, true>,
+                ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_brick_accum<5, QueueFormat::kNarrow>,
                                                                Brick<5>::kThreads, 0)
-                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_brick_accum<4, true>,
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_brick_accum<4, QueueFormat::kNarrow>,
                                                                Brick<4>::kThreads, 0);
         if (e != hipSuccess || cus < 1 || occ < 1)
             return items;
@@ -1167,10 +1196,10 @@ hipError_t launch_bin_vote(const float* x, const float* y, int64_t n, int G, int
     return hipGetLastError();
 }
 
-hipError_t launch_brick_accum(int G, int K, int edge_log2, bool spread, int32_t* grid,
+hipError_t launch_brick_accum(int G, int K, int edge_log2, QueueFormat fmt, int32_t* grid,
                               uint64_t* partial, const BinArgs& a, hipStream_t s)
 {
-    if ((edge_log2 != 4 && edge_log2 != 5) || (edge_log2 == 4 && !spread))
+    if ((edge_log2 != 4 && edge_log2 != 5) || (edge_log2 == 4 && fmt != QueueFormat::kNarrow))
         return hipErrorInvalidValue;
     const int nba = brick_axis(G, edge_log2);
     const int nb = nba * nba * nba;
@@ -1187,14 +1216,17 @@ hipError_t launch_brick_accum(int G, int K, int edge_log2, bool spread, int32_t*
     const int blocks = (a.batch && (edge_log2 == 5 || a.counts)) ? accum_blocks(edge_log2, a.batch * nb)
                                                                  : (a.batch ? a.batch * nb : nb);
     if (edge_log2 == 4)
-        hipLaunchKernelGGL((k_brick_accum<4, true>), dim3(blocks), dim3(Brick<4>::kThreads), 0, s, a,
-                           G, nba, K, grid, partial);
-    else if (spread)
-        hipLaunchKernelGGL((k_brick_accum<5, true>), dim3(blocks), dim3(Brick<5>::kThreads), 0, s, a,
-                           G, nba, K, grid, partial);
+        hipLaunchKernelGGL((k_brick_accum<4, QueueFormat::kNarrow>), dim3(blocks),
+                           dim3(Brick<4>::kThreads), 0, s, a, G, nba, K, grid, partial);
+    else if (fmt == QueueFormat::kNarrow)
+        hipLaunchKernelGGL((k_brick_accum<5, QueueFormat::kNarrow>), dim3(blocks),
+                           dim3(Brick<5>::kThreads), 0, s, a, G, nba, K, grid, partial);
+    else if (fmt == QueueFormat::kWide)
+        hipLaunchKernelGGL((k_brick_accum<5, QueueFormat::kWide>), dim3(blocks),
+                           dim3(Brick<5>::kThreads), 0, s, a, G, nba, K, grid, partial);
     else
-        hipLaunchKernelGGL((k_brick_accum<5, false>), dim3(blocks), dim3(Brick<5>::kThreads), 0, s, a,
-                           G, nba, K, grid, partial);
+        hipLaunchKernelGGL((k_brick_accum<5, QueueFormat::kKeys>), dim3(blocks),
+                           dim3(Brick<5>::kThreads), 0, s, a, G, nba, K, grid, partial);
     return hipGetLastError();
 }
 

@@ -81,7 +81,8 @@ struct Unit {
 // qstride = B * nb.
 struct BinArgs {
     uint32_t* pool;      // run queues; entry = narrow run: brick-local bits of bytes 1-3 and the
-                         // length in byte 0; wide run or key: local cell | length << 15
+                         // length in byte 0; wide run: local cell | length << 15; key: the
+                         // local cell in 16 bits (the pool read as uint16_t, same slot numbers)
     uint32_t* fill;      // [nsets][qstride] runs appended per queue
     uint32_t* qbase;     // [nsets][qstride] first pool slot of each queue
     uint32_t* cap;       // [qstride] capacity of each queue of the brick
@@ -117,9 +118,11 @@ hipError_t launch_key_vote(const float* x, const float* y, int64_t n, int G, int
                            const float2* table, const BinArgs& a, hipStream_t s);
 hipError_t launch_bin_vote(const float* x, const float* y, int64_t n, int G, int J, int edge_log2,
                            const float2* table, const BinArgs& a, hipStream_t s);
-// spread: the queues hold narrow runs (G <= 256, the binned vote's), else
-// wide runs or keys; edge 16 is narrow only.
-hipError_t launch_brick_accum(int G, int K, int edge_log2, bool spread, int32_t* grid,
+// What the brick queues hold: narrow runs (G <= 256, the binned vote's), wide
+// runs (the binned vote's above 256), or keys (the key vote's); edge 16 is
+// narrow only.
+enum class QueueFormat { kNarrow, kWide, kKeys };
+hipError_t launch_brick_accum(int G, int K, int edge_log2, QueueFormat fmt, int32_t* grid,
                               uint64_t* partial, const BinArgs& a, hipStream_t s);
 
 // Batches (G <= kMaxBatchGrid): planned on the device from the instances'
