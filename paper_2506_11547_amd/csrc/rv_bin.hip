@@ -599,12 +599,13 @@ __global__ __launch_bounds__(Pack<kWide>::kThreads, Pack<kWide>::kBlocksPerCU) v
 // its 32^3 brick, written by every lane at a fixed slot (sample, lane) of its
 // wave's staging, with no ballot or compaction; an unusable correspondence
 // writes a dropped marker.  Each key is counted into its brick's LDS counter
-// as it is staged, and the count before it (its rank within the brick) kept
-// beside it.  Every kWindow samples (the same sample index in every wave, so
-// no flush check) the workgroup sorts its keys by brick (a counting sort in
-// LDS: one reservation per brick and a scan of the counts give each brick's
-// first position, and a key's position is that plus its rank) and stores
-// them position by position into the bricks' queues as 16-bit brick-local
+// as it is staged (an atomic whose result is not waited for).  Every kWindow
+// samples (the same sample index in every wave, so no flush check) the
+// workgroup sorts its keys by brick (a counting sort in LDS: one reservation
+// per brick and a scan of the counts give each brick's first position, and
+// each key is written into a sorted copy at the next free position of its
+// brick's range, taken by an LDS atomic) and stores them position by
+// position into the bricks' queues as 16-bit brick-local
 // cells (one vote each), so one store instruction writes consecutive slots of
 // a few bricks' queues.  The accumulation reads eight keys per 16-byte load
 // and adds one per key.
@@ -617,11 +618,10 @@ struct KeyPack {
     static constexpr int kBlocksPerCU = kBlocks_;
     static constexpr int kSplit = kWindow;    // chunks of J for few circles
     static_assert(kWindow % 8 == 0, "the sample loop reads the table eight entries at a time");
-    static_assert(kWaves * kStageCap <= 65536, "16-bit sort index");
     static_assert(kMaxBricksAll % kThreads == 0, "every brick has a thread in the flush's scan");
 };
 // 16 waves in one workgroup per CU, flushing every 16 samples (1024 keys per
-// wave; 152 KiB of LDS with the ranks): measured at G = 360, J = 180 against 8
+// wave; 152 KiB of LDS with the sorted copy): measured at G = 360, J = 180 against 8
 // waves in two workgroups per CU with 16-sample (5 % slower) and 8-sample
 // windows (29 % slower), and 8 waves in one workgroup with 24-sample windows
 // (49 % slower): larger flushes write longer stretches of each brick's queue.
@@ -638,16 +638,15 @@ __device__ __forceinline__ uint32_t key_of(const Cell& c, uint32_t nba)
 }
 
 template <class KP>
-__device__ __forceinline__ void keys_flush(uint32_t (*stage)[KP::kStageCap],
-                                           uint16_t (*rank)[KP::kStageCap], uint32_t my,
+__device__ __forceinline__ void keys_flush(uint32_t (*stage)[KP::kStageCap], uint32_t my,
                                            uint32_t* s_cnt, uint2* s_dst, uint32_t* s_scan,
-                                           uint16_t* s_idx, uint32_t& s_total, int wave, int lane,
+                                           uint32_t* s_sorted, uint32_t& s_total, int wave, int lane,
                                            int nb, int nba, int G, int xs, const BinArgs& a)
 {
     constexpr int kT = KP::kThreads;
     constexpr int kPer = kMaxBricksAll / kT;
     const int t = threadIdx.x;
-    // the keys were counted per brick (and ranked) as they were staged
+    // the keys were counted per brick as they were staged
     __syncthreads();
     uint32_t c[kPer], g[kPer];
     uint32_t sum = 0;
@@ -689,17 +688,16 @@ __device__ __forceinline__ void keys_flush(uint32_t (*stage)[KP::kStageCap],
         }
     }
     __syncthreads();
-    // 3a: each key's stage index at its brick's first position plus its rank
+    // 3a: each key to the next free position of its brick's range
     for (uint32_t k = lane; k < my; k += kWave) {
         const uint32_t e = stage[wave][k];
         if (e != kDropped)
-            s_idx[s_cnt[e >> kKeyLocalBits] + rank[wave][k]] = (uint16_t)(wave * KP::kStageCap + k);
+            s_sorted[atomicAdd(&s_cnt[e >> kKeyLocalBits], 1u)] = e;
     }
     __syncthreads();
     const uint32_t total = s_total;
-    const uint32_t* flat = &stage[0][0];
     for (uint32_t p = t; p < total; p += kT) {
-        const uint32_t e = flat[s_idx[p]];
+        const uint32_t e = s_sorted[p];
         const uint32_t b = e >> kKeyLocalBits;
         const uint2 d = s_dst[b];
         if (p < d.y) {
@@ -726,11 +724,10 @@ __global__ __launch_bounds__(KP::kThreads, KP::kBlocksPerCU) void k_vote_keys(
     int J, int chunk, int ngroups, const float2* __restrict__ table, int nba, BinArgs a)
 {
     __shared__ uint32_t stage[KP::kWaves][KP::kStageCap];
-    __shared__ uint16_t rank[KP::kWaves][KP::kStageCap];
     __shared__ uint32_t s_cnt[kMaxBricksAll];
     __shared__ uint2 s_dst[kMaxBricksAll];
     __shared__ uint32_t s_scan[KP::kWaves];
-    __shared__ uint16_t s_idx[KP::kWaves * KP::kStageCap];
+    __shared__ uint32_t s_sorted[KP::kWaves * KP::kStageCap];
     __shared__ uint32_t s_total;
     const int nb = nba * nba * nba;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -747,7 +744,6 @@ __global__ __launch_bounds__(KP::kThreads, KP::kBlocksPerCU) void k_vote_keys(
     Quat u, v;
     const bool ok = load_circle(x, y, n, i, u, v);
     uint32_t* my_stage = stage[wave];
-    uint16_t* my_rank = rank[wave];
     const uint32_t unba = (uint32_t)nba;
     for (int js = j0; js < j1; js += KP::kWindow) {
         const int je = min(j1, js + KP::kWindow);
@@ -756,9 +752,9 @@ __global__ __launch_bounds__(KP::kThreads, KP::kBlocksPerCU) void k_vote_keys(
             const int slot = (j - js) * kWave + lane;
             my_stage[slot] = ok ? key : kDropped;
             if (ok)
-                my_rank[slot] = (uint16_t)atomicAdd(&s_cnt[key >> kKeyLocalBits], 1u);
+                atomicAdd(&s_cnt[key >> kKeyLocalBits], 1u);
         });
-        keys_flush<KP>(stage, rank, (uint32_t)(je - js) * kWave, s_cnt, s_dst, s_scan, s_idx,
+        keys_flush<KP>(stage, (uint32_t)(je - js) * kWave, s_cnt, s_dst, s_scan, s_sorted,
                        s_total, wave, lane, nb, nba, G, xs, a);
     }
 }
