@@ -640,20 +640,25 @@ __device__ __forceinline__ uint32_t key_of(const Cell& c, uint32_t nba)
 template <class KP>
 __device__ __forceinline__ void keys_flush(uint32_t (*stage)[KP::kStageCap], uint32_t my,
                                            uint32_t* s_cnt, uint2* s_dst, uint32_t* s_scan,
-                                           uint32_t* s_sorted, uint32_t& s_total, int wave, int lane,
-                                           int nb, int nba, int G, int xs, const BinArgs& a)
+                                           uint32_t* s_sorted, uint32_t& s_total,
+                                           uint32_t (&ends)[kMaxBricksAll / KP::kThreads], int wave,
+                                           int lane, int nb, int nba, int G, int xs,
+                                           const BinArgs& a)
 {
     constexpr int kT = KP::kThreads;
     constexpr int kPer = kMaxBricksAll / kT;
     const int t = threadIdx.x;
-    // the keys were counted per brick as they were staged
+    // The keys were counted per brick as they were staged, on top of where
+    // the previous flush's placement left each counter (its brick's end
+    // position, kept in `ends` by the thread that owns the brick), so the
+    // counters need no clearing between windows.
     __syncthreads();
     uint32_t c[kPer], g[kPer];
     uint32_t sum = 0;
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
         const int b = t * kPer + u;
-        c[u] = b < nb ? s_cnt[b] : 0u;
+        c[u] = b < nb ? s_cnt[b] - ends[u] : 0u;
         sum += c[u];
         g[u] = c[u] ? atomicAdd(a.fill + (int64_t)xs * a.qstride + b, c[u]) : 0u;
     }
@@ -685,6 +690,7 @@ __device__ __forceinline__ void keys_flush(uint32_t (*stage)[KP::kStageCap], uin
             }
             s_cnt[b] = pre;  // the brick's first sorted position
             pre += c[u];
+            ends[u] = pre;   // where placing the brick's keys leaves the counter
         }
     }
     __syncthreads();
@@ -694,6 +700,10 @@ __device__ __forceinline__ void keys_flush(uint32_t (*stage)[KP::kStageCap], uin
         if (e != kDropped)
             s_sorted[atomicAdd(&s_cnt[e >> kKeyLocalBits], 1u)] = e;
     }
+    // From here on only the sorted copy and the destinations are read, so
+    // the waves go on to stage the next window (counters and staging are
+    // free) without another barrier; the next flush's first barrier keeps
+    // its writes of s_dst, s_total and the sorted copy after these reads.
     __syncthreads();
     const uint32_t total = s_total;
     for (uint32_t p = t; p < total; p += kT) {
@@ -712,9 +722,6 @@ __device__ __forceinline__ void keys_flush(uint32_t (*stage)[KP::kStageCap], uin
             a.flags[b] = 1u;
         }
     }
-    for (int b = t; b < nb; b += kT)
-        s_cnt[b] = 0u;
-    __syncthreads();
 }
 
 // One block per (kThreads correspondences, chunk of samples).
@@ -745,6 +752,7 @@ __global__ __launch_bounds__(KP::kThreads, KP::kBlocksPerCU) void k_vote_keys(
     const bool ok = load_circle(x, y, n, i, u, v);
     uint32_t* my_stage = stage[wave];
     const uint32_t unba = (uint32_t)nba;
+    uint32_t ends[kMaxBricksAll / KP::kThreads] = {};
     for (int js = j0; js < j1; js += KP::kWindow) {
         const int je = min(j1, js + KP::kWindow);
         for_samples<true>(u, v, table, js, je, H, gm, [&](const Cell& c, int j) {
@@ -755,7 +763,7 @@ __global__ __launch_bounds__(KP::kThreads, KP::kBlocksPerCU) void k_vote_keys(
                 atomicAdd(&s_cnt[key >> kKeyLocalBits], 1u);
         });
         keys_flush<KP>(stage, (uint32_t)(je - js) * kWave, s_cnt, s_dst, s_scan, s_sorted,
-                       s_total, wave, lane, nb, nba, G, xs, a);
+                       s_total, ends, wave, lane, nb, nba, G, xs, a);
     }
 }
 
