@@ -475,8 +475,9 @@ __global__ __launch_bounds__(Pack<kWide>::kThreads, Pack<kWide>::kBlocksPerCU) v
     // this check's barrier and none writes again before the next barrier, so
     // every wave reads the same maximum and takes the same decision.
     __shared__ uint32_t s_maxfill[3];
-    __shared__ uint32_t s_dummy[P::kWaves][kWave];
-    // the wide layout's sort index and run total (bin_flush_sorted)
+    // the wide layout's per-wave scan totals, sort index and run total
+    // (bin_flush_sorted)
+    __shared__ uint32_t s_scan[P::kWaves];
     __shared__ uint16_t s_idx[kWide ? P::kWaves * P::kStageCap : 1];
     __shared__ uint32_t s_total;
     const int nb = nba * nba * nba;
@@ -526,23 +527,32 @@ __global__ __launch_bounds__(Pack<kWide>::kThreads, Pack<kWide>::kBlocksPerCU) v
     uint32_t* my_stage = stage[wave];
     int slot = 0;
 
-    // Branch-free emission: the ballot of the bare compare stays a scalar
-    // mask (usable lanes are masked in the scalar domain); lanes that do not
-    // emit store to a private dummy slot instead of taking a branch.
+    // Emission without a branch: the ballot of the bare compare stays a
+    // scalar mask (usable lanes are masked in the scalar domain), and the
+    // staging store runs under that mask as the exec mask, narrowed and
+    // restored around the one store in a single assembly block so that no
+    // other instruction can be scheduled under it (the compiler, left to
+    // branch, splits the emission into divergent blocks; a select between
+    // the slot and a private dummy slot costs one instruction per sample).
     const uint64_t okmask = __builtin_amdgcn_ballot_w64(ok);
-    uint32_t* my_dummy = &s_dummy[wave][lane];
+    typedef __attribute__((address_space(3))) uint32_t lds_u32;
     auto emit = [&](bool change) {
         const uint64_t m = __builtin_amdgcn_ballot_w64(change) & okmask;
         const uint32_t r = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
                                                      __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-        const bool mine = change && ok;
-        *(mine ? (my_stage + fill + r) : my_dummy) = kWide ? cur | (cnt << P::kLenShift) : run;
+        const uint32_t addr = (uint32_t)(uintptr_t)(lds_u32*)(my_stage + fill + r);
+        const uint32_t val = kWide ? cur | (cnt << P::kLenShift) : run;
+        uint64_t save;
+        asm volatile("s_and_saveexec_b64 %0, %1\n\tds_write_b32 %2, %3\n\ts_or_b64 exec, exec, %0"
+                     : "=&s"(save)
+                     : "s"(m), "v"(addr), "v"(val)
+                     : "memory", "scc");
         fill += (uint32_t)__popcll(m);
     };
 
     auto flush = [&](uint32_t my) {
         if constexpr (kWide)
-            bin_flush_sorted<kLog>(stage, my, s_cnt, s_dst, &s_dummy[0][0], s_idx, s_total, wave,
+            bin_flush_sorted<kLog>(stage, my, s_cnt, s_dst, s_scan, s_idx, s_total, wave,
                                    lane, nb, nba, G, xs, qoff, ovf_off, a);
         else
             bin_flush<kLog>(stage, my, s_cnt, s_dst, wave, lane, nb, nba, G, xs, qoff,
