@@ -805,7 +805,7 @@ __global__ __launch_bounds__(Brick<kLog>::kThreads) void k_brick_accum(BinArgs a
     constexpr int kAccumWaves = Br::kWaves;
     __shared__ uint32_t acc[kBrickCells];
     __shared__ uint64_t lists[kAccumWaves][kWave];
-    __shared__ uint32_t s_floor;
+    __shared__ uint32_t s_floor, s_floor_top;
     const int nb = nba * nba * nba;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
@@ -852,8 +852,10 @@ __global__ __launch_bounds__(Brick<kLog>::kThreads) void k_brick_accum(BinArgs a
 
         for (int k = threadIdx.x; k < kBrickCells / 4; k += kAccumThreads)
             acc4[k] = make_uint4(0u, 0u, 0u, 0u);
-        if (threadIdx.x == 0)
+        if (threadIdx.x == 0) {
             s_floor = 0u;
+            s_floor_top = 0xFFFFFFFFu;
+        }
         __syncthreads();
 
         const uint32_t cap = a.cap[qoff + b];
@@ -995,15 +997,23 @@ __global__ __launch_bounds__(Brick<kLog>::kThreads) void k_brick_accum(BinArgs a
             // cells past the grid's edge hold 0 and cannot raise the maximum
             lmax = max(lmax, max(max(val[0], val[1]), max(val[2], val[3])));
         }
-        // A floor for the top K: the K largest lane maxima of one wave are counts
-        // of K distinct cells, so the brick's K-th largest count is at least the
-        // K-th largest lane maximum of every wave.  Cells below the floor cannot
-        // be among the brick's K best and skip the list.
-        const uint32_t kth = (uint32_t)lane_u64(wave_sort_desc((uint64_t)lmax, lane), K - 1);
-        if (lane == 0)
+        // A floor for the top K.  Lane maxima are counts of distinct cells, so
+        // the brick's K-th largest count is at least (1) the K-th largest lane
+        // maximum of any one wave, and (2) the smallest, over the waves, of
+        // each wave's ceil(K / waves)-th largest lane maximum (every wave has
+        // that many at or above it, K in all).  In a dense brick (2) is far
+        // higher: it leaves pass 2 a few cells instead of most of them.
+        // Cells below the floor cannot be among the brick's K best and skip
+        // the list.
+        const uint64_t srt = wave_sort_desc((uint64_t)lmax, lane);
+        const uint32_t kth = (uint32_t)lane_u64(srt, K - 1);
+        const uint32_t top = (uint32_t)lane_u64(srt, (K + kAccumWaves - 1) / kAccumWaves - 1);
+        if (lane == 0) {
             atomicMax(&s_floor, kth);
+            atomicMin(&s_floor_top, top);
+        }
         __syncthreads();
-        const uint32_t floor_k = max(s_floor, 1u);
+        const uint32_t floor_k = max(max(s_floor, s_floor_top), 1u);
 
         // Pass 2: the sorted list of the brick's best cells at or above the floor.
         uint64_t list = 0;
