@@ -701,6 +701,8 @@ class Solver:
                     winner=win.value)
 
     def histogram(self) -> torch.Tensor:
+        """The last solve's vote grid (int32 [G^3], x fastest); the handle must
+        have been made with keep_histogram=True (RotVoteError otherwise)."""
         g = self._last_grid
         if g is None:
             raise RuntimeError("no solve yet")
