@@ -297,14 +297,17 @@ __device__ __forceinline__ void bin_flush(uint32_t (*stage)[Pack<false>::kStageC
                                           const BinArgs& a)
 {
     const uint32_t weights = brick_weights(nba);
+    // (the loops step a wave-uniform base, so their counters are scalar)
     // 1: runs per brick (zero-length entries are marked dropped)
-    for (uint32_t k = lane; k < my; k += kWave) {
-        const uint32_t e = stage[wave][k];
-        if ((e & 0xFFu) == 0u) {
-            stage[wave][k] = kDropped;
-            continue;
+    for (uint32_t base = 0; base < my; base += kWave) {
+        const uint32_t k = base + (uint32_t)lane;
+        if (k < my) {
+            const uint32_t e = stage[wave][k];
+            if ((e & 0xFFu) == 0u)
+                stage[wave][k] = kDropped;
+            else
+                atomicAdd(&s_cnt[run_brick<kLog>(e, weights)], 1u);
         }
-        atomicAdd(&s_cnt[run_brick<kLog>(e, weights)], 1u);
     }
     __syncthreads();
     // 2: one reservation per brick in its queue; the first pool slot of this
@@ -323,15 +326,18 @@ __device__ __forceinline__ void bin_flush(uint32_t (*stage)[Pack<false>::kStageC
     //    count each brick's total back down to zero, so the counters are clear
     //    for the next flush once every wave is through here; the step barrier
     //    that precedes any flush guarantees that.
-    for (uint32_t k = lane; k < my; k += kWave) {
-        const uint32_t e = stage[wave][k];
+    for (uint32_t base = 0; base < my; base += kWave) {
+        const uint32_t k = base + (uint32_t)lane;
+        const uint32_t e = k < my ? stage[wave][k] : kDropped;
         if (e == kDropped)
             continue;
         const uint32_t b = run_brick<kLog>(e, weights);
         const uint32_t rank = atomicSub(&s_cnt[b], 1u) - 1u;
-        const uint2 d = s_dst[b];
-        if (rank < d.y) {
-            a.pool[(uint64_t)(d.x + rank)] = e & kSpreadMask<kLog>;
+        // the destination and the room in one 64-bit LDS read
+        const uint64_t d = *reinterpret_cast<const uint64_t*>(&s_dst[b]);
+        const uint32_t slot = (uint32_t)d + rank;
+        if (rank < (uint32_t)(d >> 32)) {
+            a.pool[(uint64_t)slot] = e & kSpreadMask<kLog>;
         } else {
             const int64_t cell = ((int64_t)(e >> 24) * G + ((e >> 16) & 0xFFu)) * G + ((e >> 8) & 0xFFu);
             atomicAdd(a.ovf + ovf_off + cell, (int32_t)(e & 0xFFu));
