@@ -540,12 +540,17 @@ __global__ __launch_bounds__(Pack<kWide>::kThreads, Pack<kWide>::kBlocksPerCU) v
     // other instruction can be scheduled under it (the compiler, left to
     // branch, splits the emission into divergent blocks; a select between
     // the slot and a private dummy slot costs one instruction per sample).
+    // The compiler does not count the block's store among the wave's LDS
+    // operations; the waits for all of them that it puts before every barrier
+    // are what order the store before the flush's reads (a CPU test checks
+    // the compiled code for both that and the SCC clobber).
     const uint64_t okmask = __builtin_amdgcn_ballot_w64(ok);
     typedef __attribute__((address_space(3))) uint32_t lds_u32;
     auto emit = [&](bool change) {
         const uint64_t m = __builtin_amdgcn_ballot_w64(change) & okmask;
         const uint32_t r = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
                                                      __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+        // the slot's LDS byte offset (the pointer converted to the LDS address space)
         const uint32_t addr = (uint32_t)(uintptr_t)(lds_u32*)(my_stage + fill + r);
         const uint32_t val = kWide ? cur | (cnt << P::kLenShift) : run;
         uint64_t save;

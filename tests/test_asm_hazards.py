@@ -8,7 +8,9 @@ not keep a comparison's SCC live across it.  Without the declaration it did:
 a loop-exit compare before the block and its conditional branch after it, so
 the wide vote left its loop early (13 % of the votes at G = 360).  This test
 compiles the kernels to assembly and checks every instruction that reads SCC
-after an inline block has an SCC write between the two.
+after an inline block has an SCC write between the two, and that every
+barrier after such a block's LDS store is preceded by a wait for all LDS
+operations (the compiler does not count the store itself).
 """
 import re
 import shutil
@@ -55,6 +57,30 @@ def scc_reads_after_asm(asm_text: str) -> list[str]:
     return bad
 
 
+def barriers_after_asm_stores(asm_text: str) -> int:
+    """Barriers reached while a staging store written in an inline-assembly
+    block may still be in flight: the compiler does not count that store, so
+    only its own lgkmcnt(0) wait before a barrier (which waits for every LDS
+    operation of the wave) makes the store visible to the other waves."""
+    bad = 0
+    inside = pending = False
+    for line in asm_text.split("\n"):
+        s = line.strip()
+        if "ASMSTART" in s:
+            inside = True
+            continue
+        if "ASMEND" in s:
+            inside = False
+            continue
+        if inside and s.startswith("ds_write"):
+            pending = True
+        elif s.startswith("s_waitcnt") and "lgkmcnt(0)" in s:
+            pending = False
+        elif s.startswith("s_barrier") and pending:
+            bad += 1
+    return bad
+
+
 def test_scanner_finds_a_planted_hazard():
     text = "\n".join([
         "s_cmp_ge_i32 s22, s91",
@@ -68,6 +94,8 @@ def test_scanner_finds_a_planted_hazard():
     assert scc_reads_after_asm(text) == ["s_cbranch_scc1 .LBB8_141"]
     fixed = text.replace(";;#ASMEND", ";;#ASMEND\ns_cmp_ge_i32 s22, s91")
     assert scc_reads_after_asm(fixed) == []
+    assert barriers_after_asm_stores(text + "\ns_barrier") == 1
+    assert barriers_after_asm_stores(text + "\ns_waitcnt lgkmcnt(0)\ns_barrier") == 0
 
 
 @pytest.mark.skipif(not shutil.which(HIPCC) and not __import__("os").path.exists(HIPCC),
@@ -81,3 +109,4 @@ def test_no_scc_read_after_inline_asm(tmp_path):
     text = out.read_text()
     assert "s_and_saveexec_b64" in text and "ASMSTART" in text
     assert scc_reads_after_asm(text) == []
+    assert barriers_after_asm_stores(text) == 0
