@@ -63,6 +63,13 @@ __device__ __forceinline__ void load3(const float* __restrict__ v, int64_t n, in
     o[2] = v[2 * n + i];
 }
 
+// A row's pairs are taken kRowUnroll vectors of 64 at a time: all their loads
+// are issued before the first test, so the long rows (row i has n - 1 - i
+// pairs, and the longest sets the kernel's duration) wait once per group
+// instead of once per vector.  Loads past the last point read the last point
+// and their pairs are not kept.
+constexpr int kRowUnroll = 4;
+
 // The wave's row (wave-uniform, held in scalar registers).
 __device__ __forceinline__ int64_t wave_row()
 {
@@ -82,16 +89,20 @@ __global__ __launch_bounds__(kThreads) void k_pairs_count(const float* __restric
     load3(x, n, i, xi);
     load3(y, n, i, yi);
     uint64_t cnt = 0;
-    for (int64_t j0 = i + 1; j0 < n; j0 += 64) {
-        const int64_t j = j0 + lane;
-        bool keep = false;
-        if (j < n) {
-            float xj[3], yj[3], m[3], d[3];
-            load3(x, n, j, xj);
-            load3(y, n, j, yj);
-            keep = pair_kept(xi, yi, xj, yj, mu, m, d);
+    for (int64_t j0 = i + 1; j0 < n; j0 += 64 * kRowUnroll) {
+        float xj[kRowUnroll][3], yj[kRowUnroll][3];
+#pragma unroll
+        for (int u = 0; u < kRowUnroll; ++u) {
+            const int64_t j = j0 + u * 64 + lane;
+            load3(x, n, j < n ? j : n - 1, xj[u]);
+            load3(y, n, j < n ? j : n - 1, yj[u]);
         }
-        cnt += (uint64_t)__popcll(__ballot(keep));
+#pragma unroll
+        for (int u = 0; u < kRowUnroll; ++u) {
+            float m[3], d[3];
+            const bool keep = (j0 + u * 64 + lane < n) && pair_kept(xi, yi, xj[u], yj[u], mu, m, d);
+            cnt += (uint64_t)__popcll(__ballot(keep));
+        }
     }
     if (lane == 0)
         rows[i] = cnt;
@@ -142,30 +153,34 @@ __global__ __launch_bounds__(kThreads) void k_pairs_emit(
     load3(x, n, i, xi);
     load3(y, n, i, yi);
     uint64_t k0 = rows[i];
-    for (int64_t j0 = i + 1; j0 < n; j0 += 64) {
-        const int64_t j = j0 + lane;
-        bool keep = false;
-        float m[3] = {0.0f, 0.0f, 0.0f}, d[3] = {0.0f, 0.0f, 0.0f};
-        if (j < n) {
-            float xj[3], yj[3];
-            load3(x, n, j, xj);
-            load3(y, n, j, yj);
-            keep = pair_kept(xi, yi, xj, yj, mu, m, d);
-        }
-        const uint64_t bal = __ballot(keep);
-        if (keep) {
-            const int64_t k = (int64_t)(k0 + (uint64_t)__popcll(bal & below));
+    for (int64_t j0 = i + 1; j0 < n; j0 += 64 * kRowUnroll) {
+        float xj[kRowUnroll][3], yj[kRowUnroll][3];
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                mo[c * P + k] = m[c];
-                no[c * P + k] = d[c];
-            }
-            if (idx) {
-                idx[k] = (int32_t)i;
-                idx[P + k] = (int32_t)j;
-            }
+        for (int u = 0; u < kRowUnroll; ++u) {
+            const int64_t j = j0 + u * 64 + lane;
+            load3(x, n, j < n ? j : n - 1, xj[u]);
+            load3(y, n, j < n ? j : n - 1, yj[u]);
         }
-        k0 += (uint64_t)__popcll(bal);
+#pragma unroll
+        for (int u = 0; u < kRowUnroll; ++u) {
+            const int64_t j = j0 + u * 64 + lane;
+            float m[3], d[3];
+            const bool keep = (j < n) && pair_kept(xi, yi, xj[u], yj[u], mu, m, d);
+            const uint64_t bal = __ballot(keep);
+            if (keep) {
+                const int64_t k = (int64_t)(k0 + (uint64_t)__popcll(bal & below));
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    mo[c * P + k] = m[c];
+                    no[c * P + k] = d[c];
+                }
+                if (idx) {
+                    idx[k] = (int32_t)i;
+                    idx[P + k] = (int32_t)j;
+                }
+            }
+            k0 += (uint64_t)__popcll(bal);
+        }
     }
 }
 
