@@ -378,10 +378,11 @@ __device__ __forceinline__ void bin_flush_sorted(uint32_t (*stage)[Pack<true>::k
     __syncthreads();
     // 2: each thread's bricks t*kPer.. (consecutive, so a scan of the
     //    per-thread sums orders the bricks); a reservation per brick, and the
-    //    first sorted position of its runs in s_cnt.  The reservation atomics
-    //    are issued first: their round trip overlaps the scan (issuing the
-    //    capacity and queue-base loads with them measured slower).
-    uint32_t c[kPer], g[kPer];
+    //    first sorted position of its runs in s_cnt.  The reservations (and
+    //    the queues' capacities and bases) are requested here but first
+    //    needed after the placement (3a), so their round trip overlaps the
+    //    scan and the placement.
+    uint32_t c[kPer], g[kPer], cap[kPer], qb[kPer];
     uint32_t sum = 0;
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
@@ -390,6 +391,8 @@ __device__ __forceinline__ void bin_flush_sorted(uint32_t (*stage)[Pack<true>::k
         sum += c[u];
         const int64_t q = (int64_t)xs * a.qstride + qoff + b;
         g[u] = c[u] ? atomicAdd(a.fill + q, c[u]) : 0u;
+        cap[u] = c[u] ? a.cap[qoff + b] : 0u;
+        qb[u] = c[u] ? a.qbase[q] : 0u;
     }
     // inclusive scan of the sums within the wave, then over the wave totals
     uint32_t incl = sum;
@@ -408,18 +411,12 @@ __device__ __forceinline__ void bin_flush_sorted(uint32_t (*stage)[Pack<true>::k
     uint32_t pre = wpre + incl - sum;
     if (t == kT - 1)
         s_total = wpre + incl;
+    uint32_t first[kPer];
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
         const int b = t * kPer + u;
+        first[u] = pre;
         if (b < nb) {
-            if (c[u]) {
-                const int64_t q = (int64_t)xs * a.qstride + qoff + b;
-                const uint32_t cap = a.cap[qoff + b];
-                const uint32_t room = cap > g[u] ? cap - g[u] : 0u;
-                // slot of sorted position p: qbase + g + (p - pre) (mod 2^32);
-                // positions from pre + room on overflow
-                s_dst[b] = make_uint2(a.qbase[q] + g[u] - pre, pre + min(room, c[u]));
-            }
             s_cnt[b] = pre;
             pre += c[u];
         }
@@ -432,6 +429,22 @@ __device__ __forceinline__ void bin_flush_sorted(uint32_t (*stage)[Pack<true>::k
             continue;
         const uint32_t pos = atomicAdd(&s_cnt[brick_of<kLog, true>(e & P::kCellMask, nba)], 1u);
         s_idx[pos] = (uint16_t)(wave * P::kStageCap + k);
+    }
+    // the bricks' destinations, now that their reservations are back (the
+    // empty assembly statements keep the compiler from computing them, and
+    // so waiting for the reservations, before the placement): the slot of
+    // sorted position p is qbase + g + (p - first) (mod 2^32), positions
+    // from first + room on overflow
+#pragma unroll
+    for (int u = 0; u < kPer; ++u)
+        asm volatile("" : "+v"(g[u]), "+v"(cap[u]), "+v"(qb[u]));
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        const int b = t * kPer + u;
+        if (b < nb && c[u]) {
+            const uint32_t room = cap[u] > g[u] ? cap[u] - g[u] : 0u;
+            s_dst[b] = make_uint2(qb[u] + g[u] - first[u], first[u] + min(room, c[u]));
+        }
     }
     __syncthreads();
     // 3b: the runs in brick order; then the counters are cleared for the next
@@ -674,7 +687,10 @@ __device__ __forceinline__ void keys_flush(uint32_t (*stage)[KP::kStageCap], uin
     // position, kept in `ends` by the thread that owns the brick), so the
     // counters need no clearing between windows.
     __syncthreads();
-    uint32_t c[kPer], g[kPer];
+    // The reservations (and the queues' capacities and bases) are requested
+    // here but first needed after the placement (3a), so their round trip
+    // overlaps the scan and the placement instead of stalling the workgroup.
+    uint32_t c[kPer], g[kPer], cap[kPer], qb[kPer];
     uint32_t sum = 0;
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
@@ -682,6 +698,8 @@ __device__ __forceinline__ void keys_flush(uint32_t (*stage)[KP::kStageCap], uin
         c[u] = b < nb ? s_cnt[b] - ends[u] : 0u;
         sum += c[u];
         g[u] = c[u] ? atomicAdd(a.fill + (int64_t)xs * a.qstride + b, c[u]) : 0u;
+        cap[u] = c[u] ? a.cap[b] : 0u;
+        qb[u] = c[u] ? a.qbase[(int64_t)xs * a.qstride + b] : 0u;
     }
     uint32_t incl = sum;
 #pragma unroll
@@ -699,16 +717,12 @@ __device__ __forceinline__ void keys_flush(uint32_t (*stage)[KP::kStageCap], uin
     uint32_t pre = wpre + incl - sum;
     if (t == kT - 1)
         s_total = wpre + incl;
+    uint32_t first[kPer];
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
         const int b = t * kPer + u;
+        first[u] = pre;
         if (b < nb) {
-            if (c[u]) {
-                const int64_t q = (int64_t)xs * a.qstride + b;
-                const uint32_t cap = a.cap[b];
-                const uint32_t room = cap > g[u] ? cap - g[u] : 0u;
-                s_dst[b] = make_uint2(a.qbase[q] + g[u] - pre, pre + min(room, c[u]));
-            }
             s_cnt[b] = pre;  // the brick's first sorted position
             pre += c[u];
             ends[u] = pre;   // where placing the brick's keys leaves the counter
@@ -720,6 +734,20 @@ __device__ __forceinline__ void keys_flush(uint32_t (*stage)[KP::kStageCap], uin
         const uint32_t e = stage[wave][k];
         if (e != kDropped)
             s_sorted[atomicAdd(&s_cnt[e >> kKeyLocalBits], 1u)] = e;
+    }
+    // the bricks' destinations, now that their reservations are back (the
+    // empty assembly statements keep the compiler from computing them, and
+    // so waiting for the reservations, before the placement)
+#pragma unroll
+    for (int u = 0; u < kPer; ++u)
+        asm volatile("" : "+v"(g[u]), "+v"(cap[u]), "+v"(qb[u]));
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        const int b = t * kPer + u;
+        if (b < nb && c[u]) {
+            const uint32_t room = cap[u] > g[u] ? cap[u] - g[u] : 0u;
+            s_dst[b] = make_uint2(qb[u] + g[u] - first[u], first[u] + min(room, c[u]));
+        }
     }
     // From here on only the sorted copy and the destinations are read, so
     // the waves go on to stage the next window (counters and staging are
