@@ -422,13 +422,23 @@ __device__ __forceinline__ void bin_flush_sorted(uint32_t (*stage)[Pack<true>::k
         }
     }
     __syncthreads();
-    // 3a: each run's stage index at its sorted position
-    for (uint32_t k = lane; k < my; k += kWave) {
-        const uint32_t e = stage[wave][k];
-        if (e == kDropped)
-            continue;
-        const uint32_t pos = atomicAdd(&s_cnt[brick_of<kLog, true>(e & P::kCellMask, nba)], 1u);
-        s_idx[pos] = (uint16_t)(wave * P::kStageCap + k);
+    // 3a: each run's stage index at its sorted position (four runs per lane
+    //     at a time, so their LDS round trips overlap)
+    for (uint32_t k0 = lane; k0 < my; k0 += 4 * kWave) {
+        uint32_t ev[4];
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+            const uint32_t k = k0 + h * kWave;
+            ev[h] = k < my ? stage[wave][k] : kDropped;
+        }
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+            if (ev[h] == kDropped)
+                continue;
+            const uint32_t pos =
+                atomicAdd(&s_cnt[brick_of<kLog, true>(ev[h] & P::kCellMask, nba)], 1u);
+            s_idx[pos] = (uint16_t)(wave * P::kStageCap + k0 + h * kWave);
+        }
     }
     // the bricks' destinations, now that their reservations are back (the
     // empty assembly statements keep the compiler from computing them, and
@@ -453,19 +463,37 @@ __device__ __forceinline__ void bin_flush_sorted(uint32_t (*stage)[Pack<true>::k
     //    before all are stored: the closing barrier.
     const uint32_t total = s_total;
     const uint32_t* flat = &stage[0][0];
-    for (uint32_t p = t; p < total; p += kT) {
-        const uint32_t e = flat[s_idx[p]];
-        const uint32_t pc = e & P::kCellMask;
-        const uint32_t len = e >> P::kLenShift;
-        const uint32_t b = brick_of<kLog, true>(pc, nba);
-        const uint2 d = s_dst[b];
-        if (p < d.y) {
-            a.pool[(uint64_t)(d.x + p)] = local_of<kLog, true>(pc) | (len << 15);
-        } else {
-            const int64_t cell = ((int64_t)((pc >> (2 * P::kBits)) & P::kAxis) * G +
-                                  ((pc >> P::kBits) & P::kAxis)) * G + (pc & P::kAxis);
-            atomicAdd(a.ovf + ovf_off + cell, (int32_t)len);
-            a.flags[qoff + b] = 1u;
+    // four positions per thread at a time: their chains of LDS reads overlap
+    for (uint32_t p0 = t; p0 < total; p0 += 4 * kT) {
+        uint32_t ev[4], bv[4];
+        uint2 dv[4];
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+            const uint32_t p = p0 + h * kT;
+            ev[h] = p < total ? flat[s_idx[p]] : 0u;
+        }
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+            bv[h] = brick_of<kLog, true>(ev[h] & P::kCellMask, nba);
+            dv[h] = s_dst[bv[h]];
+        }
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+            const uint32_t p = p0 + h * kT;
+            if (p >= total)
+                continue;
+            const uint32_t pc = ev[h] & P::kCellMask;
+            const uint32_t len = ev[h] >> P::kLenShift;
+            const uint32_t b = bv[h];
+            const uint2 d = dv[h];
+            if (p < d.y) {
+                a.pool[(uint64_t)(d.x + p)] = local_of<kLog, true>(pc) | (len << 15);
+            } else {
+                const int64_t cell = ((int64_t)((pc >> (2 * P::kBits)) & P::kAxis) * G +
+                                      ((pc >> P::kBits) & P::kAxis)) * G + (pc & P::kAxis);
+                atomicAdd(a.ovf + ovf_off + cell, (int32_t)len);
+                a.flags[qoff + b] = 1u;
+            }
         }
     }
     for (int b = t; b < nb; b += kT)
@@ -729,11 +757,19 @@ __device__ __forceinline__ void keys_flush(uint32_t (*stage)[KP::kStageCap], uin
         }
     }
     __syncthreads();
-    // 3a: each key to the next free position of its brick's range
-    for (uint32_t k = lane; k < my; k += kWave) {
-        const uint32_t e = stage[wave][k];
-        if (e != kDropped)
-            s_sorted[atomicAdd(&s_cnt[e >> kKeyLocalBits], 1u)] = e;
+    // 3a: each key to the next free position of its brick's range (four
+    //     keys per lane at a time, so their LDS round trips overlap)
+    for (uint32_t k0 = lane; k0 < my; k0 += 4 * kWave) {
+        uint32_t ev[4];
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+            const uint32_t k = k0 + h * kWave;
+            ev[h] = k < my ? stage[wave][k] : kDropped;
+        }
+#pragma unroll
+        for (int h = 0; h < 4; ++h)
+            if (ev[h] != kDropped)
+                s_sorted[atomicAdd(&s_cnt[ev[h] >> kKeyLocalBits], 1u)] = ev[h];
     }
     // the bricks' destinations, now that their reservations are back (the
     // empty assembly statements keep the compiler from computing them, and
@@ -755,10 +791,27 @@ __device__ __forceinline__ void keys_flush(uint32_t (*stage)[KP::kStageCap], uin
     // its writes of s_dst, s_total and the sorted copy after these reads.
     __syncthreads();
     const uint32_t total = s_total;
-    for (uint32_t p = t; p < total; p += kT) {
-        const uint32_t e = s_sorted[p];
+    // four positions per thread at a time: their LDS reads overlap
+    constexpr int kU = 4;
+    for (uint32_t p0 = t; p0 < total; p0 += kU * kT) {
+        uint32_t ev[kU];
+        uint2 dv[kU];
+#pragma unroll
+        for (int h = 0; h < kU; ++h) {
+            const uint32_t p = p0 + h * kT;
+            ev[h] = p < total ? s_sorted[p] : 0u;
+        }
+#pragma unroll
+        for (int h = 0; h < kU; ++h)
+            dv[h] = s_dst[ev[h] >> kKeyLocalBits];
+#pragma unroll
+        for (int h = 0; h < kU; ++h) {
+        const uint32_t p = p0 + h * kT;
+        if (p >= total)
+            continue;
+        const uint32_t e = ev[h];
         const uint32_t b = e >> kKeyLocalBits;
-        const uint2 d = s_dst[b];
+        const uint2 d = dv[h];
         if (p < d.y) {
             reinterpret_cast<uint16_t*>(a.pool)[(uint64_t)(d.x + p)] = (uint16_t)(e & kKeyLocalMask);
         } else {
@@ -769,6 +822,7 @@ __device__ __forceinline__ void keys_flush(uint32_t (*stage)[KP::kStageCap], uin
                                  (bx * 32 + (l & 31u));
             atomicAdd(a.ovf + cell, 1);
             a.flags[b] = 1u;
+        }
         }
     }
 }
