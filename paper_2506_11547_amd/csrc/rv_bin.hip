@@ -326,9 +326,16 @@ __device__ __forceinline__ void bin_flush(uint32_t (*stage)[Pack<false>::kStageC
     //    count each brick's total back down to zero, so the counters are clear
     //    for the next flush once every wave is through here; the step barrier
     //    that precedes any flush guarantees that.
-    for (uint32_t base = 0; base < my; base += kWave) {
-        const uint32_t k = base + (uint32_t)lane;
-        const uint32_t e = k < my ? stage[wave][k] : kDropped;
+    for (uint32_t base = 0; base < my; base += 2 * kWave) {
+        uint32_t ev[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const uint32_t k = base + h * kWave + (uint32_t)lane;
+            ev[h] = k < my ? stage[wave][k] : kDropped;
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+        const uint32_t e = ev[h];
         if (e == kDropped)
             continue;
         const uint32_t b = run_brick<kLog>(e, weights);
@@ -342,6 +349,7 @@ __device__ __forceinline__ void bin_flush(uint32_t (*stage)[Pack<false>::kStageC
             const int64_t cell = ((int64_t)(e >> 24) * G + ((e >> 16) & 0xFFu)) * G + ((e >> 8) & 0xFFu);
             atomicAdd(a.ovf + ovf_off + cell, (int32_t)(e & 0xFFu));
             a.flags[qoff + b] = 1u;
+        }
         }
     }
 }
