@@ -674,8 +674,9 @@ __global__ __launch_bounds__(Pack<kWide>::kThreads, Pack<kWide>::kBlocksPerCU) v
 // workgroup sorts its keys by brick (a counting sort in LDS: one reservation
 // per brick and a scan of the counts give each brick's first position, and
 // each key is written into a sorted copy at the next free position of its
-// brick's range, taken by an LDS atomic) and stores them position by
-// position into the bricks' queues as 16-bit brick-local
+// brick's range, taken by an LDS atomic; the sorted keys take the place of
+// the staged ones, which every wave holds in registers by then) and stores
+// them position by position into the bricks' queues as 16-bit brick-local
 // cells (one vote each), so one store instruction writes consecutive slots of
 // a few bricks' queues.  The accumulation reads eight keys per 16-byte load
 // and adds one per key.
@@ -690,12 +691,14 @@ struct KeyPack {
     static_assert(kWindow % 8 == 0, "the sample loop reads the table eight entries at a time");
     static_assert(kMaxBricksAll % kThreads == 0, "every brick has a thread in the flush's scan");
 };
-// 16 waves in one workgroup per CU, flushing every 16 samples (1024 keys per
-// wave; 152 KiB of LDS with the sorted copy): measured at G = 360, J = 180 against 8
-// waves in two workgroups per CU with 16-sample (5 % slower) and 8-sample
-// windows (29 % slower), and 8 waves in one workgroup with 24-sample windows
-// (49 % slower): larger flushes write longer stretches of each brick's queue.
-using Keys = KeyPack<16, 16, 1>;
+// 16 waves in one workgroup per CU, flushing every 32 samples (2048 keys per
+// wave; 152 KiB of LDS): larger flushes write longer stretches of each
+// brick's queue and pay the barriers, the scan and the reservations less
+// often.  Measured at G = 360, J = 180 (with a separate sorted copy, so 16
+// samples at most) against 8 waves in two workgroups per CU with 16-sample
+// (5 % slower) and 8-sample windows (29 % slower), and 8 waves in one
+// workgroup with 24-sample windows (49 % slower).
+using Keys = KeyPack<16, 32, 1>;
 
 constexpr uint32_t kKeyLocalBits = 15;  // cell within a 32^3 brick
 constexpr uint32_t kKeyLocalMask = (1u << kKeyLocalBits) - 1u;
@@ -708,9 +711,9 @@ __device__ __forceinline__ uint32_t key_of(const Cell& c, uint32_t nba)
 }
 
 template <class KP>
-__device__ __forceinline__ void keys_flush(uint32_t (*stage)[KP::kStageCap], uint32_t my,
+__device__ __forceinline__ void keys_flush(uint32_t (*stage)[KP::kStageCap], int nsamp,
                                            uint32_t* s_cnt, uint2* s_dst, uint32_t* s_scan,
-                                           uint32_t* s_sorted, uint32_t& s_total,
+                                           uint32_t& s_total,
                                            uint32_t (&ends)[kMaxBricksAll / KP::kThreads], int wave,
                                            int lane, int nb, int nba, int G, int xs,
                                            const BinArgs& a)
@@ -718,6 +721,14 @@ __device__ __forceinline__ void keys_flush(uint32_t (*stage)[KP::kStageCap], uin
     constexpr int kT = KP::kThreads;
     constexpr int kPer = kMaxBricksAll / kT;
     const int t = threadIdx.x;
+    uint32_t* const sorted = &stage[0][0];  // the sort's result, over every wave's staging
+    // this wave's staged keys, into registers: the placement below writes
+    // the sorted keys over the staging of all waves (every wave has read its
+    // own before the second barrier)
+    uint32_t ev[KP::kWindow];
+#pragma unroll
+    for (int h = 0; h < KP::kWindow; ++h)
+        ev[h] = h < nsamp ? stage[wave][h * kWave + lane] : kDropped;
     // The keys were counted per brick as they were staged, on top of where
     // the previous flush's placement left each counter (its brick's end
     // position, kept in `ends` by the thread that owns the brick), so the
@@ -765,20 +776,12 @@ __device__ __forceinline__ void keys_flush(uint32_t (*stage)[KP::kStageCap], uin
         }
     }
     __syncthreads();
-    // 3a: each key to the next free position of its brick's range (four
-    //     keys per lane at a time, so their LDS round trips overlap)
-    for (uint32_t k0 = lane; k0 < my; k0 += 4 * kWave) {
-        uint32_t ev[4];
+    // 3a: each key to the next free position of its brick's range (all of a
+    //     lane's keys at once, so their LDS round trips overlap)
 #pragma unroll
-        for (int h = 0; h < 4; ++h) {
-            const uint32_t k = k0 + h * kWave;
-            ev[h] = k < my ? stage[wave][k] : kDropped;
-        }
-#pragma unroll
-        for (int h = 0; h < 4; ++h)
-            if (ev[h] != kDropped)
-                s_sorted[atomicAdd(&s_cnt[ev[h] >> kKeyLocalBits], 1u)] = ev[h];
-    }
+    for (int h = 0; h < KP::kWindow; ++h)
+        if (ev[h] != kDropped)
+            sorted[atomicAdd(&s_cnt[ev[h] >> kKeyLocalBits], 1u)] = ev[h];
     // the bricks' destinations, now that their reservations are back (the
     // empty assembly statements keep the compiler from computing them, and
     // so waiting for the reservations, before the placement)
@@ -793,44 +796,46 @@ __device__ __forceinline__ void keys_flush(uint32_t (*stage)[KP::kStageCap], uin
             s_dst[b] = make_uint2(qb[u] + g[u] - first[u], first[u] + min(room, c[u]));
         }
     }
-    // From here on only the sorted copy and the destinations are read, so
-    // the waves go on to stage the next window (counters and staging are
-    // free) without another barrier; the next flush's first barrier keeps
-    // its writes of s_dst, s_total and the sorted copy after these reads.
     __syncthreads();
+    // 3b: each wave stores the sorted positions that lie in its own staging
+    // area, so it goes on to stage the next window there without another
+    // barrier; the next flush's first barrier keeps its writes of s_dst,
+    // s_total and the sorted keys after these reads.
     const uint32_t total = s_total;
-    // four positions per thread at a time: their LDS reads overlap
+    const uint32_t lo = (uint32_t)wave * KP::kStageCap;
+    const uint32_t hi = min(total, lo + (uint32_t)KP::kStageCap);
+    // four positions per lane at a time: their LDS reads overlap
     constexpr int kU = 4;
-    for (uint32_t p0 = t; p0 < total; p0 += kU * kT) {
-        uint32_t ev[kU];
+    for (uint32_t p0 = lo + lane; p0 < hi; p0 += kU * kWave) {
+        uint32_t sv[kU];
         uint2 dv[kU];
 #pragma unroll
         for (int h = 0; h < kU; ++h) {
-            const uint32_t p = p0 + h * kT;
-            ev[h] = p < total ? s_sorted[p] : 0u;
+            const uint32_t p = p0 + h * kWave;
+            sv[h] = p < hi ? sorted[p] : 0u;
         }
 #pragma unroll
         for (int h = 0; h < kU; ++h)
-            dv[h] = s_dst[ev[h] >> kKeyLocalBits];
+            dv[h] = s_dst[sv[h] >> kKeyLocalBits];
 #pragma unroll
         for (int h = 0; h < kU; ++h) {
-        const uint32_t p = p0 + h * kT;
-        if (p >= total)
-            continue;
-        const uint32_t e = ev[h];
-        const uint32_t b = e >> kKeyLocalBits;
-        const uint2 d = dv[h];
-        if (p < d.y) {
-            reinterpret_cast<uint16_t*>(a.pool)[(uint64_t)(d.x + p)] = (uint16_t)(e & kKeyLocalMask);
-        } else {
-            const uint32_t l = e & kKeyLocalMask;
-            const uint32_t bx = b % (uint32_t)nba, by = (b / (uint32_t)nba) % (uint32_t)nba,
-                           bz = b / (uint32_t)(nba * nba);
-            const int64_t cell = ((int64_t)(bz * 32 + (l >> 10)) * G + (by * 32 + ((l >> 5) & 31u))) * G +
-                                 (bx * 32 + (l & 31u));
-            atomicAdd(a.ovf + cell, 1);
-            a.flags[b] = 1u;
-        }
+            const uint32_t p = p0 + h * kWave;
+            if (p >= hi)
+                continue;
+            const uint32_t e = sv[h];
+            const uint32_t b = e >> kKeyLocalBits;
+            const uint2 d = dv[h];
+            if (p < d.y) {
+                reinterpret_cast<uint16_t*>(a.pool)[(uint64_t)(d.x + p)] = (uint16_t)(e & kKeyLocalMask);
+            } else {
+                const uint32_t l = e & kKeyLocalMask;
+                const uint32_t bx = b % (uint32_t)nba, by = (b / (uint32_t)nba) % (uint32_t)nba,
+                               bz = b / (uint32_t)(nba * nba);
+                const int64_t cell = ((int64_t)(bz * 32 + (l >> 10)) * G + (by * 32 + ((l >> 5) & 31u))) * G +
+                                     (bx * 32 + (l & 31u));
+                atomicAdd(a.ovf + cell, 1);
+                a.flags[b] = 1u;
+            }
         }
     }
 }
@@ -845,7 +850,6 @@ __global__ __launch_bounds__(KP::kThreads, KP::kBlocksPerCU) void k_vote_keys(
     __shared__ uint32_t s_cnt[kMaxBricksAll];
     __shared__ uint2 s_dst[kMaxBricksAll];
     __shared__ uint32_t s_scan[KP::kWaves];
-    __shared__ uint32_t s_sorted[KP::kWaves * KP::kStageCap];
     __shared__ uint32_t s_total;
     const int nb = nba * nba * nba;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -873,8 +877,8 @@ __global__ __launch_bounds__(KP::kThreads, KP::kBlocksPerCU) void k_vote_keys(
             if (ok)
                 atomicAdd(&s_cnt[key >> kKeyLocalBits], 1u);
         });
-        keys_flush<KP>(stage, (uint32_t)(je - js) * kWave, s_cnt, s_dst, s_scan, s_sorted,
-                       s_total, ends, wave, lane, nb, nba, G, xs, a);
+        keys_flush<KP>(stage, je - js, s_cnt, s_dst, s_scan, s_total, ends, wave, lane, nb, nba,
+                       G, xs, a);
     }
 }
 
