@@ -154,7 +154,7 @@ TRAFFIC_RECORDS = {w: [ROOT / "profiles" / f"vote_{k}__{w}_traffic.json" for k i
                    for w in ("large", "batch", "paper_default", "rigid")}
 
 
-KEY_VOTE_KERNEL = "rv::k_vote_keys<rv::KeyPack<16, 16, 1> >"
+KEY_VOTE_KERNEL = "rv::k_vote_keys<rv::KeyPack<16, 32, 1> >"
 
 
 def vote_kernel_name(grid: int, edge: int = 0, strategy: str = "brick") -> str:

@@ -39,7 +39,7 @@ def test_vote_kernel_name(grid, edge, name):
     # the key strategy has one kernel instance (the source's configuration)
     assert bench.vote_kernel_name(grid, edge, "keys") == bench.KEY_VOTE_KERNEL
     src = (ROOT / "paper_2506_11547_amd" / "csrc" / "rv_bin.hip").read_text()
-    assert "using Keys = KeyPack<16, 16, 1>;" in src
+    assert "using Keys = KeyPack<16, 32, 1>;" in src
 
 
 def make_record(tmp_path, workload, kernel, digests):
