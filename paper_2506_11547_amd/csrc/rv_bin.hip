@@ -702,12 +702,15 @@ using Keys = KeyPack<16, 32, 1>;
 
 constexpr uint32_t kKeyLocalBits = 15;  // cell within a 32^3 brick
 constexpr uint32_t kKeyLocalMask = (1u << kKeyLocalBits) - 1u;
+// The brick index sits above bit 16, so a key's low half-word is its cell
+// (bit 15 clear) and is stored as it is.
+constexpr uint32_t kKeyBrickShift = 16;
 
 __device__ __forceinline__ uint32_t key_of(const Cell& c, uint32_t nba)
 {
     const uint32_t brick = __umul24(__umul24(c.z >> 5, nba) + (c.y >> 5), nba) + (c.x >> 5);
     const uint32_t local = ((c.z & 31u) << 10) | ((c.y & 31u) << 5) | (c.x & 31u);
-    return (brick << kKeyLocalBits) | local;
+    return (brick << kKeyBrickShift) | local;
 }
 
 template <class KP>
@@ -776,12 +779,38 @@ __device__ __forceinline__ void keys_flush(uint32_t (*stage)[KP::kStageCap], int
         }
     }
     __syncthreads();
-    // 3a: each key to the next free position of its brick's range (all of a
-    //     lane's keys at once, so their LDS round trips overlap)
+    // 3a: each key to the next free position of its brick's range.  A
+    //     lane's keys are all usable or all dropped (its correspondence's),
+    //     and a group's positions are all taken before the first is used, so
+    //     the compiler issues the group's atomics back to back and their LDS
+    //     round trips overlap (a test per key would wait for each one).
+    if (ev[0] != kDropped) {
+        constexpr int kGroup = KP::kWindow % 16 == 0 ? 16 : 8;  // windows are multiples of 8
+        if (nsamp == KP::kWindow) {
 #pragma unroll
-    for (int h = 0; h < KP::kWindow; ++h)
-        if (ev[h] != kDropped)
-            sorted[atomicAdd(&s_cnt[ev[h] >> kKeyLocalBits], 1u)] = ev[h];
+            for (int h0 = 0; h0 < KP::kWindow; h0 += kGroup) {
+                uint32_t pos[kGroup];
+#pragma unroll
+                for (int h = 0; h < kGroup; ++h)
+                    pos[h] = atomicAdd(&s_cnt[ev[h0 + h] >> kKeyBrickShift], 1u);
+#pragma unroll
+                for (int h = 0; h < kGroup; ++h)
+                    sorted[pos[h]] = ev[h0 + h];
+            }
+        } else {  // the last window of a chunk (the tests on nsamp are uniform)
+#pragma unroll
+            for (int h0 = 0; h0 < KP::kWindow; h0 += kGroup) {
+                uint32_t pos[kGroup];
+#pragma unroll
+                for (int h = 0; h < kGroup; ++h)
+                    pos[h] = h0 + h < nsamp ? atomicAdd(&s_cnt[ev[h0 + h] >> kKeyBrickShift], 1u) : 0u;
+#pragma unroll
+                for (int h = 0; h < kGroup; ++h)
+                    if (h0 + h < nsamp)
+                        sorted[pos[h]] = ev[h0 + h];
+            }
+        }
+    }
     // the bricks' destinations, now that their reservations are back (the
     // empty assembly statements keep the compiler from computing them, and
     // so waiting for the reservations, before the placement)
@@ -816,17 +845,30 @@ __device__ __forceinline__ void keys_flush(uint32_t (*stage)[KP::kStageCap], int
         }
 #pragma unroll
         for (int h = 0; h < kU; ++h)
-            dv[h] = s_dst[sv[h] >> kKeyLocalBits];
+            dv[h] = s_dst[sv[h] >> kKeyBrickShift];
+        // a whole group of positions with room in every queue (the usual
+        // case) is stored without a test per position
+        const bool whole = p0 - lane + kU * kWave <= hi;
+        bool spill = false;
+#pragma unroll
+        for (int h = 0; h < kU; ++h)
+            spill |= p0 + h * kWave >= dv[h].y;
+        if (whole && !__any(spill)) {
+#pragma unroll
+            for (int h = 0; h < kU; ++h)
+                reinterpret_cast<uint16_t*>(a.pool)[(uint64_t)(dv[h].x + p0 + h * kWave)] = (uint16_t)sv[h];
+            continue;
+        }
 #pragma unroll
         for (int h = 0; h < kU; ++h) {
             const uint32_t p = p0 + h * kWave;
             if (p >= hi)
                 continue;
             const uint32_t e = sv[h];
-            const uint32_t b = e >> kKeyLocalBits;
+            const uint32_t b = e >> kKeyBrickShift;
             const uint2 d = dv[h];
             if (p < d.y) {
-                reinterpret_cast<uint16_t*>(a.pool)[(uint64_t)(d.x + p)] = (uint16_t)(e & kKeyLocalMask);
+                reinterpret_cast<uint16_t*>(a.pool)[(uint64_t)(d.x + p)] = (uint16_t)e;
             } else {
                 const uint32_t l = e & kKeyLocalMask;
                 const uint32_t bx = b % (uint32_t)nba, by = (b / (uint32_t)nba) % (uint32_t)nba,
@@ -875,7 +917,7 @@ __global__ __launch_bounds__(KP::kThreads, KP::kBlocksPerCU) void k_vote_keys(
             const int slot = (j - js) * kWave + lane;
             my_stage[slot] = ok ? key : kDropped;
             if (ok)
-                atomicAdd(&s_cnt[key >> kKeyLocalBits], 1u);
+                atomicAdd(&s_cnt[key >> kKeyBrickShift], 1u);
         });
         keys_flush<KP>(stage, je - js, s_cnt, s_dst, s_scan, s_total, ends, wave, lane, nb, nba,
                        G, xs, a);
