@@ -705,11 +705,22 @@ constexpr uint32_t kKeyLocalMask = (1u << kKeyLocalBits) - 1u;
 // (bit 15 clear) and is stored as it is.
 constexpr uint32_t kKeyBrickShift = 16;
 
-__device__ __forceinline__ uint32_t key_of(const Cell& c, uint32_t nba)
+// Brick-axis weights of key_of for nba bricks per axis (under 2^24 for the
+// 12 bricks per axis of G = 384).
+__host__ __device__ constexpr uint32_t key_weight_y(uint32_t nba) { return nba * 65536u - 1024u; }
+__host__ __device__ constexpr uint32_t key_weight_z(uint32_t nba) { return nba * nba * 65536u - 32768u; }
+static_assert(key_weight_z(12) < (1u << 24), "24-bit multiplies");
+
+// brick << 16 | cell within the brick, ((bz nba + by) nba + bx) << 16 |
+// lz << 10 | ly << 5 | lx, as one sum over the axes: a coordinate v = 32 b + l
+// at its cell weight w (1, 32, 1024) gives l w + 32 b w, and b times (brick
+// weight - 32 w) completes the brick part (brick weights 65536, nba 65536,
+// nba^2 65536); three 24-bit multiplies, no masks.
+__device__ __forceinline__ uint32_t key_of(const Cell& c, uint32_t wy, uint32_t wz)
 {
-    const uint32_t brick = __umul24(__umul24(c.z >> 5, nba) + (c.y >> 5), nba) + (c.x >> 5);
-    const uint32_t local = ((c.z & 31u) << 10) | ((c.y & 31u) << 5) | (c.x & 31u);
-    return (brick << kKeyBrickShift) | local;
+    static_assert(kKeyBrickShift == 16 && kKeyLocalBits == 15, "the weights assume this layout");
+    return c.x + __umul24(c.x >> 5, 65536u - 32u) + (c.y << 5) + __umul24(c.y >> 5, wy) +
+           (c.z << 10) + __umul24(c.z >> 5, wz);
 }
 
 template <class KP>
@@ -907,12 +918,12 @@ __global__ __launch_bounds__(KP::kThreads, KP::kBlocksPerCU) void k_vote_keys(
     Quat u, v;
     const bool ok = load_circle(x, y, n, i, u, v);
     uint32_t* my_stage = stage[wave];
-    const uint32_t unba = (uint32_t)nba;
+    const uint32_t wy = key_weight_y((uint32_t)nba), wz = key_weight_z((uint32_t)nba);
     uint32_t ends[kMaxBricksAll / KP::kThreads] = {};
     for (int js = j0; js < j1; js += KP::kWindow) {
         const int je = min(j1, js + KP::kWindow);
         for_samples<true>(u, v, table, js, je, H, gm, [&](const Cell& c, int j) {
-            const uint32_t key = key_of(c, unba);
+            const uint32_t key = key_of(c, wy, wz);
             const int slot = (j - js) * kWave + lane;
             my_stage[slot] = ok ? key : kDropped;
             if (ok)
